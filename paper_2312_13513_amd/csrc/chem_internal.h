@@ -1,0 +1,60 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// chemistry library.  Nothing here is part of the public ABI (include/chem.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chem {
+
+constexpr double kRu = 8.31446261815324;   // J/(mol K)
+constexpr double kPstd = 101325.0;         // standard-state pressure, Pa
+constexpr int kQmax = 5;                   // highest BDF order
+
+// NASA-7 range block: 7 coefficients plus the divided ones used by H/RT and S/R.
+//   c[0..6] = a1..a7, c[7..10] = a2/2, a3/3, a4/4, a5/5, c[11..13] = a3/2, a4/3, a5/4
+constexpr int kRangeLen = 14;
+// Per species: T_mid, low block, high block.
+constexpr int kSpeciesLen = 1 + 2 * kRangeLen;
+
+// One reaction as seen by the kernels: up to two molecule slots per side; an
+// empty slot holds the sentinel species index K (concentration 1, G/RT 0), a
+// coefficient of 2 is two slots with the same species.
+struct DevRxn {
+    int32_t r0, r1, p0, p1;
+    int32_t dnu;       // product molecules minus reactant molecules
+    int32_t pad[3];
+    double lnA;        // ln of the SI pre-exponential factor
+    double b;          // temperature exponent
+    double Ea_R;       // activation temperature Ea / Ru, K
+    double pad2;
+};
+static_assert(sizeof(DevRxn) == 64, "reaction record is 64 bytes");
+
+struct DevMechView {
+    int32_t K, R;
+    int32_t two_range;          // 0 when every species uses one NASA range
+    int32_t pad;
+    const double *species;      // K x kSpeciesLen
+    const double *W;            // K, kg/mol
+    const double *invW;         // K
+    const DevRxn *rxn;          // R
+};
+
+struct BdfParams {
+    double rtol, atol;
+    int32_t max_steps;
+    int32_t pad;
+};
+
+// Launchers (one thread per cell).  Return hipError_t of the launch.
+hipError_t launch_rhs(const DevMechView &m, const double *T, const double *p, const double *Y,
+                      int64_t ldY, int64_t n, double *F, int64_t ldF, hipStream_t s);
+hipError_t launch_jacobian(const DevMechView &m, const double *T, const double *p, const double *Y,
+                           int64_t ldY, int64_t n, double *J, int64_t ldJ, hipStream_t s);
+hipError_t launch_bdf_thread(const DevMechView &m, double *T, const double *p, double *Y,
+                             int64_t ldY, int64_t n, double dt, const BdfParams &prm,
+                             int32_t *status, int32_t *counters, int block, hipStream_t s);
+bool thread_kernel_supports(int K);
+
+}  // namespace chem

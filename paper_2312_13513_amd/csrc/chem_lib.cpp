@@ -1,0 +1,393 @@
+// Host runtime of the chemistry library: .mech reader and validation, device
+// tables, argument checking and the C ABI of include/chem.h.
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/chem.h"
+#include "chem_internal.h"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+struct HostRxn {
+    std::vector<std::pair<int, int>> reac, prod;   // (species, coefficient)
+    double A = 0, b = 0, Ea = 0;
+};
+
+struct HostMech {
+    int K = 0, R = 0, E = 0;
+    std::vector<double> aw;                 // atomic weights, g/mol
+    std::vector<std::vector<int>> counts;   // K x E
+    std::vector<std::vector<double>> nasa;  // K x 17
+    std::vector<HostRxn> rxn;
+};
+
+// Whitespace-token reader with error reporting.
+class Tokens {
+  public:
+    explicit Tokens(std::istream &in) : in_(in) {}
+    bool word(std::string &w) { return static_cast<bool>(in_ >> w); }
+    bool expect(const char *w)
+    {
+        std::string s;
+        return word(s) && s == w;
+    }
+    template <typename T>
+    bool num(T &v)
+    {
+        std::string s;
+        if (!word(s)) return false;
+        std::istringstream is(s);
+        is >> v;
+        return !is.fail() && is.eof();
+    }
+
+  private:
+    std::istream &in_;
+};
+
+int parse_mech(const char *path, HostMech &m)
+{
+    std::ifstream f(path);
+    if (!f) return fail(CHEM_EMECH, std::string("cannot open mechanism file ") + path);
+    Tokens t(f);
+    int ver = 0, seed = 0, attempt = 0;
+    std::string gen, u;
+    if (!t.expect("CHEMMECH") || !t.num(ver) || ver != 1)
+        return fail(CHEM_EMECH, "not a CHEMMECH 1 file");
+    if (!t.expect("generator") || !t.word(gen) || !t.expect("seed") || !t.num(seed) ||
+        !t.expect("attempt") || !t.num(attempt) || !t.expect("units"))
+        return fail(CHEM_EMECH, "bad header");
+    for (int i = 0; i < 6; i++)
+        if (!t.word(u)) return fail(CHEM_EMECH, "bad units line");
+    if (!t.expect("elements") || !t.num(m.E) || m.E < 1 || m.E > 16)
+        return fail(CHEM_EMECH, "bad element count");
+    m.aw.resize(m.E);
+    for (int e = 0; e < m.E; e++) {
+        std::string name;
+        if (!t.word(name) || !t.num(m.aw[e]) || !(m.aw[e] > 0))
+            return fail(CHEM_EMECH, "bad element record");
+    }
+    if (!t.expect("species") || !t.num(m.K) || m.K < 1 || m.K > 4096)
+        return fail(CHEM_EMECH, "bad species count");
+    m.counts.assign(m.K, std::vector<int>(m.E));
+    m.nasa.assign(m.K, std::vector<double>(17));
+    for (int k = 0; k < m.K; k++) {
+        std::string name;
+        if (!t.word(name)) return fail(CHEM_EMECH, "truncated species list");
+        int atoms = 0;
+        for (int e = 0; e < m.E; e++) {
+            if (!t.num(m.counts[k][e]) || m.counts[k][e] < 0)
+                return fail(CHEM_EMECH, "bad element counts of species " + name);
+            atoms += m.counts[k][e];
+        }
+        if (atoms == 0) return fail(CHEM_EMECH, "species " + name + " has no atoms");
+        for (int j = 0; j < 17; j++)
+            if (!t.num(m.nasa[k][j]) || !std::isfinite(m.nasa[k][j]))
+                return fail(CHEM_EMECH, "bad NASA coefficients of species " + name);
+        if (!(m.nasa[k][0] < m.nasa[k][1] && m.nasa[k][1] < m.nasa[k][2]))
+            return fail(CHEM_EMECH, "bad NASA temperature ranges of species " + name);
+    }
+    if (!t.expect("reactions") || !t.num(m.R) || m.R < 0 || m.R > 1000000)
+        return fail(CHEM_EMECH, "bad reaction count");
+    m.rxn.resize(m.R);
+    for (int i = 0; i < m.R; i++) {
+        HostRxn &r = m.rxn[i];
+        std::string name;
+        int n = 0;
+        if (!t.word(name) || !t.num(n) || n < 1 || n > 2)
+            return fail(CHEM_EMECH, "bad reactant list of reaction " + std::to_string(i));
+        for (int s = 0; s < n; s++) {
+            int k = -1, nu = 0;
+            if (!t.num(k) || !t.num(nu) || k < 0 || k >= m.K || nu < 1)
+                return fail(CHEM_EMECH, "bad reactant of reaction " + std::to_string(i));
+            r.reac.push_back({k, nu});
+        }
+        if (!t.num(n) || n < 1 || n > 2)
+            return fail(CHEM_EMECH, "bad product list of reaction " + std::to_string(i));
+        for (int s = 0; s < n; s++) {
+            int k = -1, nu = 0;
+            if (!t.num(k) || !t.num(nu) || k < 0 || k >= m.K || nu < 1)
+                return fail(CHEM_EMECH, "bad product of reaction " + std::to_string(i));
+            r.prod.push_back({k, nu});
+        }
+        if (!t.num(r.A) || !t.num(r.b) || !t.num(r.Ea) || !(r.A > 0) || !std::isfinite(r.b) ||
+            !std::isfinite(r.Ea))
+            return fail(CHEM_EMECH, "bad Arrhenius data of reaction " + std::to_string(i));
+        int mr = 0, mp = 0;
+        for (auto &s : r.reac) mr += s.second;
+        for (auto &s : r.prod) mp += s.second;
+        if (mr > 2 || mp > 2)
+            return fail(CHEM_EMECH, "reaction " + std::to_string(i) + " has more than two molecules on a side");
+        for (int e = 0; e < m.E; e++) {
+            int bal = 0;
+            for (auto &s : r.reac) bal -= s.second * m.counts[s.first][e];
+            for (auto &s : r.prod) bal += s.second * m.counts[s.first][e];
+            if (bal != 0)
+                return fail(CHEM_EMECH, "reaction " + std::to_string(i) + " is not element balanced");
+        }
+    }
+    if (!t.expect("end")) return fail(CHEM_EMECH, "missing end marker");
+    return CHEM_OK;
+}
+
+}  // namespace
+
+struct chem_mech_s {
+    int device = 0;
+    HostMech host;
+    std::vector<double> W;
+    chem::DevMechView view{};
+    void *dev_block = nullptr;
+};
+
+namespace {
+
+void fill_range(const double *a, double *out)
+{
+    for (int j = 0; j < 7; j++) out[j] = a[j];
+    out[7] = a[1] / 2.0;
+    out[8] = a[2] / 3.0;
+    out[9] = a[3] / 4.0;
+    out[10] = a[4] / 5.0;
+    out[11] = a[2] / 2.0;
+    out[12] = a[3] / 3.0;
+    out[13] = a[4] / 4.0;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return CHEM_OK;
+    return fail(CHEM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool is_device_ptr(const void *p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *chem_last_error(void) { return g_err.c_str(); }
+
+int chem_default_opts(chem_opts *o)
+{
+    if (!o) return fail(CHEM_EINVAL, "opts is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->rtol = 1e-8;
+    o->atol = 1e-12;
+    o->max_steps = 20000;
+    o->precision = 0;
+    o->schedule = -1;
+    o->block = 0;
+    return CHEM_OK;
+}
+
+int chem_load_mechanism(const char *path, int device, chem_mech *out)
+{
+    if (!path || !out) return fail(CHEM_EINVAL, "path and out must not be NULL");
+    *out = nullptr;
+    auto *m = new chem_mech_s();
+    int rc = parse_mech(path, m->host);
+    if (rc != CHEM_OK) {
+        delete m;
+        return rc;
+    }
+    const HostMech &h = m->host;
+    m->device = device;
+    const int K = h.K, R = h.R;
+    // host-side tables
+    std::vector<double> species((size_t)K * chem::kSpeciesLen), W(K), invW(K);
+    bool two_range = false;
+    for (int k = 0; k < K; k++) {
+        double w = 0.0;
+        for (int e = 0; e < h.E; e++) w += h.counts[k][e] * h.aw[e];
+        W[k] = 1e-3 * w;
+        invW[k] = 1.0 / W[k];
+        double *s = &species[(size_t)k * chem::kSpeciesLen];
+        s[0] = h.nasa[k][1];
+        fill_range(&h.nasa[k][3], s + 1);
+        fill_range(&h.nasa[k][10], s + 1 + chem::kRangeLen);
+        for (int j = 0; j < 7; j++)
+            if (h.nasa[k][3 + j] != h.nasa[k][10 + j]) two_range = true;
+    }
+    std::vector<chem::DevRxn> rx(R > 0 ? R : 1);
+    for (int i = 0; i < R; i++) {
+        const HostRxn &r = h.rxn[i];
+        int slots_r[2] = {K, K}, slots_p[2] = {K, K}, nr = 0, np = 0, order = 0;
+        for (auto &s : r.reac)
+            for (int c = 0; c < s.second; c++) slots_r[nr++] = s.first;
+        for (auto &s : r.prod)
+            for (int c = 0; c < s.second; c++) slots_p[np++] = s.first;
+        order = nr;
+        chem::DevRxn d{};
+        d.r0 = slots_r[0];
+        d.r1 = slots_r[1];
+        d.p0 = slots_p[0];
+        d.p1 = slots_p[1];
+        d.dnu = np - nr;
+        // A in cm-mol-s: (cm^3/mol)^(order-1)/s; SI factor 1e-6 per extra order
+        d.lnA = std::log(r.A) + (order - 1) * std::log(1e-6);
+        d.b = r.b;
+        d.Ea_R = r.Ea / chem::kRu;
+        rx[i] = d;
+    }
+    m->W = W;
+    // one device block: species | W | invW | reactions
+    const size_t n_sp = species.size() * sizeof(double);
+    const size_t n_w = (size_t)K * sizeof(double);
+    const size_t off_w = (n_sp + 255) & ~size_t(255);
+    const size_t off_iw = (off_w + n_w + 255) & ~size_t(255);
+    const size_t off_rx = (off_iw + n_w + 255) & ~size_t(255);
+    const size_t total = off_rx + rx.size() * sizeof(chem::DevRxn);
+    int prev = 0;
+    if ((rc = check_hip(hipGetDevice(&prev), "hipGetDevice")) != CHEM_OK) {
+        delete m;
+        return rc;
+    }
+    if ((rc = check_hip(hipSetDevice(device), "hipSetDevice")) != CHEM_OK) {
+        delete m;
+        return rc;
+    }
+    char *blk = nullptr;
+    if (hipMalloc((void **)&blk, total) != hipSuccess) {
+        (void)hipGetLastError();
+        hipSetDevice(prev);
+        delete m;
+        return fail(CHEM_ENOMEM, "hipMalloc of the mechanism tables failed");
+    }
+    std::vector<char> staging(total, 0);
+    std::memcpy(staging.data(), species.data(), n_sp);
+    std::memcpy(staging.data() + off_w, W.data(), n_w);
+    std::memcpy(staging.data() + off_iw, invW.data(), n_w);
+    std::memcpy(staging.data() + off_rx, rx.data(), rx.size() * sizeof(chem::DevRxn));
+    rc = check_hip(hipMemcpy(blk, staging.data(), total, hipMemcpyHostToDevice), "hipMemcpy");
+    hipSetDevice(prev);
+    if (rc != CHEM_OK) {
+        hipFree(blk);
+        delete m;
+        return rc;
+    }
+    m->dev_block = blk;
+    m->view.K = K;
+    m->view.R = R;
+    m->view.two_range = two_range ? 1 : 0;
+    m->view.species = (const double *)blk;
+    m->view.W = (const double *)(blk + off_w);
+    m->view.invW = (const double *)(blk + off_iw);
+    m->view.rxn = (const chem::DevRxn *)(blk + off_rx);
+    *out = m;
+    return CHEM_OK;
+}
+
+void chem_free_mechanism(chem_mech m)
+{
+    if (!m) return;
+    if (m->dev_block) {
+        int prev = 0;
+        hipGetDevice(&prev);
+        hipSetDevice(m->device);
+        hipFree(m->dev_block);
+        hipSetDevice(prev);
+    }
+    delete m;
+}
+
+int chem_mechanism_info(chem_mech m, int32_t *K, int32_t *R, int32_t *E, double *W)
+{
+    if (!m) return fail(CHEM_EINVAL, "mechanism handle is NULL");
+    if (K) *K = m->host.K;
+    if (R) *R = m->host.R;
+    if (E) *E = m->host.E;
+    if (W)
+        for (int k = 0; k < m->host.K; k++) W[k] = m->W[k];
+    return CHEM_OK;
+}
+
+static int check_state_args(chem_mech m, const double *T, const double *p, const double *Y,
+                            int64_t ldY, int64_t n)
+{
+    if (!m) return fail(CHEM_EINVAL, "mechanism handle is NULL");
+    if (n < 0) return fail(CHEM_EINVAL, "ncells must be >= 0");
+    if (n == 0) return CHEM_OK;
+    if (ldY < n) return fail(CHEM_EINVAL, "ldY must be >= ncells");
+    if (!is_device_ptr(T) || !is_device_ptr(p) || !is_device_ptr(Y))
+        return fail(CHEM_EINVAL, "T, p and Y must be device pointers");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != m->device)
+        return fail(CHEM_EINVAL, "the current HIP device is not the mechanism's device");
+    return CHEM_OK;
+}
+
+int chem_integrate(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
+                   double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
+                   void *stream)
+{
+    int rc = check_state_args(m, T, p, Y, ldY, n);
+    if (rc != CHEM_OK) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be finite and > 0");
+    chem_opts o;
+    chem_default_opts(&o);
+    if (opts) o = *opts;
+    if (!(o.rtol > 0.0) || !(o.atol > 0.0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol))
+        return fail(CHEM_EINVAL, "rtol and atol must be finite and > 0");
+    if (o.max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
+    if (o.precision != 0) return fail(CHEM_EUNSUP, "only precision 0 (FP64) is implemented");
+    if (o.schedule != -1 && o.schedule != 0) return fail(CHEM_EUNSUP, "unknown schedule");
+    if (o.block != 0 && o.block != 64) return fail(CHEM_EUNSUP, "block must be 0 or 64");
+    if (n == 0) return CHEM_OK;
+    if ((status && !is_device_ptr(status)) || (counters && !is_device_ptr(counters)))
+        return fail(CHEM_EINVAL, "status and counters must be device pointers or NULL");
+    if (!chem::thread_kernel_supports(m->host.K))
+        return fail(CHEM_EUNSUP, "no integrator kernel is built for K = " + std::to_string(m->host.K));
+    chem::BdfParams prm{o.rtol, o.atol, o.max_steps, 0};
+    return check_hip(chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status, counters,
+                                             64, (hipStream_t)stream),
+                     "integrator launch");
+}
+
+int chem_eval_rhs(chem_mech m, const double *T, const double *p, const double *Y, int64_t ldY,
+                  int64_t n, double *F, int64_t ldF, void *stream)
+{
+    int rc = check_state_args(m, T, p, Y, ldY, n);
+    if (rc != CHEM_OK || n == 0) return rc;
+    if (ldF < n || !is_device_ptr(F)) return fail(CHEM_EINVAL, "F must be a device array with ldF >= ncells");
+    if (!chem::thread_kernel_supports(m->host.K))
+        return fail(CHEM_EUNSUP, "no kernel is built for K = " + std::to_string(m->host.K));
+    return check_hip(chem::launch_rhs(m->view, T, p, Y, ldY, n, F, ldF, (hipStream_t)stream), "rhs launch");
+}
+
+int chem_eval_jacobian(chem_mech m, const double *T, const double *p, const double *Y, int64_t ldY,
+                       int64_t n, double *J, int64_t ldJ, void *stream)
+{
+    int rc = check_state_args(m, T, p, Y, ldY, n);
+    if (rc != CHEM_OK || n == 0) return rc;
+    if (ldJ < n || !is_device_ptr(J)) return fail(CHEM_EINVAL, "J must be a device array with ldJ >= ncells");
+    if (!chem::thread_kernel_supports(m->host.K))
+        return fail(CHEM_EUNSUP, "no kernel is built for K = " + std::to_string(m->host.K));
+    return check_hip(chem::launch_jacobian(m->view, T, p, Y, ldY, n, J, ldJ, (hipStream_t)stream),
+                     "jacobian launch");
+}
+
+}  // extern "C"

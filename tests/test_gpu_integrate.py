@@ -1,0 +1,298 @@
+"""GPU parity: the HIP kernels (called through the C ABI) against the CPU
+oracle, element by element on the same seeded inputs.
+
+Bars (floating point): max|dT| < 1e-6 K and max|dY| < 1e-10 for the plain FP64
+integrator at rtol 1e-8 / atol 1e-12; per-cell step counts must agree.  The
+right-hand side and Jacobian kernels are compared at round-off level relative
+to the magnitude of the terms that cancel in them."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+P_ATM = 101325.0
+DT_TOL, DY_TOL = 1e-6, 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def gm9(mech_dir, torch):
+    from paper_2312_13513_amd import chem
+    m = chem.Mechanism(str(mech_dir / "M9.mech"), 0)
+    yield m
+    m.close()
+
+
+def run_gpu(torch, mech, T, p, Y, dt, opts=None, ld=None, want=True, stream=None):
+    dev = torch.device("cuda:0")
+    n = T.shape[0]
+    ld = ld or n
+    Yp = np.zeros((Y.shape[0], ld))
+    Yp[:, :n] = Y
+    if ld > n:
+        Yp[:, n:] = -7.0
+    Tt = torch.tensor(T, dtype=torch.float64, device=dev)
+    pt = torch.tensor(p, dtype=torch.float64, device=dev)
+    Yt = torch.tensor(Yp, dtype=torch.float64, device=dev)
+    st = torch.full((n,), -1, dtype=torch.int32, device=dev) if want else None
+    cn = torch.zeros(6 * n, dtype=torch.int32, device=dev) if want else None
+    mech.integrate(Tt, pt, Yt, dt, opts=opts, status=st, counters=cn, stream=stream)
+    torch.cuda.synchronize()
+    Yo = Yt.cpu().numpy()
+    out = (Tt.cpu().numpy(), Yo[:, :n].copy())
+    if ld > n:
+        assert np.all(Yo[:, n:] == -7.0), "padding columns were written"
+    if want:
+        return out + (st.cpu().numpy(), cn.cpu().numpy().reshape(6, n).T.copy())
+    return out
+
+
+def compare(tag, Tg, Yg, sg, cg, To, Yo, so, co):
+    dT = np.abs(Tg - To)
+    dY = np.abs(Yg - Yo).max(axis=0)
+    flips = np.where(cg[:, 0] != co[:, 0])[0]
+    _say(f"[{tag}] n={Tg.size} max|dT|={dT.max():.3e} K max|dY|={dY.max():.3e} "
+         f"status_eq={np.array_equal(sg, so)} step-count flips={flips.size}")
+    assert np.array_equal(sg, so)
+    assert dT.max() < DT_TOL, f"max|dT| {dT.max()} at cell {dT.argmax()}"
+    assert dY.max() < DY_TOL, f"max|dY| {dY.max()} at cell {dY.argmax()}"
+    return flips
+
+
+# --------------------------------------------------------------------------- building blocks
+
+def _states(m, n, seed):
+    from chemgen.fields import cells4096
+    f = cells4096(m, n=n, seed=seed)
+    return f.T, f.p, f.Y
+
+
+def test_rhs_parity(torch, gm9, om9, mech_dir):
+    from chemgen.mechanism import read_mechanism
+    m = read_mechanism(str(mech_dir / "M9.mech"))
+    T, p, Y = _states(m, 777, 21)
+    dev = torch.device("cuda:0")
+    F = torch.zeros((10, T.size), dtype=torch.float64, device=dev)
+    gm9.rhs(torch.tensor(T, device=dev), torch.tensor(p, device=dev), torch.tensor(Y, device=dev), F)
+    torch.cuda.synchronize()
+    Fg = F.cpu().numpy()
+    W = m.molar_masses()
+    worst = 0.0
+    for i in range(T.size):
+        fo = om9.rhs(p[i], np.append(Y[:, i], T[i]))
+        kf, kr, q, wd = om9.rates(T[i], p[i], Y[:, i])
+        rho = p[i] / (8.31446261815324 * T[i]) / np.sum(Y[:, i] / W)
+        C = rho * Y[:, i] / W
+        gross = np.zeros(9)
+        for r, (reac, prod, *_ ) in enumerate(m.reactions):
+            fwd = kf[r] * np.prod([C[k] ** nu for k, nu in reac])
+            rev = kr[r] * np.prod([C[k] ** nu for k, nu in prod])
+            for k, nu in reac + prod:
+                gross[k] += nu * (abs(fwd) + abs(rev))
+        scale = np.append(W * gross / rho, np.abs(fo[-1]) + 1e-300)
+        scale[-1] = max(scale[-1], np.sum(np.abs(om9.thermo(T[i])[1]) * 8.314 * T[i] * gross) /
+                        (rho * np.sum(Y[:, i] * om9.thermo(T[i])[0] * 8.314 / W)))
+        err = np.abs(Fg[:, i] - fo) / scale
+        worst = max(worst, err.max())
+    _say(f"[rhs] worst relative-to-gross error {worst:.2e}")
+    assert worst < 1e-12
+
+
+def test_jacobian_parity(torch, gm9, om9, mech_dir):
+    from chemgen.mechanism import read_mechanism
+    m = read_mechanism(str(mech_dir / "M9.mech"))
+    T, p, Y = _states(m, 300, 22)
+    dev = torch.device("cuda:0")
+    J = torch.zeros((100, T.size), dtype=torch.float64, device=dev)
+    gm9.jacobian(torch.tensor(T, device=dev), torch.tensor(p, device=dev), torch.tensor(Y, device=dev), J)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy()
+    worst = 0.0
+    for i in range(T.size):
+        Jo = om9.jac(p[i], np.append(Y[:, i], T[i]))
+        Jc = om9.jac_cs(p[i], np.append(Y[:, i], T[i]))
+        scale = np.maximum(np.abs(Jo), np.abs(Jc)).max(axis=1, keepdims=True)
+        worst = max(worst, (np.abs(Jg[:, i].reshape(10, 10) - Jo) / scale).max())
+    _say(f"[jacobian] worst row-relative error {worst:.2e}")
+    assert worst < 1e-12
+
+
+# --------------------------------------------------------------------------- integrator
+
+@pytest.fixture(scope="module")
+def cells4096_run(torch, gm9, om9, mech_dir):
+    from chemgen.fields import cells4096
+    from chemgen.mechanism import read_mechanism
+    m = read_mechanism(str(mech_dir / "M9.mech"))
+    f = cells4096(m)
+    _say("[cells4096] GPU run")
+    g = run_gpu(torch, gm9, f.T, f.p, f.Y, f.dt)
+    o = om9.integrate(f.T, f.p, f.Y, f.dt)[:4]
+    return f, g, o
+
+
+def test_parity_cells4096(cells4096_run, om9):
+    f, g, o = cells4096_run
+    flips = compare("cells4096", *g, *o)
+    assert flips.size == 0
+    assert np.all(g[2] == 0)
+    # error of both against a tight-tolerance run (reported beside parity)
+    idx = np.arange(0, f.n, 16)
+    Tt, Yt, st, _, _ = om9.integrate(f.T[idx], f.p[idx], f.Y[:, idx], f.dt, rtol=1e-13, atol=1e-17,
+                                     max_steps=200000)
+    _say(f"[cells4096] error vs rtol=1e-13 run: max|dT| = {np.abs(g[0][idx] - Tt).max():.2e} K, "
+         f"max|dY| = {np.abs(g[1][:, idx] - Yt).max():.2e}")
+
+
+def test_counters_match_oracle(cells4096_run):
+    f, g, o = cells4096_run
+    for c, name in enumerate(("nst", "nfe", "nje", "nni", "netf", "ncfn")):
+        same = np.mean(g[3][:, c] == o[3][:, c])
+        _say(f"[cells4096] counter {name}: fraction equal {same:.5f}")
+        assert same == 1.0
+
+
+def test_parity_flame64_sampled(torch, gm9, om9, mech_dir):
+    """The 64^3 flame field in the benchmark's launch configuration; the oracle
+    integrates a seeded sample of 4096 cells."""
+    from chemgen.fields import flame64, seeded_sample
+    from chemgen.mechanism import read_mechanism
+    m = read_mechanism(str(mech_dir / "M9.mech"))
+    f = flame64(m)
+    _say("[flame64] GPU run, 262144 cells")
+    Tg, Yg, sg, cg = run_gpu(torch, gm9, f.T, f.p, f.Y, f.dt)
+    assert np.all(sg == 0)
+    idx = seeded_sample(f.n, 4096, seed=11)
+    To, Yo, so, co, _ = om9.integrate(f.T[idx], f.p[idx], f.Y[:, idx], f.dt)
+    flips = compare("flame64-sample", Tg[idx], Yg[:, idx], sg[idx], cg[idx], To, Yo, so, co)
+    assert flips.size <= 1
+    # properties at every cell: element totals and enthalpy are conserved
+    W = m.molar_masses()
+    b0 = m.counts.T @ (f.Y / W[:, None])
+    b1 = m.counts.T @ (Yg / W[:, None])
+    assert np.max(np.abs(b1 - b0) / (np.abs(b0) + 1e-30)) < 1e-10
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 257])
+def test_ragged_sizes_match_full_run(torch, gm9, cells4096_run, n):
+    f, g, o = cells4096_run
+    sel = np.arange(100, 100 + n)
+    Tg, Yg, sg, cg = run_gpu(torch, gm9, f.T[sel], f.p[sel], f.Y[:, sel], f.dt)
+    assert np.array_equal(Tg, g[0][sel]) and np.array_equal(Yg, g[1][:, sel])
+    assert np.array_equal(cg, g[3][sel])
+
+
+def test_leading_dimension_and_optional_outputs(torch, gm9, cells4096_run):
+    f, g, o = cells4096_run
+    sel = np.arange(0, 300)
+    Tg, Yg = run_gpu(torch, gm9, f.T[sel], f.p[sel], f.Y[:, sel], f.dt, ld=333, want=False)
+    assert np.array_equal(Tg, g[0][sel]) and np.array_equal(Yg, g[1][:, sel])
+
+
+def test_side_stream(torch, gm9, cells4096_run):
+    f, g, o = cells4096_run
+    sel = np.arange(0, 256)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        Tg, Yg, sg, cg = run_gpu(torch, gm9, f.T[sel], f.p[sel], f.Y[:, sel], f.dt, stream=s)
+    assert np.array_equal(Tg, g[0][sel])
+
+
+def test_zero_cells_is_noop(torch, gm9):
+    dev = torch.device("cuda:0")
+    T = torch.zeros(0, dtype=torch.float64, device=dev)
+    Y = torch.zeros((9, 0), dtype=torch.float64, device=dev)
+    gm9.integrate(T, T, Y, 1e-6)
+    torch.cuda.synchronize()
+
+
+def test_bad_arguments(torch, gm9):
+    from paper_2312_13513_amd import chem
+    dev = torch.device("cuda:0")
+    T = torch.full((4,), 1000.0, dtype=torch.float64, device=dev)
+    Y = torch.full((9, 4), 1 / 9, dtype=torch.float64, device=dev)
+    for dt in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(chem.ChemError):
+            gm9.integrate(T, T, Y, dt)
+    Tc = T.cpu()                              # host arrays are rejected
+    rc = chem.lib().chem_integrate(chem.C.c_void_p(gm9.handle), Tc.data_ptr(), T.data_ptr(),
+                                   Y.data_ptr(), 4, 4, 1e-6, None, None, None, None)
+    assert rc == -1
+    o = chem.chem_default_opts()
+    o.rtol = -1.0
+    with pytest.raises(chem.ChemError):
+        gm9.integrate(T, T, Y, 1e-6, opts=o)
+
+
+def test_max_steps_and_nan_status(torch, gm9, cells4096_run):
+    from paper_2312_13513_amd import chem
+    f, g, o = cells4096_run
+    sel = np.arange(0, 128)
+    opts = chem.chem_default_opts()
+    opts.max_steps = 1
+    Tg, Yg, sg, cg = run_gpu(torch, gm9, f.T[sel], f.p[sel], f.Y[:, sel], f.dt, opts=opts)
+    many = g[3][sel, 0] > 1
+    assert np.all(sg[many] == 1)
+    assert np.array_equal(Tg[many], f.T[sel][many]) and np.array_equal(Yg[:, many], f.Y[:, sel][:, many])
+    T = f.T[sel].copy()
+    T[5] = float("nan")
+    Tg, Yg, sg, cg = run_gpu(torch, gm9, T, f.p[sel], f.Y[:, sel], f.dt)
+    assert sg[5] == 4 and np.isnan(Tg[5])
+    ok = np.arange(128) != 5
+    assert np.all(sg[ok] == 0) and np.array_equal(Tg[ok], g[0][sel][ok])
+
+
+def test_equilibrium_cells_one_step(torch, gm9, mech_dir):
+    from chemgen.fields import flame_field
+    from chemgen.mechanism import read_mechanism
+    m = read_mechanism(str(mech_dir / "M9.mech"))
+    f = flame_field(m, (16, 16, 16), 102, 1e-6, "t", "M9")
+    ends = np.where((f.c < 1e-12) | (f.c > 1 - 1e-12))[0]
+    Tg, Yg, sg, cg = run_gpu(torch, gm9, f.T[ends], f.p[ends], f.Y[:, ends], f.dt)
+    assert np.all(sg == 0) and np.all(cg[:, 0] <= 2)
+
+
+def test_isomerisation_closed_form_gpu(torch, tmp_path):
+    """A <-> B relaxation on the GPU against the exponential closed form."""
+    from chemgen.mechanism import custom_mechanism
+    from paper_2312_13513_amd import chem
+    K_eq, rate = 2.5, 1e9
+    k_f = rate * K_eq / (1 + K_eq)
+    counts = [[1, 1], [1, 1]] + [[1, 0]] * 4 + [[0, 1]] * 3
+    coeffs = [[3.5, 0, 0, 0, 0, 0.0, 10.0], [3.5, 0, 0, 0, 0, 0.0, 10.0 + math.log(K_eq)]] + \
+             [[3.0, 0, 0, 0, 0, 0.0, 5.0]] * 7
+    mm = custom_mechanism(counts, coeffs, [([(0, 1)], [(1, 1)], k_f, 0.0, 0.0)])
+    path = str(tmp_path / "iso.mech")
+    mm.write(path)
+    gm = chem.Mechanism(path, 0)
+    n = 64
+    rng = np.random.default_rng(4)
+    Y = np.zeros((9, n))
+    Y[0] = rng.uniform(0.05, 0.6, n)
+    Y[1] = rng.uniform(0.0, 0.3, n)
+    Y[2] = 1 - Y[0] - Y[1]
+    T = rng.uniform(600, 2000, n)
+    dt = 3.0 / rate
+    Tg, Yg, sg, cg = run_gpu(torch, gm, T, np.full(n, P_ATM), Y, dt)
+    Yeq = (Y[0] + Y[1]) / (1 + K_eq)
+    exact = Yeq + (Y[0] - Yeq) * math.exp(-rate * dt)
+    assert np.all(sg == 0)
+    assert np.all(np.abs(Yg[0] - exact) <= 100 * (1e-8 * np.abs(exact) + 1e-12))
+    assert np.allclose(Tg, T, rtol=1e-12)
+    gm.close()
