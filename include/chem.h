@@ -83,6 +83,12 @@ void chem_free_mechanism(chem_mech mech);
  * species molar masses in kg/mol (host memory). */
 int chem_mechanism_info(chem_mech mech, int32_t *K, int32_t *R, int32_t *E, double *W);
 
+/* Which kernels serve this mechanism: "specialised:<tag>" when the file was
+ * compiled into the library by the mechanism compiler (straight-line
+ * right-hand side and Jacobian), "table" for the table-driven kernels.
+ * The string is owned by the handle. */
+const char *chem_mechanism_variant(chem_mech mech);
+
 /* Advance ncells cells over [0, dt] in place.
  *   T[ncells]            temperature, K (in/out)
  *   p[ncells]            pressure, Pa (in), constant over the step

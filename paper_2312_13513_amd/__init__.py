@@ -2,7 +2,13 @@
 
 The HIP library ``libchem.so`` (C ABI in include/chem.h) integrates every CFD
 cell over a flow step as an adiabatic constant-pressure reactor; ``chem`` is
-its ctypes binding over torch device tensors and streams.
+its ctypes binding over torch device tensors and streams.  Importing ``chem``
+fails loudly when the library has not been built (there is no CPU fallback).
 """
-from . import chem  # noqa: F401  (fails loudly if the library is not built)
-from .chem import Mechanism, ChemError  # noqa: F401
+
+
+def __getattr__(name):
+    if name in ("Mechanism", "ChemError"):
+        from . import chem
+        return getattr(chem, name)
+    raise AttributeError(name)

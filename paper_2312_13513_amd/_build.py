@@ -22,18 +22,40 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+def specialised_mechanisms(outdir: str) -> dict:
+    """Mechanisms that get compiled-in specialised kernels: the standard
+    9-species synthetic mechanism (one thread per cell holds its state), plus
+    any .mech files listed in CHEM_EXTRA_MECHS (colon-separated paths)."""
+    sys.path.insert(0, os.path.dirname(HERE))
+    from chemgen.mechanism import standard_mechanism
+    os.makedirs(outdir, exist_ok=True)
+    paths = {}
+    p = os.path.join(outdir, "M9.mech")
+    standard_mechanism("M9").write(p)
+    paths["M9"] = p
+    for i, extra in enumerate(filter(None, os.environ.get("CHEM_EXTRA_MECHS", "").split(":"))):
+        paths[f"X{i}"] = extra
+    return paths
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source and link libchem.so (always rebuilds)."""
+    """Generate the specialised sources, compile everything, link libchem.so
+    (always rebuilds)."""
+    from . import codegen
     objdir = os.path.join(HERE, "_build")
+    gendir = os.path.join(objdir, "gen")
     os.makedirs(objdir, exist_ok=True)
+    gen_sources = codegen.write_generated(specialised_mechanisms(gendir), gendir)
     objs = []
-    for src in sources():
+    for src in sources() + gen_sources:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = ["hipcc", *HIPCC_FLAGS, *lang, "-c", src, "-o", obj]
+        cmd = ["hipcc", *HIPCC_FLAGS, "-I", CSRC, "-x", "hip", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=subprocess.PIPE if not verbose else None)
+        r = subprocess.run(cmd, stderr=subprocess.PIPE, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stderr)
+            raise RuntimeError(f"hipcc failed on {src}")
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
@@ -43,4 +65,6 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2312_13513_amd import _build as b
+    print(b.build(verbose="-v" in sys.argv))

@@ -43,6 +43,8 @@ def _load():
     L.chem_free_mechanism.argtypes = [vp]
     L.chem_free_mechanism.restype = None
     L.chem_mechanism_info.argtypes = [vp, i32p, i32p, i32p, C.POINTER(C.c_double)]
+    L.chem_mechanism_variant.restype = C.c_char_p
+    L.chem_mechanism_variant.argtypes = [vp]
     L.chem_integrate.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), vp, vp, vp]
     L.chem_eval_rhs.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, vp]
     L.chem_eval_jacobian.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, vp]
@@ -53,7 +55,7 @@ _lib = _load()
 
 #: Symbols that include/chem.h declares (checked by the ABI test).
 EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
-            "chem_mechanism_info", "chem_integrate", "chem_eval_rhs", "chem_eval_jacobian",
+            "chem_mechanism_info", "chem_mechanism_variant", "chem_integrate", "chem_eval_rhs", "chem_eval_jacobian",
             "chem_last_error")
 
 
@@ -105,6 +107,10 @@ def chem_mechanism_info(handle: int) -> Tuple[int, int, int, list]:
     return K.value, R.value, E.value, list(W[: K.value])
 
 
+def chem_mechanism_variant(handle: int) -> str:
+    return _lib.chem_mechanism_variant(C.c_void_p(handle)).decode()
+
+
 def chem_integrate(handle: int, T, p, Y, dt: float, opts: Optional[chem_opts] = None,
                    status=None, counters=None, stream=None, ncells: Optional[int] = None) -> None:
     """Advance the cells in place: T (n,), p (n,), Y (K, ldY) float64 GPU tensors."""
@@ -133,6 +139,7 @@ class Mechanism:
         self.handle = chem_load_mechanism(path, device)
         self.K, self.R, self.E, self.W = chem_mechanism_info(self.handle)
         self.N = self.K + 1
+        self.variant = chem_mechanism_variant(self.handle)
 
     def close(self):
         if self.handle:

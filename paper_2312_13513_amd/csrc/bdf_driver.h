@@ -1,0 +1,831 @@
+// BDF integrator driver for gfx950: one lane owns one cell, lanes refill from
+// a work queue, and each lane runs a small state machine so that the costly
+// pieces -- the right-hand side and the Jacobian + LU -- have exactly one call
+// site each.  Whatever phase a lane is in (initial-step estimate, Newton
+// iteration, restart), all lanes that need a right-hand side evaluate it
+// together in the same instruction stream; branch divergence is confined to
+// the cheap bookkeeping between those sites.
+//
+// The decisions follow the integrator contract shared with the CPU oracle
+// (variable-order 1..5, variable-coefficient BDF in Nordsieck form, modified
+// Newton); only their scheduling across lanes differs.
+//
+// Mech is a functor type with `static constexpr int K` and device members
+//   rhs(p, y[K+1], f[K+1])   and   jac(p, y[K+1], J[(K+1)*(K+1)]).
+#pragma once
+
+#include "chem_internal.h"
+
+namespace chem {
+
+// ---------------------------------------------------------------------------
+// dense LU with row partial pivoting, registers, static indexing
+// ---------------------------------------------------------------------------
+
+// Factor in place; ties keep the upper row.  Pivot rows are recorded in a
+// packed 4-bit-per-column word pair (N <= 16) or an int array.
+template <int N>
+__device__ __forceinline__ bool lu_factor(double *M, int *piv)
+{
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        int pk = k;
+        double best = fabs(M[k * N + k]);
+#pragma unroll
+        for (int r = k + 1; r < N; r++) {
+            const double v = fabs(M[r * N + k]);
+            if (v > best) {
+                best = v;
+                pk = r;
+            }
+        }
+        piv[k] = pk;
+        ok = ok && (best != 0.0);
+        if (pk != k) {
+#pragma unroll
+            for (int r = k + 1; r < N; r++) {
+                if (pk == r) {
+#pragma unroll
+                    for (int c = 0; c < N; c++) {
+                        const double t = M[k * N + c];
+                        M[k * N + c] = M[r * N + c];
+                        M[r * N + c] = t;
+                    }
+                }
+            }
+        }
+        const double inv = 1.0 / M[k * N + k];
+#pragma unroll
+        for (int r = k + 1; r < N; r++) {
+            const double l = M[r * N + k] * inv;
+            M[r * N + k] = l;
+#pragma unroll
+            for (int c = k + 1; c < N; c++) M[r * N + c] -= l * M[k * N + c];
+        }
+    }
+    return ok;
+}
+
+template <int N>
+__device__ __forceinline__ void lu_solve(const double *M, const int *piv, double *b)
+{
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        const int pk = piv[k];
+        if (pk != k) {
+#pragma unroll
+            for (int r = k + 1; r < N; r++) {
+                if (pk == r) {
+                    const double t = b[k];
+                    b[k] = b[r];
+                    b[r] = t;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 1; r < N; r++)
+#pragma unroll
+        for (int c = 0; c < r; c++) b[r] -= M[r * N + c] * b[c];
+#pragma unroll
+    for (int r = N - 1; r >= 0; r--) {
+#pragma unroll
+        for (int c = r + 1; c < N; c++) b[r] -= M[r * N + c] * b[c];
+        b[r] /= M[r * N + r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// contract constants
+// ---------------------------------------------------------------------------
+
+namespace bdf {
+constexpr int kMaxCor = 3;
+constexpr int kMsbp = 20;
+constexpr double kDgmax = 0.3;
+constexpr double kCrdown = 0.3;
+constexpr double kRdiv = 2.0;
+constexpr double kNlscoef = 0.1;
+constexpr int kMaxNef = 7;
+constexpr int kMaxNcf = 10;
+constexpr double kEtaCf = 0.25;
+constexpr double kEtaMinEf = 0.1;
+constexpr double kEtaMaxEf = 0.9;
+constexpr double kEtaNef2 = 0.2;
+constexpr int kNefRestart = 3;
+constexpr double kThresh = 1.5;
+constexpr double kEtaMaxFirst = 1e4;
+constexpr double kEtaMax = 10.0;
+constexpr double kBiasQm1 = 6.0, kBiasQ = 6.0, kBiasQp1 = 10.0;
+constexpr double kAddon = 1e-6;
+constexpr int kH0Iters = 4;
+
+enum Phase : int { FETCH = 0, F0 = 1, H0 = 2, NEWTON = 3, RESTART = 4, LUFAIL = 5, DONE = 6 };
+}  // namespace bdf
+
+template <int N>
+__device__ __forceinline__ double wrms_norm(const double *v, const double *w)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        const double t = v[i] * w[i];
+        s += t * t;
+    }
+    return sqrt(s * (1.0 / N));
+}
+
+template <int N>
+__device__ __forceinline__ bool finite_vec(const double *v)
+{
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < N; i++) ok = ok && isfinite(v[i]);
+    return ok;
+}
+
+__device__ __forceinline__ double factorial_d(int n)
+{
+    double f = 1.0;
+#pragma unroll
+    for (int i = 2; i <= 7; i++)
+        if (i <= n) f *= i;
+    return f;
+}
+
+// Nordsieck array of one lane in LDS: element (j, i) of lane L at
+// lds[(j*N + i)*64 + L], so a wave's 64 lanes touch 64 consecutive doubles and
+// every static (j, i) is an immediate offset.
+template <int N>
+struct NordLds {
+    double *base;   // lds + lane
+    __device__ __forceinline__ double &operator()(int j, int i) const { return base[(j * N + i) * 64]; }
+};
+
+// Per-lane integrator state.  Every array is indexed statically.
+template <int N>
+struct LaneState {
+    NordLds<N> z;               // Nordsieck array (LDS)
+    double M[N * N];            // LU factors of I - gamma_M J
+    int piv[N];
+    double w[N], e[N], ehat[N], fy[N];
+    double tau[kQmax + 2];      // past step sizes, tau[1] most recent
+    double xi[kQmax + 2], l[kQmax + 1];
+    double p, t, h, t_end, gamma, gamma_M, Cq, crate, del_old, dsm, ehat_h, s_eval, hg, hub;
+    int64_t cell;
+    int phase, q, qwait, nst_M, it, nef, ncf, h0_it;
+    bool have_M, ehat_ok, force_M, last, jcur, need_J;
+    int nst, nfe, nje, nni, netf, ncfn;
+};
+
+template <int N>
+__device__ __forceinline__ void nord_predict(LaneState<N> &S)
+{
+#pragma unroll
+    for (int k = 1; k <= kQmax; k++)
+#pragma unroll
+        for (int j = kQmax; j >= k; j--)
+            if (j <= S.q)
+#pragma unroll
+                for (int i = 0; i < N; i++) S.z(j - 1, i) += S.z(j, i);
+}
+
+template <int N>
+__device__ __forceinline__ void nord_restore(LaneState<N> &S)
+{
+#pragma unroll
+    for (int k = kQmax; k >= 1; k--)
+#pragma unroll
+        for (int j = k; j <= kQmax; j++)
+            if (j <= S.q && k <= S.q)
+#pragma unroll
+                for (int i = 0; i < N; i++) S.z(j - 1, i) -= S.z(j, i);
+}
+
+template <int N>
+__device__ __forceinline__ void nord_rescale(LaneState<N> &S, double eta)
+{
+    double f = 1.0;
+#pragma unroll
+    for (int j = 1; j <= kQmax; j++) {
+        f *= eta;
+        if (j <= S.q)
+#pragma unroll
+            for (int i = 0; i < N; i++) S.z(j, i) *= f;
+    }
+}
+
+// xi_{q+1} = (h + tau_1 + ... + tau_q) / h, summed with the order as a guard
+// on values (an element pick by order would become a dynamic register index).
+template <int N>
+__device__ __forceinline__ double xi_q1(const LaneState<N> &S)
+{
+    double s = S.h;
+#pragma unroll
+    for (int i = 1; i <= kQmax; i++)
+        if (i <= S.q) s += S.tau[i];
+    return s / S.h;
+}
+
+struct CellIO {
+    double *T;
+    const double *p;
+    double *Y;
+    int64_t ldY, n;
+    int32_t *status, *counters;
+    const BdfParams *prm;
+};
+
+template <int N>
+__device__ __forceinline__ void finish_cell(LaneState<N> &S, const CellIO &io, int st)
+{
+    constexpr int K = N - 1;
+    double y[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) y[i] = S.z(0, i);
+    if (st == 0 && !finite_vec<N>(y)) st = 4;
+    const int64_t i = S.cell;
+    if (st == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) io.Y[k * io.ldY + i] = y[k];
+        io.T[i] = y[K];
+    }
+    if (io.status) io.status[i] = st;
+    if (io.counters) {
+        io.counters[0 * io.n + i] = S.nst;
+        io.counters[1 * io.n + i] = S.nfe;
+        io.counters[2 * io.n + i] = S.nje;
+        io.counters[3 * io.n + i] = S.nni;
+        io.counters[4 * io.n + i] = S.netf;
+        io.counters[5 * io.n + i] = S.ncfn;
+    }
+    S.phase = bdf::FETCH;
+}
+
+// Predict, compute the step coefficients and decide whether M is refreshed.
+template <int N>
+__device__ __forceinline__ void begin_attempt(LaneState<N> &S, const CellIO &io)
+{
+    const double tnew = S.t + S.h;
+    if (tnew == S.t) {
+        finish_cell(S, io, 2);
+        return;
+    }
+    nord_predict(S);
+    {
+        double s = S.h;
+        S.xi[1] = 1.0;
+#pragma unroll
+        for (int i = 2; i <= kQmax + 1; i++) {
+            s += S.tau[i - 1];
+            S.xi[i] = s / S.h;
+        }
+        S.l[0] = 1.0;
+#pragma unroll
+        for (int j = 1; j <= kQmax; j++) S.l[j] = 0.0;
+#pragma unroll
+        for (int i = 1; i <= kQmax; i++)
+            if (i <= S.q)
+#pragma unroll
+                for (int j = i; j >= 1; j--) S.l[j] += S.l[j - 1] / S.xi[i];
+    }
+    S.gamma = S.h / S.l[1];
+    S.Cq = 1.0 / (1.0 + S.l[1] * xi_q1(S));
+    S.jcur = false;
+    S.need_J = !S.have_M || S.force_M || S.nst >= S.nst_M + bdf::kMsbp ||
+               fabs(S.gamma / S.gamma_M - 1.0) > bdf::kDgmax;
+#pragma unroll
+    for (int i = 0; i < N; i++) S.e[i] = 0.0;
+    S.it = 0;
+    S.del_old = 0.0;
+    S.s_eval = 1.0;
+    S.phase = bdf::NEWTON;
+}
+
+template <int N>
+__device__ __forceinline__ void begin_step(LaneState<N> &S, const CellIO &io)
+{
+    if (S.nst >= io.prm->max_steps) {
+        finish_cell(S, io, 1);
+        return;
+    }
+    S.last = false;
+    if (S.t + S.h >= S.t_end) {
+        nord_rescale(S, (S.t_end - S.t) / S.h);
+        S.h = S.t_end - S.t;
+        S.last = true;
+    }
+#pragma unroll
+    for (int i = 0; i < N; i++) S.w[i] = 1.0 / (io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
+    S.nef = 0;
+    S.ncf = 0;
+    S.force_M = false;
+    begin_attempt(S, io);
+}
+
+template <int N>
+__device__ __forceinline__ void begin_integration(LaneState<N> &S, const CellIO &io)
+{
+    // S.h set; S.ehat holds f(y0); z[0] holds y0
+    S.q = 1;
+#pragma unroll
+    for (int i = 0; i < N; i++) S.z(1, i) = S.h * S.ehat[i];
+    S.qwait = 2;
+    S.have_M = false;
+    S.ehat_ok = false;
+    S.gamma_M = 0.0;
+    S.crate = 1.0;
+    S.ehat_h = 0.0;
+    S.t = 0.0;
+    begin_step(S, io);
+}
+
+template <int N>
+__device__ __forceinline__ void conv_fail(LaneState<N> &S, const CellIO &io)
+{
+    nord_restore(S);
+    if (!S.jcur) {
+        S.force_M = true;
+        begin_attempt(S, io);
+        return;
+    }
+    S.ncfn++;
+    if (++S.ncf >= bdf::kMaxNcf) {
+        finish_cell(S, io, 3);
+        return;
+    }
+    nord_rescale(S, bdf::kEtaCf);
+    S.h *= bdf::kEtaCf;
+    S.last = false;
+    begin_attempt(S, io);
+}
+
+// Step size and order for the step after an accepted one.
+template <int N>
+__device__ __forceinline__ void select_next(LaneState<N> &S)
+{
+    using namespace bdf;
+    const int q = S.q;
+    const double h_done = S.h;
+    double prod_q = 1.0;
+#pragma unroll
+    for (int i = 1; i <= kQmax; i++)
+        if (i <= q) prod_q *= S.xi[i];
+    const double x1 = xi_q1(S);
+    const double gfac = prod_q * (1.0 / S.l[1] + x1) / factorial_d(q + 1);
+    double ehat_new[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) ehat_new[i] = S.e[i] / gfac;
+    if (S.qwait > 0) S.qwait--;
+    const double etamax = (S.nef > 0 || S.ncf > 0) ? 1.0 : (S.nst == 1 ? kEtaMaxFirst : kEtaMax);
+    double eta = 1.0;
+    int qnew = q;
+    if (etamax > 1.0) {
+        eta = 1.0 / (pow(kBiasQ * S.dsm, 1.0 / (q + 1)) + kAddon);
+        if (S.qwait == 0) {
+            double eta_m = 0.0, eta_p = 0.0;
+            if (q > 1) {
+                double prod = 1.0, l1 = 0.0, zq[N];
+#pragma unroll
+                for (int i = 0; i < N; i++) zq[i] = 0.0;
+#pragma unroll
+                for (int j = 2; j <= kQmax; j++)
+                    if (j == q)
+#pragma unroll
+                        for (int i = 0; i < N; i++) zq[i] = S.z(j, i);
+#pragma unroll
+                for (int i = 1; i < kQmax; i++)
+                    if (i <= q - 1) {
+                        prod *= S.xi[i];
+                        l1 += 1.0 / S.xi[i];
+                    }
+                const double Em = wrms_norm<N>(zq, S.w) * prod / l1;
+                eta_m = 1.0 / (pow(kBiasQm1 * Em, 1.0 / q) + kAddon);
+            }
+            if (q < kQmax && S.ehat_ok) {
+                const double rr = pow(h_done / S.ehat_h, q + 1);
+                double dv[N];
+#pragma unroll
+                for (int i = 0; i < N; i++) dv[i] = ehat_new[i] - S.ehat[i] * rr;
+                double prod = 1.0, l1 = 0.0;
+#pragma unroll
+                for (int i = 1; i <= kQmax; i++)
+                    if (i <= q + 1) {
+                        prod *= S.xi[i];
+                        l1 += 1.0 / S.xi[i];
+                    }
+                const double Ep = wrms_norm<N>(dv, S.w) * prod / (factorial_d(q + 2) * l1);
+                eta_p = 1.0 / (pow(kBiasQp1 * Ep, 1.0 / (q + 2)) + kAddon);
+            }
+            if (eta_m > eta && eta_m >= eta_p) {
+                eta = eta_m;
+                qnew = q - 1;
+            } else if (eta_p > eta) {
+                eta = eta_p;
+                qnew = q + 1;
+            }
+        }
+        if (eta < kThresh) {
+            eta = 1.0;
+            qnew = q;
+        } else if (eta > etamax) {
+            eta = etamax;
+        }
+    }
+    if (qnew == q - 1) {
+        // drop the top column: subtract z_q * x * prod_{i<q} (x + xi_i)
+        double d[kQmax + 2];
+#pragma unroll
+        for (int j = 0; j < kQmax + 2; j++) d[j] = 0.0;
+        d[1] = 1.0;
+#pragma unroll
+        for (int i = 1; i < kQmax; i++)
+            if (i <= q - 1)
+#pragma unroll
+                for (int j = kQmax; j >= 1; j--)
+                    if (j <= i + 1) d[j] = d[j - 1] + S.xi[i] * d[j];
+        double zq[N];
+#pragma unroll
+        for (int i = 0; i < N; i++) zq[i] = 0.0;
+#pragma unroll
+        for (int j = 2; j <= kQmax; j++)
+            if (j == q)
+#pragma unroll
+                for (int i = 0; i < N; i++) zq[i] = S.z(j, i);
+#pragma unroll
+        for (int j = 1; j < kQmax; j++)
+            if (j < q)
+#pragma unroll
+                for (int i = 0; i < N; i++) S.z(j, i) -= d[j] * zq[i];
+        S.q = qnew;
+        S.qwait = qnew + 1;
+        S.ehat_ok = false;
+    } else if (qnew == q + 1) {
+        // add e * (x / xi_{q+1}) * Lambda_q(x)
+        const double inv = 1.0 / x1;
+#pragma unroll
+        for (int j = 2; j <= kQmax; j++)
+            if (j == q + 1)
+#pragma unroll
+                for (int i = 0; i < N; i++) S.z(j, i) = 0.0;
+#pragma unroll
+        for (int j = 1; j <= kQmax; j++)
+            if (j <= q + 1)
+#pragma unroll
+                for (int i = 0; i < N; i++) S.z(j, i) += S.e[i] * S.l[j - 1] * inv;
+        S.q = qnew;
+        S.qwait = qnew + 1;
+        S.ehat_ok = false;
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; i++) S.ehat[i] = ehat_new[i];
+        S.ehat_h = h_done;
+        S.ehat_ok = true;
+    }
+#pragma unroll
+    for (int i = kQmax + 1; i >= 2; i--) S.tau[i] = S.tau[i - 1];
+    S.tau[1] = h_done;
+    if (eta != 1.0) {
+        nord_rescale(S, eta);
+        S.h *= eta;
+    }
+}
+
+// Error test after a converged Newton iteration; accept or retry.
+template <int N>
+__device__ __forceinline__ void error_test(LaneState<N> &S, const CellIO &io)
+{
+    using namespace bdf;
+    S.dsm = S.Cq * wrms_norm<N>(S.e, S.w);
+    if (S.dsm > 1.0) {
+        nord_restore(S);
+        S.netf++;
+        if (++S.nef >= kMaxNef) {
+            finish_cell(S, io, 2);
+            return;
+        }
+        S.last = false;
+        if (S.nef >= kNefRestart) {
+            S.h *= kEtaMinEf;
+            S.q = 1;
+            S.s_eval = 0.0;
+            S.phase = RESTART;   // needs f(z0)
+            return;
+        }
+        double eta = 1.0 / (pow(kBiasQ * S.dsm, 1.0 / (S.q + 1)) + kAddon);
+        eta = fmin(fmax(eta, kEtaMinEf), kEtaMaxEf);
+        if (S.nef >= 2) eta = fmin(eta, kEtaNef2);
+        nord_rescale(S, eta);
+        S.h *= eta;
+        begin_attempt(S, io);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j <= kQmax; j++)
+        if (j <= S.q)
+#pragma unroll
+            for (int i = 0; i < N; i++) S.z(j, i) += S.l[j] * S.e[i];
+    S.t = S.last ? S.t_end : S.t + S.h;
+    S.nst++;
+    if (S.t >= S.t_end) {
+        finish_cell(S, io, 0);
+        return;
+    }
+    select_next(S);
+    begin_step(S, io);
+}
+
+template <class Mech>
+__device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
+                          unsigned long long *queue, double *lds)
+{
+    constexpr int K = Mech::K;
+    constexpr int N = K + 1;
+    using namespace bdf;
+    LaneState<N> S;
+    S.z.base = lds + (threadIdx.x & 63);
+    S.phase = FETCH;
+    S.t_end = t_end;
+    S.need_J = false;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        // ---- refill idle lanes from the queue (one atomic per wave) ----
+        {
+            const bool want = (S.phase == FETCH);
+            const unsigned long long mask = __ballot(want);
+            if (mask) {
+                const int leader = __ffsll((long long)mask) - 1;
+                const int cnt = __popcll(mask);
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(queue, (unsigned long long)cnt);
+                base = __shfl(base, leader);
+                if (want) {
+                    const unsigned long long rank = __popcll(mask & ((1ull << lane) - 1ull));
+                    const unsigned long long c = base + rank;
+                    if (c < (unsigned long long)io.n) {
+                        S.cell = (int64_t)c;
+                        const int64_t i = S.cell;
+#pragma unroll
+                        for (int k = 0; k < K; k++) S.z(0, k) = io.Y[k * io.ldY + i];
+                        S.z(0, K) = io.T[i];
+                        S.p = io.p[i];
+                        S.nst = S.nfe = S.nje = S.nni = S.netf = S.ncfn = 0;
+#pragma unroll
+                        for (int j = 0; j < kQmax + 2; j++) S.tau[j] = 0.0;
+                        S.s_eval = 0.0;
+                        S.need_J = false;
+                        S.phase = F0;
+                    } else {
+                        S.phase = DONE;
+                    }
+                }
+            }
+        }
+        if (__ballot(S.phase != DONE) == 0ull) break;
+
+        // ---- Jacobian + LU (the single call site) ----
+        if (S.need_J && S.phase == NEWTON) {
+            double yj[N];
+#pragma unroll
+            for (int i = 0; i < N; i++) yj[i] = S.z(0, i);
+            mech.jac(S.p, yj, S.M);
+#pragma unroll
+            for (int r = 0; r < N; r++)
+#pragma unroll
+                for (int c = 0; c < N; c++) S.M[r * N + c] = (r == c ? 1.0 : 0.0) - S.gamma * S.M[r * N + c];
+            S.nje++;
+            const bool ok = lu_factor<N>(S.M, S.piv);
+            S.gamma_M = S.gamma;
+            S.nst_M = S.nst;
+            S.crate = 1.0;
+            S.have_M = ok;
+            S.jcur = true;
+            S.force_M = false;
+            S.need_J = false;
+            if (!ok) S.phase = LUFAIL;
+        }
+
+        // ---- right-hand side (the single call site) ----
+        if (S.phase == F0 || S.phase == H0 || S.phase == NEWTON || S.phase == RESTART) {
+            double yv[N];
+            const bool h0 = (S.phase == H0);
+#pragma unroll
+            for (int i = 0; i < N; i++) yv[i] = S.z(0, i) + S.s_eval * (h0 ? S.ehat[i] : S.e[i]);
+            mech.rhs(S.p, yv, S.fy);
+            S.nfe++;
+        }
+
+        // ---- bookkeeping ----
+        if (S.phase == NEWTON) {
+            bool conv = false, fail = false;
+            if (!finite_vec<N>(S.fy)) {
+                fail = true;
+            } else {
+                double d[N];
+                const double inv_l1 = 1.0 / S.l[1];
+#pragma unroll
+                for (int i = 0; i < N; i++) d[i] = -(S.e[i] - S.gamma * S.fy[i] + S.z(1, i) * inv_l1);
+                lu_solve<N>(S.M, S.piv, d);
+                if (S.gamma != S.gamma_M) {
+                    const double s = 2.0 / (1.0 + S.gamma / S.gamma_M);
+#pragma unroll
+                    for (int i = 0; i < N; i++) d[i] *= s;
+                }
+                const double dl = wrms_norm<N>(d, S.w);
+#pragma unroll
+                for (int i = 0; i < N; i++) S.e[i] += d[i];
+                S.nni++;
+                if (S.it > 0) S.crate = fmax(kCrdown * S.crate, dl / S.del_old);
+                const double dcon = dl * fmin(S.crate, 1.0) * S.Cq / kNlscoef;
+                if (dcon <= 1.0) {
+                    conv = true;
+                } else if ((S.it > 0 && dl > kRdiv * S.del_old) || S.it + 1 >= kMaxCor) {
+                    fail = true;
+                } else {
+                    S.del_old = dl;
+                    S.it++;
+                }
+            }
+            if (conv)
+                error_test(S, io);
+            else if (fail)
+                conv_fail(S, io);
+        } else if (S.phase == LUFAIL) {
+            conv_fail(S, io);
+        } else if (S.phase == F0) {
+            if (!finite_vec<N>(S.fy)) {
+                finish_cell(S, io, 4);
+            } else {
+#pragma unroll
+                for (int i = 0; i < N; i++) {
+                    S.ehat[i] = S.fy[i];   // keeps f(y0) until the first step
+                    S.w[i] = 1.0 / (io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
+                }
+                if (wrms_norm<N>(S.fy, S.w) == 0.0) {
+                    S.h = t_end;
+                    begin_integration(S, io);
+                } else {
+                    double hub = t_end;
+#pragma unroll
+                    for (int i = 0; i < N; i++) {
+                        const double lim = 0.1 * fabs(S.z(0, i)) + 1.0 / S.w[i];
+                        if (fabs(S.fy[i]) * hub > lim) hub = lim / fabs(S.fy[i]);
+                    }
+                    S.hub = hub;
+                    S.hg = hub;
+                    S.s_eval = hub;
+                    S.h0_it = 0;
+                    S.phase = H0;
+                }
+            }
+        } else if (S.phase == H0) {
+            bool done = false;
+            if (!finite_vec<N>(S.fy)) {
+                S.hg *= 0.1;
+            } else {
+                double dv[N];
+#pragma unroll
+                for (int i = 0; i < N; i++) dv[i] = (S.fy[i] - S.ehat[i]) / S.hg;
+                const double ydd = wrms_norm<N>(dv, S.w);
+                double hnew = ydd > 0.0 ? sqrt(2.0 / ydd) : S.hub;
+                if (hnew > S.hub) hnew = S.hub;
+                const double ratio = hnew / S.hg;
+                S.hg = hnew;
+                done = (ratio >= 0.5 && ratio <= 2.0);
+            }
+            S.h0_it++;
+            if (done || S.h0_it >= kH0Iters) {
+                S.h = 0.5 * S.hg;
+                if (S.h > t_end) S.h = t_end;
+                begin_integration(S, io);
+            } else {
+                S.s_eval = S.hg;
+            }
+        } else if (S.phase == RESTART) {
+            if (!finite_vec<N>(S.fy)) {
+                finish_cell(S, io, 4);
+            } else {
+#pragma unroll
+                for (int i = 0; i < N; i++) S.z(1, i) = S.h * S.fy[i];
+#pragma unroll
+                for (int j = 0; j < kQmax + 2; j++) S.tau[j] = 0.0;
+                S.qwait = 2;
+                S.ehat_ok = false;
+                begin_attempt(S, io);
+            }
+        }
+    }
+}
+
+template <class Mech>
+__global__ void __launch_bounds__(64) bdf_queue_kernel(Mech mech, double *__restrict__ T,
+                                                       const double *__restrict__ p,
+                                                       double *__restrict__ Y, int64_t ldY,
+                                                       int64_t n, double dt, BdfParams prm,
+                                                       int32_t *__restrict__ status,
+                                                       int32_t *__restrict__ counters,
+                                                       unsigned long long *__restrict__ queue)
+{
+    __shared__ double nord[(kQmax + 1) * (Mech::K + 1) * 64];
+    CellIO io{T, p, Y, ldY, n, status, counters, &prm};
+    run_lanes(mech, io, dt, queue, nord);
+}
+
+template <class Mech>
+__global__ void __launch_bounds__(256) rhs_eval_kernel(Mech mech, const double *__restrict__ T,
+                                                       const double *__restrict__ p,
+                                                       const double *__restrict__ Y, int64_t ldY,
+                                                       int64_t n, double *__restrict__ F, int64_t ldF)
+{
+    constexpr int K = Mech::K;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double y[K + 1], f[K + 1];
+#pragma unroll
+    for (int k = 0; k < K; k++) y[k] = Y[k * ldY + i];
+    y[K] = T[i];
+    mech.rhs(p[i], y, f);
+#pragma unroll
+    for (int k = 0; k <= K; k++) F[k * ldF + i] = f[k];
+}
+
+template <class Mech>
+__global__ void __launch_bounds__(64) jac_eval_kernel(Mech mech, const double *__restrict__ T,
+                                                      const double *__restrict__ p,
+                                                      const double *__restrict__ Y, int64_t ldY,
+                                                      int64_t n, double *__restrict__ J, int64_t ldJ)
+{
+    constexpr int K = Mech::K;
+    constexpr int N = K + 1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double y[N], jac[N * N];
+#pragma unroll
+    for (int k = 0; k < K; k++) y[k] = Y[k * ldY + i];
+    y[K] = T[i];
+    mech.jac(p[i], y, jac);
+#pragma unroll
+    for (int k = 0; k < N * N; k++) J[k * ldJ + i] = jac[k];
+}
+
+__global__ void reset_queue_kernel(unsigned long long *queue);
+
+// Grid of the queue kernel: enough one-wave blocks to fill every CU at the
+// kernel's occupancy, never more lanes than cells.
+int queue_grid(const void *kernel, int64_t n);
+
+// Launchers of a mechanism-specialised functor (defined by generated code).
+typedef hipError_t (*gen_integrate_fn)(double *T, const double *p, double *Y, int64_t ldY,
+                                       int64_t n, double dt, const BdfParams &prm, int32_t *status,
+                                       int32_t *counters, unsigned long long *queue, hipStream_t s);
+typedef hipError_t (*gen_eval_fn)(const double *T, const double *p, const double *Y, int64_t ldY,
+                                  int64_t n, double *out, int64_t ld, hipStream_t s);
+
+struct GenEntry {
+    unsigned long long hash;
+    int K;
+    const char *tag;
+    gen_integrate_fn integrate;
+    gen_eval_fn rhs;
+    gen_eval_fn jac;
+};
+
+const GenEntry *gen_registry(int *count);
+
+#define CHEM_DECLARE_GEN_LAUNCHERS(TAG)                                                          \
+    hipError_t gen_integrate_##TAG(double *, const double *, double *, int64_t, int64_t, double,  \
+                                   const BdfParams &, int32_t *, int32_t *, unsigned long long *, \
+                                   hipStream_t);                                                  \
+    hipError_t gen_rhs_##TAG(const double *, const double *, const double *, int64_t, int64_t,    \
+                             double *, int64_t, hipStream_t);                                     \
+    hipError_t gen_jac_##TAG(const double *, const double *, const double *, int64_t, int64_t,    \
+                             double *, int64_t, hipStream_t);
+
+#define CHEM_DEFINE_GEN_LAUNCHERS(MECH, TAG)                                                      \
+    hipError_t gen_integrate_##TAG(double *T, const double *p, double *Y, int64_t ldY, int64_t n, \
+                                   double dt, const BdfParams &prm, int32_t *status,              \
+                                   int32_t *counters, unsigned long long *queue, hipStream_t s)   \
+    {                                                                                             \
+        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, queue);                    \
+        const int blocks = queue_grid((const void *)bdf_queue_kernel<MECH>, n);                   \
+        hipLaunchKernelGGL(bdf_queue_kernel<MECH>, dim3(blocks), dim3(64), 0, s, MECH{}, T, p, Y, \
+                           ldY, n, dt, prm, status, counters, queue);                             \
+        return hipGetLastError();                                                                 \
+    }                                                                                             \
+    hipError_t gen_rhs_##TAG(const double *T, const double *p, const double *Y, int64_t ldY,      \
+                             int64_t n, double *F, int64_t ldF, hipStream_t s)                    \
+    {                                                                                             \
+        hipLaunchKernelGGL(rhs_eval_kernel<MECH>, dim3((unsigned)((n + 255) / 256)), dim3(256),   \
+                           0, s, MECH{}, T, p, Y, ldY, n, F, ldF);                                \
+        return hipGetLastError();                                                                 \
+    }                                                                                             \
+    hipError_t gen_jac_##TAG(const double *T, const double *p, const double *Y, int64_t ldY,      \
+                             int64_t n, double *J, int64_t ldJ, hipStream_t s)                    \
+    {                                                                                             \
+        hipLaunchKernelGGL(jac_eval_kernel<MECH>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0,  \
+                           s, MECH{}, T, p, Y, ldY, n, J, ldJ);                                   \
+        return hipGetLastError();                                                                 \
+    }
+
+}  // namespace chem

@@ -5,12 +5,13 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <iterator>
 #include <sstream>
 #include <string>
 #include <vector>
 
 #include "../../include/chem.h"
-#include "chem_internal.h"
+#include "bdf_driver.h"
 
 namespace {
 
@@ -152,7 +153,25 @@ struct chem_mech_s {
     std::vector<double> W;
     chem::DevMechView view{};
     void *dev_block = nullptr;
+    unsigned long long *queues = nullptr;   // work-queue counters, one per in-flight call
+    unsigned next_queue = 0;
+    const chem::GenEntry *gen = nullptr;    // mechanism-specialised kernels, if compiled
+    std::string variant = "table";
 };
+
+namespace {
+constexpr int kQueues = 64;
+
+unsigned long long fnv1a64(const std::string &data)
+{
+    unsigned long long h = 0xCBF29CE484222325ull;
+    for (unsigned char c : data) {
+        h ^= c;
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+}  // namespace
 
 namespace {
 
@@ -210,6 +229,18 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     *out = nullptr;
     auto *m = new chem_mech_s();
     int rc = parse_mech(path, m->host);
+    if (rc == CHEM_OK) {
+        std::ifstream fb(path, std::ios::binary);
+        std::string bytes((std::istreambuf_iterator<char>(fb)), std::istreambuf_iterator<char>());
+        const unsigned long long h = fnv1a64(bytes);
+        int ng = 0;
+        const chem::GenEntry *reg = chem::gen_registry(&ng);
+        for (int i = 0; i < ng; i++)
+            if (reg[i].hash == h && reg[i].K == m->host.K) {
+                m->gen = &reg[i];
+                m->variant = std::string("specialised:") + reg[i].tag;
+            }
+    }
     if (rc != CHEM_OK) {
         delete m;
         return rc;
@@ -260,7 +291,8 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     const size_t off_w = (n_sp + 255) & ~size_t(255);
     const size_t off_iw = (off_w + n_w + 255) & ~size_t(255);
     const size_t off_rx = (off_iw + n_w + 255) & ~size_t(255);
-    const size_t total = off_rx + rx.size() * sizeof(chem::DevRxn);
+    const size_t off_q = (off_rx + rx.size() * sizeof(chem::DevRxn) + 255) & ~size_t(255);
+    const size_t total = off_q + kQueues * 256;
     int prev = 0;
     if ((rc = check_hip(hipGetDevice(&prev), "hipGetDevice")) != CHEM_OK) {
         delete m;
@@ -297,6 +329,7 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     m->view.W = (const double *)(blk + off_w);
     m->view.invW = (const double *)(blk + off_iw);
     m->view.rxn = (const chem::DevRxn *)(blk + off_rx);
+    m->queues = (unsigned long long *)(blk + off_q);
     *out = m;
     return CHEM_OK;
 }
@@ -323,6 +356,12 @@ int chem_mechanism_info(chem_mech m, int32_t *K, int32_t *R, int32_t *E, double 
     if (W)
         for (int k = 0; k < m->host.K; k++) W[k] = m->W[k];
     return CHEM_OK;
+}
+
+const char *chem_mechanism_variant(chem_mech m)
+{
+    if (!m) return "";
+    return m->variant.c_str();
 }
 
 static int check_state_args(chem_mech m, const double *T, const double *p, const double *Y,
@@ -359,12 +398,17 @@ int chem_integrate(chem_mech m, double *T, const double *p, double *Y, int64_t l
     if (n == 0) return CHEM_OK;
     if ((status && !is_device_ptr(status)) || (counters && !is_device_ptr(counters)))
         return fail(CHEM_EINVAL, "status and counters must be device pointers or NULL");
-    if (!chem::thread_kernel_supports(m->host.K))
+    if (!m->gen && !chem::thread_kernel_supports(m->host.K))
         return fail(CHEM_EUNSUP, "no integrator kernel is built for K = " + std::to_string(m->host.K));
     chem::BdfParams prm{o.rtol, o.atol, o.max_steps, 0};
-    return check_hip(chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status, counters,
-                                             64, (hipStream_t)stream),
-                     "integrator launch");
+    // each call takes its own queue counter (64 rotate), so that calls in
+    // flight on different streams do not share one
+    unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);
+    hipError_t e = m->gen ? m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue,
+                                              (hipStream_t)stream)
+                          : chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status,
+                                                    counters, queue, (hipStream_t)stream);
+    return check_hip(e, "integrator launch");
 }
 
 int chem_eval_rhs(chem_mech m, const double *T, const double *p, const double *Y, int64_t ldY,
@@ -373,6 +417,7 @@ int chem_eval_rhs(chem_mech m, const double *T, const double *p, const double *Y
     int rc = check_state_args(m, T, p, Y, ldY, n);
     if (rc != CHEM_OK || n == 0) return rc;
     if (ldF < n || !is_device_ptr(F)) return fail(CHEM_EINVAL, "F must be a device array with ldF >= ncells");
+    if (m->gen) return check_hip(m->gen->rhs(T, p, Y, ldY, n, F, ldF, (hipStream_t)stream), "rhs launch");
     if (!chem::thread_kernel_supports(m->host.K))
         return fail(CHEM_EUNSUP, "no kernel is built for K = " + std::to_string(m->host.K));
     return check_hip(chem::launch_rhs(m->view, T, p, Y, ldY, n, F, ldF, (hipStream_t)stream), "rhs launch");
@@ -384,6 +429,7 @@ int chem_eval_jacobian(chem_mech m, const double *T, const double *p, const doub
     int rc = check_state_args(m, T, p, Y, ldY, n);
     if (rc != CHEM_OK || n == 0) return rc;
     if (ldJ < n || !is_device_ptr(J)) return fail(CHEM_EINVAL, "J must be a device array with ldJ >= ncells");
+    if (m->gen) return check_hip(m->gen->jac(T, p, Y, ldY, n, J, ldJ, (hipStream_t)stream), "jacobian launch");
     if (!chem::thread_kernel_supports(m->host.K))
         return fail(CHEM_EUNSUP, "no kernel is built for K = " + std::to_string(m->host.K));
     return check_hip(chem::launch_jacobian(m->view, T, p, Y, ldY, n, J, ldJ, (hipStream_t)stream),
