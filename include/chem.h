@@ -65,7 +65,11 @@ typedef struct {
     int32_t precision;  /* 0 = FP64 throughout (only mode so far) */
     int32_t schedule;   /* -1 = library choice, 0 = one thread per cell */
     int32_t block;      /* threads per block, 0 = library choice */
-    int32_t reserved[8];
+    int32_t jac_batch;  /* one-thread-per-cell kernels: lanes of a wave that wait for
+                           a new Newton matrix before the Jacobian is evaluated
+                           (1..64; 0 = library choice).  Scheduling only: results
+                           do not depend on it. */
+    int32_t reserved[7];
 } chem_opts;
 
 /* Fill opts with the defaults above. */

@@ -22,12 +22,25 @@ namespace chem {
 // dense LU with row partial pivoting, registers, static indexing
 // ---------------------------------------------------------------------------
 
-// Factor in place; ties keep the upper row.  Pivot rows are recorded in a
-// packed 4-bit-per-column word pair (N <= 16) or an int array.
-template <int N>
-__device__ __forceinline__ bool lu_factor(double *M, int *piv)
+// A value the optimiser must treat as opaque: a per-lane row exchange written
+// as selects between such values cannot be folded back into a load through a
+// selected address (which would push the whole array out of registers).
+__device__ __forceinline__ double reg_value(double v)
 {
+    unsigned lo = (unsigned)__double_as_longlong(v);
+    unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(v) >> 32);
+    
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Factor in place; ties keep the upper row.  The pivot row of column k is
+// kept in bits 4k..4k+3 of one 64-bit word (N <= 16).
+template <int N>
+__device__ __forceinline__ bool lu_factor(double *M, unsigned long long &piv)
+{
+    static_assert(N <= 16, "packed pivots hold at most 16 rows");
     bool ok = true;
+    piv = 0ull;
 #pragma unroll
     for (int k = 0; k < N; k++) {
         int pk = k;
@@ -40,19 +53,21 @@ __device__ __forceinline__ bool lu_factor(double *M, int *piv)
                 pk = r;
             }
         }
-        piv[k] = pk;
+        piv |= (unsigned long long)pk << (4 * k);
         ok = ok && (best != 0.0);
         if (pk != k) {
 #pragma unroll
-            for (int r = k + 1; r < N; r++) {
-                if (pk == r) {
+            for (int c = 0; c < N; c++) {
+                const double mk = reg_value(M[k * N + c]);
+                double nk = mk;
 #pragma unroll
-                    for (int c = 0; c < N; c++) {
-                        const double t = M[k * N + c];
-                        M[k * N + c] = M[r * N + c];
-                        M[r * N + c] = t;
-                    }
+                for (int r = k + 1; r < N; r++) {
+                    const double mr = reg_value(M[r * N + c]);
+                    const bool sw = (pk == r);
+                    nk = sw ? mr : nk;
+                    M[r * N + c] = sw ? mk : mr;
                 }
+                M[k * N + c] = nk;
             }
         }
         const double inv = 1.0 / M[k * N + k];
@@ -68,21 +83,21 @@ __device__ __forceinline__ bool lu_factor(double *M, int *piv)
 }
 
 template <int N>
-__device__ __forceinline__ void lu_solve(const double *M, const int *piv, double *b)
+__device__ __forceinline__ void lu_solve(const double *M, unsigned long long piv, double *b)
 {
 #pragma unroll
     for (int k = 0; k < N; k++) {
-        const int pk = piv[k];
-        if (pk != k) {
+        const int pk = (int)((piv >> (4 * k)) & 15ull);
+        const double bk = reg_value(b[k]);
+        double nk = bk;
 #pragma unroll
-            for (int r = k + 1; r < N; r++) {
-                if (pk == r) {
-                    const double t = b[k];
-                    b[k] = b[r];
-                    b[r] = t;
-                }
-            }
+        for (int r = k + 1; r < N; r++) {
+            const double br = reg_value(b[r]);
+            const bool sw = (pk == r);
+            nk = sw ? br : nk;
+            b[r] = sw ? bk : br;
         }
+        b[k] = nk;
     }
 #pragma unroll
     for (int r = 1; r < N; r++)
@@ -125,6 +140,12 @@ enum Phase : int { FETCH = 0, F0 = 1, H0 = 2, NEWTON = 3, RESTART = 4, LUFAIL = 
 }  // namespace bdf
 
 template <int N>
+struct NordLds;
+
+template <int N>
+__device__ __forceinline__ double wrms_norm(const double *v, const NordLds<N> &z);
+
+template <int N>
 __device__ __forceinline__ double wrms_norm(const double *v, const double *w)
 {
     double s = 0.0;
@@ -154,25 +175,41 @@ __device__ __forceinline__ double factorial_d(int n)
     return f;
 }
 
-// Nordsieck array of one lane in LDS: element (j, i) of lane L at
-// lds[(j*N + i)*64 + L], so a wave's 64 lanes touch 64 consecutive doubles and
-// every static (j, i) is an immediate offset.
+// Per-lane arrays kept in LDS: element (j, i) of lane L at lds[(j*N + i)*64 + L],
+// so a wave's 64 lanes touch 64 consecutive doubles and every static (j, i)
+// is an immediate offset.  Rows 0..kQmax hold the Nordsieck array, row
+// kQmax+1 the scaled correction of the previous step (order-raise estimate),
+// row kQmax+2 the error weights.
 template <int N>
 struct NordLds {
     double *base;   // lds + lane
     __device__ __forceinline__ double &operator()(int j, int i) const { return base[(j * N + i) * 64]; }
 };
+constexpr int kLdsRows = kQmax + 3;
+
+template <int N>
+__device__ __forceinline__ double wrms_norm(const double *v, const NordLds<N> &z)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        const double t = v[i] * z(kQmax + 2, i);
+        s += t * t;
+    }
+    return sqrt(s * (1.0 / N));
+}
+constexpr int kEhatRow = kQmax + 1;
+constexpr int kWeightRow = kQmax + 2;   // error weights 1/(rtol |y_n| + atol)
 
 // Per-lane integrator state.  Every array is indexed statically.
 template <int N>
 struct LaneState {
-    NordLds<N> z;               // Nordsieck array (LDS)
+    NordLds<N> z;               // Nordsieck array and previous scaled correction (LDS)
     double M[N * N];            // LU factors of I - gamma_M J
-    int piv[N];
-    double w[N], e[N], ehat[N], fy[N];
+    unsigned long long piv;     // packed pivot rows
+    double e[N], fy[N];
     double tau[kQmax + 2];      // past step sizes, tau[1] most recent
-    double xi[kQmax + 2], l[kQmax + 1];
-    double p, t, h, t_end, gamma, gamma_M, Cq, crate, del_old, dsm, ehat_h, s_eval, hg, hub;
+    double p, t, h, t_end, gamma, gamma_M, Cq, inv_l1, crate, del_old, dsm, ehat_h, s_eval, hg, hub;
     int64_t cell;
     int phase, q, qwait, nst_M, it, nef, ncf, h0_it;
     bool have_M, ehat_ok, force_M, last, jcur, need_J;
@@ -214,6 +251,28 @@ __device__ __forceinline__ void nord_rescale(LaneState<N> &S, double eta)
 #pragma unroll
             for (int i = 0; i < N; i++) S.z(j, i) *= f;
     }
+}
+
+// Step coefficients from the history: xi_i = (h + tau_1 + ... + tau_{i-1}) / h,
+// l = coefficients of prod_{i=1..q} (1 + x / xi_i).
+template <int N>
+__device__ __forceinline__ void step_coeffs(const LaneState<N> &S, double *xi, double *l)
+{
+    double s = S.h;
+    xi[1] = 1.0;
+#pragma unroll
+    for (int i = 2; i <= kQmax + 1; i++) {
+        s += S.tau[i - 1];
+        xi[i] = s / S.h;
+    }
+    l[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= kQmax; j++) l[j] = 0.0;
+#pragma unroll
+    for (int i = 1; i <= kQmax; i++)
+        if (i <= S.q)
+#pragma unroll
+            for (int j = i; j >= 1; j--) l[j] += l[j - 1] / xi[i];
 }
 
 // xi_{q+1} = (h + tau_1 + ... + tau_q) / h, summed with the order as a guard
@@ -273,31 +332,15 @@ __device__ __forceinline__ void begin_attempt(LaneState<N> &S, const CellIO &io)
         return;
     }
     nord_predict(S);
-    {
-        double s = S.h;
-        S.xi[1] = 1.0;
-#pragma unroll
-        for (int i = 2; i <= kQmax + 1; i++) {
-            s += S.tau[i - 1];
-            S.xi[i] = s / S.h;
-        }
-        S.l[0] = 1.0;
-#pragma unroll
-        for (int j = 1; j <= kQmax; j++) S.l[j] = 0.0;
-#pragma unroll
-        for (int i = 1; i <= kQmax; i++)
-            if (i <= S.q)
-#pragma unroll
-                for (int j = i; j >= 1; j--) S.l[j] += S.l[j - 1] / S.xi[i];
-    }
-    S.gamma = S.h / S.l[1];
-    S.Cq = 1.0 / (1.0 + S.l[1] * xi_q1(S));
+    double xi[kQmax + 2], l[kQmax + 1];
+    step_coeffs(S, xi, l);
+    S.gamma = S.h / l[1];
+    S.inv_l1 = 1.0 / l[1];
+    S.Cq = 1.0 / (1.0 + l[1] * xi_q1(S));
     S.jcur = false;
     S.need_J = !S.have_M || S.force_M || S.nst >= S.nst_M + bdf::kMsbp ||
                fabs(S.gamma / S.gamma_M - 1.0) > bdf::kDgmax;
-#pragma unroll
-    for (int i = 0; i < N; i++) S.e[i] = 0.0;
-    S.it = 0;
+    S.it = 0;   // the accumulated correction e starts at 0 (set after the first solve)
     S.del_old = 0.0;
     S.s_eval = 1.0;
     S.phase = bdf::NEWTON;
@@ -317,7 +360,7 @@ __device__ __forceinline__ void begin_step(LaneState<N> &S, const CellIO &io)
         S.last = true;
     }
 #pragma unroll
-    for (int i = 0; i < N; i++) S.w[i] = 1.0 / (io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
+    for (int i = 0; i < N; i++) S.z(kWeightRow, i) = 1.0 / (io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
     S.nef = 0;
     S.ncf = 0;
     S.force_M = false;
@@ -327,10 +370,10 @@ __device__ __forceinline__ void begin_step(LaneState<N> &S, const CellIO &io)
 template <int N>
 __device__ __forceinline__ void begin_integration(LaneState<N> &S, const CellIO &io)
 {
-    // S.h set; S.ehat holds f(y0); z[0] holds y0
+    // S.h set; S.e holds f(y0); z[0] holds y0
     S.q = 1;
 #pragma unroll
-    for (int i = 0; i < N; i++) S.z(1, i) = S.h * S.ehat[i];
+    for (int i = 0; i < N; i++) S.z(1, i) = S.h * S.e[i];
     S.qwait = 2;
     S.have_M = false;
     S.ehat_ok = false;
@@ -368,12 +411,14 @@ __device__ __forceinline__ void select_next(LaneState<N> &S)
     using namespace bdf;
     const int q = S.q;
     const double h_done = S.h;
+    double xi[kQmax + 2], l[kQmax + 1];
+    step_coeffs(S, xi, l);
     double prod_q = 1.0;
 #pragma unroll
     for (int i = 1; i <= kQmax; i++)
-        if (i <= q) prod_q *= S.xi[i];
+        if (i <= q) prod_q *= xi[i];
     const double x1 = xi_q1(S);
-    const double gfac = prod_q * (1.0 / S.l[1] + x1) / factorial_d(q + 1);
+    const double gfac = prod_q * (1.0 / l[1] + x1) / factorial_d(q + 1);
     double ehat_new[N];
 #pragma unroll
     for (int i = 0; i < N; i++) ehat_new[i] = S.e[i] / gfac;
@@ -397,25 +442,25 @@ __device__ __forceinline__ void select_next(LaneState<N> &S)
 #pragma unroll
                 for (int i = 1; i < kQmax; i++)
                     if (i <= q - 1) {
-                        prod *= S.xi[i];
-                        l1 += 1.0 / S.xi[i];
+                        prod *= xi[i];
+                        l1 += 1.0 / xi[i];
                     }
-                const double Em = wrms_norm<N>(zq, S.w) * prod / l1;
+                const double Em = wrms_norm<N>(zq, S.z) * prod / l1;
                 eta_m = 1.0 / (pow(kBiasQm1 * Em, 1.0 / q) + kAddon);
             }
             if (q < kQmax && S.ehat_ok) {
                 const double rr = pow(h_done / S.ehat_h, q + 1);
                 double dv[N];
 #pragma unroll
-                for (int i = 0; i < N; i++) dv[i] = ehat_new[i] - S.ehat[i] * rr;
+                for (int i = 0; i < N; i++) dv[i] = ehat_new[i] - S.z(kEhatRow, i) * rr;
                 double prod = 1.0, l1 = 0.0;
 #pragma unroll
                 for (int i = 1; i <= kQmax; i++)
                     if (i <= q + 1) {
-                        prod *= S.xi[i];
-                        l1 += 1.0 / S.xi[i];
+                        prod *= xi[i];
+                        l1 += 1.0 / xi[i];
                     }
-                const double Ep = wrms_norm<N>(dv, S.w) * prod / (factorial_d(q + 2) * l1);
+                const double Ep = wrms_norm<N>(dv, S.z) * prod / (factorial_d(q + 2) * l1);
                 eta_p = 1.0 / (pow(kBiasQp1 * Ep, 1.0 / (q + 2)) + kAddon);
             }
             if (eta_m > eta && eta_m >= eta_p) {
@@ -444,7 +489,7 @@ __device__ __forceinline__ void select_next(LaneState<N> &S)
             if (i <= q - 1)
 #pragma unroll
                 for (int j = kQmax; j >= 1; j--)
-                    if (j <= i + 1) d[j] = d[j - 1] + S.xi[i] * d[j];
+                    if (j <= i + 1) d[j] = d[j - 1] + xi[i] * d[j];
         double zq[N];
 #pragma unroll
         for (int i = 0; i < N; i++) zq[i] = 0.0;
@@ -473,13 +518,13 @@ __device__ __forceinline__ void select_next(LaneState<N> &S)
         for (int j = 1; j <= kQmax; j++)
             if (j <= q + 1)
 #pragma unroll
-                for (int i = 0; i < N; i++) S.z(j, i) += S.e[i] * S.l[j - 1] * inv;
+                for (int i = 0; i < N; i++) S.z(j, i) += S.e[i] * l[j - 1] * inv;
         S.q = qnew;
         S.qwait = qnew + 1;
         S.ehat_ok = false;
     } else {
 #pragma unroll
-        for (int i = 0; i < N; i++) S.ehat[i] = ehat_new[i];
+        for (int i = 0; i < N; i++) S.z(kEhatRow, i) = ehat_new[i];
         S.ehat_h = h_done;
         S.ehat_ok = true;
     }
@@ -497,7 +542,7 @@ template <int N>
 __device__ __forceinline__ void error_test(LaneState<N> &S, const CellIO &io)
 {
     using namespace bdf;
-    S.dsm = S.Cq * wrms_norm<N>(S.e, S.w);
+    S.dsm = S.Cq * wrms_norm<N>(S.e, S.z);
     if (S.dsm > 1.0) {
         nord_restore(S);
         S.netf++;
@@ -521,11 +566,15 @@ __device__ __forceinline__ void error_test(LaneState<N> &S, const CellIO &io)
         begin_attempt(S, io);
         return;
     }
+    {
+        double xi[kQmax + 2], l[kQmax + 1];
+        step_coeffs(S, xi, l);
 #pragma unroll
-    for (int j = 0; j <= kQmax; j++)
-        if (j <= S.q)
+        for (int j = 0; j <= kQmax; j++)
+            if (j <= S.q)
 #pragma unroll
-            for (int i = 0; i < N; i++) S.z(j, i) += S.l[j] * S.e[i];
+                for (int i = 0; i < N; i++) S.z(j, i) += l[j] * S.e[i];
+    }
     S.t = S.last ? S.t_end : S.t + S.h;
     S.nst++;
     if (S.t >= S.t_end) {
@@ -584,8 +633,19 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
         }
         if (__ballot(S.phase != DONE) == 0ull) break;
 
-        // ---- Jacobian + LU (the single call site) ----
-        if (S.need_J && S.phase == NEWTON) {
+        // ---- Jacobian + LU (the single call site), batched across the wave:
+        // a lane that needs a new Newton matrix waits until jac_batch lanes
+        // wait too, or until no lane can progress without one.  This moves
+        // work in time only; every lane takes the same decisions. ----
+        const bool waitJ = S.need_J && S.phase == NEWTON;
+        const unsigned long long mJ = __ballot(waitJ);
+        bool runJ = false;
+        if (mJ) {
+            const bool progress = ((S.phase == F0 || S.phase == H0 || S.phase == NEWTON ||
+                                    S.phase == RESTART) && !waitJ) || S.phase == LUFAIL;
+            runJ = __popcll(mJ) >= io.prm->jac_batch || __ballot(progress) == 0ull;
+        }
+        if (runJ && waitJ) {
             double yj[N];
 #pragma unroll
             for (int i = 0; i < N; i++) yj[i] = S.z(0, i);
@@ -606,35 +666,41 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
             if (!ok) S.phase = LUFAIL;
         }
 
+        const bool waiting = S.need_J && S.phase == NEWTON;
+
         // ---- right-hand side (the single call site) ----
-        if (S.phase == F0 || S.phase == H0 || S.phase == NEWTON || S.phase == RESTART) {
+        if ((S.phase == F0 || S.phase == H0 || S.phase == NEWTON || S.phase == RESTART) && !waiting) {
             double yv[N];
-            const bool h0 = (S.phase == H0);
+            // prediction itself (first Newton iteration, F0, RESTART), or the
+            // prediction plus s_eval * e (later iterations; H0 with e = f(y0))
+            const bool use_e = (S.phase == H0) || (S.phase == NEWTON && S.it > 0);
 #pragma unroll
-            for (int i = 0; i < N; i++) yv[i] = S.z(0, i) + S.s_eval * (h0 ? S.ehat[i] : S.e[i]);
+            for (int i = 0; i < N; i++) yv[i] = use_e ? S.z(0, i) + S.s_eval * S.e[i] : S.z(0, i);
             mech.rhs(S.p, yv, S.fy);
             S.nfe++;
         }
 
         // ---- bookkeeping ----
-        if (S.phase == NEWTON) {
+        if (S.phase == NEWTON && !waiting) {
             bool conv = false, fail = false;
             if (!finite_vec<N>(S.fy)) {
                 fail = true;
             } else {
                 double d[N];
-                const double inv_l1 = 1.0 / S.l[1];
+                const double inv_l1 = S.inv_l1;
+                const bool first = (S.it == 0);
 #pragma unroll
-                for (int i = 0; i < N; i++) d[i] = -(S.e[i] - S.gamma * S.fy[i] + S.z(1, i) * inv_l1);
+                for (int i = 0; i < N; i++)
+                    d[i] = -((first ? 0.0 : S.e[i]) - S.gamma * S.fy[i] + S.z(1, i) * inv_l1);
                 lu_solve<N>(S.M, S.piv, d);
                 if (S.gamma != S.gamma_M) {
                     const double s = 2.0 / (1.0 + S.gamma / S.gamma_M);
 #pragma unroll
                     for (int i = 0; i < N; i++) d[i] *= s;
                 }
-                const double dl = wrms_norm<N>(d, S.w);
+                const double dl = wrms_norm<N>(d, S.z);
 #pragma unroll
-                for (int i = 0; i < N; i++) S.e[i] += d[i];
+                for (int i = 0; i < N; i++) S.e[i] = first ? d[i] : S.e[i] + d[i];
                 S.nni++;
                 if (S.it > 0) S.crate = fmax(kCrdown * S.crate, dl / S.del_old);
                 const double dcon = dl * fmin(S.crate, 1.0) * S.Cq / kNlscoef;
@@ -659,17 +725,17 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
             } else {
 #pragma unroll
                 for (int i = 0; i < N; i++) {
-                    S.ehat[i] = S.fy[i];   // keeps f(y0) until the first step
-                    S.w[i] = 1.0 / (io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
+                    S.e[i] = S.fy[i];   // e keeps f(y0) until the first step
+                    S.z(kWeightRow, i) = 1.0 / (io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
                 }
-                if (wrms_norm<N>(S.fy, S.w) == 0.0) {
+                if (wrms_norm<N>(S.fy, S.z) == 0.0) {
                     S.h = t_end;
                     begin_integration(S, io);
                 } else {
                     double hub = t_end;
 #pragma unroll
                     for (int i = 0; i < N; i++) {
-                        const double lim = 0.1 * fabs(S.z(0, i)) + 1.0 / S.w[i];
+                        const double lim = 0.1 * fabs(S.z(0, i)) + 1.0 / S.z(kWeightRow, i);
                         if (fabs(S.fy[i]) * hub > lim) hub = lim / fabs(S.fy[i]);
                     }
                     S.hub = hub;
@@ -686,8 +752,8 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
             } else {
                 double dv[N];
 #pragma unroll
-                for (int i = 0; i < N; i++) dv[i] = (S.fy[i] - S.ehat[i]) / S.hg;
-                const double ydd = wrms_norm<N>(dv, S.w);
+                for (int i = 0; i < N; i++) dv[i] = (S.fy[i] - S.e[i]) / S.hg;
+                const double ydd = wrms_norm<N>(dv, S.z);
                 double hnew = ydd > 0.0 ? sqrt(2.0 / ydd) : S.hub;
                 if (hnew > S.hub) hnew = S.hub;
                 const double ratio = hnew / S.hg;
@@ -727,7 +793,7 @@ __global__ void __launch_bounds__(64) bdf_queue_kernel(Mech mech, double *__rest
                                                        int32_t *__restrict__ counters,
                                                        unsigned long long *__restrict__ queue)
 {
-    __shared__ double nord[(kQmax + 1) * (Mech::K + 1) * 64];
+    __shared__ double nord[kLdsRows * (Mech::K + 1) * 64];
     CellIO io{T, p, Y, ldY, n, status, counters, &prm};
     run_lanes(mech, io, dt, queue, nord);
 }

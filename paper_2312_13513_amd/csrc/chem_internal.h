@@ -44,7 +44,7 @@ struct DevMechView {
 struct BdfParams {
     double rtol, atol;
     int32_t max_steps;
-    int32_t pad;
+    int32_t jac_batch;   // lanes of a wave that wait before a Jacobian is evaluated
 };
 
 // Launchers of the table-driven kernels.  Return hipError_t of the launch.

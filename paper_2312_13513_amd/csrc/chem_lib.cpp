@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/chem.h"
+#include "chem.h"
 #include "bdf_driver.h"
 
 namespace {
@@ -400,7 +400,8 @@ int chem_integrate(chem_mech m, double *T, const double *p, double *Y, int64_t l
         return fail(CHEM_EINVAL, "status and counters must be device pointers or NULL");
     if (!m->gen && !chem::thread_kernel_supports(m->host.K))
         return fail(CHEM_EUNSUP, "no integrator kernel is built for K = " + std::to_string(m->host.K));
-    chem::BdfParams prm{o.rtol, o.atol, o.max_steps, 0};
+    if (o.jac_batch < 0 || o.jac_batch > 64) return fail(CHEM_EINVAL, "jac_batch must be in 0..64");
+    chem::BdfParams prm{o.rtol, o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16};
     // each call takes its own queue counter (64 rotate), so that calls in
     // flight on different streams do not share one
     unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);
