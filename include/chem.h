@@ -62,8 +62,17 @@ typedef struct {
     double rtol;        /* relative tolerance (default 1e-8) */
     double atol;        /* absolute tolerance, all components (default 1e-12) */
     int32_t max_steps;  /* accepted steps per cell per call (default 20000) */
-    int32_t precision;  /* 0 = FP64 throughout (only mode so far) */
-    int32_t schedule;   /* -1 = library choice, 0 = one thread per cell */
+    int32_t precision;  /* 0 = FP64 throughout; 1 = Jacobian, Newton matrix, LU
+                           factors and triangular solves in FP32, while residuals,
+                           state, norms, error control and equilibrium constants
+                           stay FP64 (wave schedule only; results then differ
+                           from FP64 at the level of the integration tolerance) */
+    int32_t schedule;   /* -1 = library choice (one thread per cell when such a
+                           kernel exists and precision is 0, else one wave per
+                           cell), 0 = one thread per cell (K <= 9 table kernel or
+                           a compiled-in mechanism), 1 = one 64-lane wave per
+                           cell (any K <= 63).  CHEM_EUNSUP when the chosen
+                           schedule cannot serve the mechanism or precision. */
     int32_t block;      /* threads per block, 0 = library choice */
     int32_t jac_batch;  /* one-thread-per-cell kernels: lanes of a wave that wait for
                            a new Newton matrix before the Jacobian is evaluated

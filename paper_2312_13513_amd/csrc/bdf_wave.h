@@ -1,0 +1,24 @@
+// Wave-per-cell integrator (bdf_wave.hip): tables and launcher.
+#pragma once
+
+#include "chem_internal.h"
+
+namespace chem {
+
+// For each species k, the reactions with a non-zero net coefficient, in
+// increasing reaction order: entries inc[inc_off[k] .. inc_off[k+1]) hold
+// (reaction index, net coefficient).
+struct WaveTables {
+    const int *inc_off;
+    const int2 *inc;
+};
+
+// Padded row count of the wave kernel for N unknowns (0 = unsupported).
+int wave_kernel_rows(int N);
+
+hipError_t launch_bdf_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
+                           double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
+                           int32_t *status, int32_t *counters, unsigned long long *queue,
+                           double *qscratch, int max_waves, bool fp32_lu, hipStream_t s);
+
+}  // namespace chem

@@ -1,0 +1,774 @@
+// Wave-per-cell BDF integrator for larger mechanisms on gfx950.
+//
+// One 64-lane wave owns one cell at a time and takes the next from a work
+// queue.  Lane i owns component i of every state vector (Nordsieck column,
+// correction, weights) and row i of the Newton matrix, in registers; lanes
+// cooperate on the right-hand side (lane k: thermo of species k; lane j:
+// reactions j, j+64, ...) through LDS.  Sums over reactions are gathered by
+// the owning species lane in a fixed order, so results do not depend on
+// timing.  Control flow is uniform across the wave: every decision of the
+// integrator contract (the same as the one-thread-per-cell driver and the CPU
+// oracle) is taken once per cell, so cells of very different stiffness do not
+// hold each other back.
+//
+// NP is the padded row count (a compile-time bound on N = K+1 <= 64).  LT is
+// the type of the Jacobian, the Newton matrix, its LU factors and the
+// triangular solves: double (plain FP64) or float (mixed precision: those in
+// FP32; residuals, state, norms, error control and the equilibrium constants
+// in FP64, so that the Newton iteration restores the accuracy).
+
+#include "bdf_driver.h"
+#include "bdf_wave.h"
+
+namespace chem {
+namespace {
+
+constexpr int kWaveLanes = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// value of lane src (src wave-uniform), for every lane regardless of EXEC
+__device__ __forceinline__ double lane_value(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+// Lane holding the largest |v| among candidates; ties go to the smallest pos.
+__device__ __forceinline__ int wave_argmax(double v, bool cand, int pos)
+{
+    double a = cand ? fabs(v) : -1.0;
+    int key = cand ? pos : (1 << 30);
+    int idx = lane_id();
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double oa = __shfl_xor(a, off);
+        const int ok = __shfl_xor(key, off);
+        const int oi = __shfl_xor(idx, off);
+        if (oa > a || (oa == a && ok < key)) {
+            a = oa;
+            key = ok;
+            idx = oi;
+        }
+    }
+    return uniform(idx);
+}
+
+template <int NP, typename LT>
+struct WaveLds {
+    double C[kWaveLanes + 1], g[kWaveLanes + 1], h[kWaveLanes + 1];
+    LT row[NP][NP + 2];   // Jacobian rows; column NP+1 collects sentinel slots
+};
+
+// Species data of this lane, loaded once per kernel.
+struct SpeciesLane {
+    double a[kRangeLen];   // NASA block for the lane's species (single range)
+    double a_hi[kRangeLen];
+    double Tmid;
+    double W, invW;
+};
+
+__device__ __forceinline__ void lane_thermo(const SpeciesLane &s, bool two_range, double T,
+                                            double invT, double lnT, double &cp, double &h,
+                                            double &g, double &dcp)
+{
+    double a[kRangeLen];
+    const bool low = !two_range || T < s.Tmid;
+#pragma unroll
+    for (int j = 0; j < kRangeLen; j++) a[j] = low ? s.a[j] : s.a_hi[j];
+    cp = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+    h = a[0] + T * (a[7] + T * (a[8] + T * (a[9] + T * a[10]))) + a[5] * invT;
+    g = h - (a[0] * lnT + T * (a[1] + T * (a[11] + T * (a[12] + T * a[13]))) + a[6]);
+    dcp = a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + T * 4.0 * a[4]));
+}
+
+// f(y): each lane passes its component yi and receives fi.
+template <int NP, typename LT>
+__device__ double wave_rhs(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT> &L,
+                           const SpeciesLane &sp, int K, double p, double yi, double *qbuf)
+{
+    const int lane = lane_id();
+    const double T = lane_value(yi, K);
+    const double invT = 1.0 / T;
+    const double lnT = log(T);
+    double cpk = 0.0, hk = 0.0, gk = 0.0, dcpk = 0.0;
+    if (lane < K) lane_thermo(sp, m.two_range, T, invT, lnT, cpk, hk, gk, dcpk);
+    const double sumYW = wave_sum(lane < K ? yi * sp.invW : 0.0);
+    const double rho = p / (kRu * T * sumYW);
+    const double cpm = kRu * wave_sum(lane < K ? yi * cpk * sp.invW : 0.0);
+    if (lane < K) {
+        L.C[lane] = rho * yi * sp.invW;
+        L.g[lane] = gk;
+    } else if (lane == K) {
+        L.C[K] = 1.0;
+        L.g[K] = 0.0;
+    }
+    __syncthreads();
+    const double ln_c0 = log(kPstd / kRu) - lnT;
+    for (int r = lane; r < m.R; r += kWaveLanes) {
+        const DevRxn x = m.rxn[r];
+        const double lnkf = x.lnA + x.b * lnT - x.Ea_R * invT;
+        const double dg = L.g[x.p0] + L.g[x.p1] - L.g[x.r0] - L.g[x.r1];
+        const double lnkr = lnkf + dg - x.dnu * ln_c0;
+        qbuf[r] = exp(lnkf) * L.C[x.r0] * L.C[x.r1] - exp(lnkr) * L.C[x.p0] * L.C[x.p1];
+    }
+    __syncthreads();
+    double wk = 0.0;
+    if (lane < K) {
+        const int b = wt.inc_off[lane], e = wt.inc_off[lane + 1];
+        for (int j = b; j < e; j++) {
+            const int2 ent = wt.inc[j];
+            wk += (double)ent.y * qbuf[ent.x];
+        }
+    }
+    const double heat = wave_sum(lane < K ? hk * wk : 0.0);
+    __syncthreads();
+    if (lane < K) return sp.W * wk / rho;
+    if (lane == K) return -(kRu * T) * heat / (rho * cpm);
+    return 0.0;
+}
+
+// Row `lane` of M = I - gamma J at the state yi.
+template <int NP, typename LT>
+__device__ void wave_newton_matrix(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT> &L,
+                                   const SpeciesLane &sp, int K, double p, double yi, double gamma,
+                                   double *qbuf, LT *Mrow)
+{
+    const int lane = lane_id();
+    const int N = K + 1;
+    const double T = lane_value(yi, K);
+    const double invT = 1.0 / T;
+    const double lnT = log(T);
+    double cpk = 0.0, hk = 0.0, gk = 0.0, dcpk = 0.0;
+    if (lane < K) lane_thermo(sp, m.two_range, T, invT, lnT, cpk, hk, gk, dcpk);
+    const double sumYW = wave_sum(lane < K ? yi * sp.invW : 0.0);
+    const double wbar = 1.0 / sumYW;
+    const double rho = p * wbar / (kRu * T);
+    const double cpm = kRu * wave_sum(lane < K ? yi * cpk * sp.invW : 0.0);
+    const double dcpm = kRu * wave_sum(lane < K ? yi * dcpk * sp.invW : 0.0);
+    if (lane < K) {
+        L.C[lane] = rho * yi * sp.invW;
+        L.g[lane] = gk;
+        L.h[lane] = hk;
+    } else if (lane == K) {
+        L.C[K] = 1.0;
+        L.g[K] = 0.0;
+        L.h[K] = 0.0;
+    }
+    if (lane < N)
+#pragma unroll
+        for (int c = 0; c < NP + 2; c++) L.row[lane][c] = (LT)0;
+    __syncthreads();
+    const int R = m.R;
+    double *qh = qbuf + R, *dqT = qbuf + 2 * R, *dq = qbuf + 3 * R;
+    const double ln_c0 = log(kPstd / kRu) - lnT;
+    for (int r = lane; r < R; r += kWaveLanes) {
+        const DevRxn x = m.rxn[r];
+        const double lnkf = x.lnA + x.b * lnT - x.Ea_R * invT;
+        const double dg = L.g[x.p0] + L.g[x.p1] - L.g[x.r0] - L.g[x.r1];
+        const double dh = L.h[x.p0] + L.h[x.p1] - L.h[x.r0] - L.h[x.r1];
+        const double lnkr = lnkf + dg - x.dnu * ln_c0;
+        const double kf = exp(lnkf), kr = exp(lnkr);
+        const double cr0 = L.C[x.r0], cr1 = L.C[x.r1], cp0 = L.C[x.p0], cp1 = L.C[x.p1];
+        const double fwd = kf * cr0 * cr1, rev = kr * cp0 * cp1;
+        const double mf = (x.r1 != K) ? 2.0 : 1.0, mr = (x.p1 != K) ? 2.0 : 1.0;
+        const double dlnkf = (x.b + x.Ea_R * invT) * invT;
+        const double dlnkr = dlnkf - (dh - x.dnu) * invT;
+        qbuf[r] = fwd - rev;
+        qh[r] = mf * fwd - mr * rev;
+        dqT[r] = fwd * dlnkf - rev * dlnkr;
+        dq[4 * r + 0] = kf * cr1;
+        dq[4 * r + 1] = kf * cr0;
+        dq[4 * r + 2] = -kr * cp1;
+        dq[4 * r + 3] = -kr * cp0;
+    }
+    __syncthreads();
+    // species rows: owner lane k walks the reactions it takes part in
+    double wk = 0.0, wTk = 0.0, ACk = 0.0;
+    if (lane < K) {
+        const int b = wt.inc_off[lane], e = wt.inc_off[lane + 1];
+        for (int j = b; j < e; j++) {
+            const int2 ent = wt.inc[j];
+            const int r = ent.x;
+            const double nu = (double)ent.y;
+            const DevRxn x = m.rxn[r];
+            wk += nu * qbuf[r];
+            wTk += nu * dqT[r];
+            ACk += nu * qh[r];
+            const int sl[4] = {x.r0, x.r1, x.p0, x.p1};
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+                const bool sentinel = sl[s] == K;
+                const int c = sentinel ? NP + 1 : sl[s];
+                const double f = sentinel ? 0.0 : nu * sp.W * m.invW[sl[s]];
+                L.row[lane][c] += (LT)(f * dq[4 * r + s]);
+            }
+        }
+    }
+    const double RT = kRu * T;
+    const double rcp = rho * cpm;
+    const double inv_rcp = 1.0 / rcp;
+    const double S = RT * wave_sum(lane < K ? hk * wk : 0.0);
+    const double hAC = wave_sum(lane < K ? hk * ACk : 0.0);
+    const double dST = wave_sum(lane < K ? kRu * cpk * wk + RT * hk * (wTk - ACk * invT) : 0.0);
+    __syncthreads();
+    // temperature row: lane j sums column j over the species rows
+    double JT = 0.0;
+    if (lane < K) {
+        double col = 0.0;
+        for (int k = 0; k < K; k++) col += (double)L.row[k][lane] * (L.h[k] * m.invW[k]);
+        const double dS = RT * rho * (col - (wbar / rho) * sp.invW * hAC);
+        const double drcp = rho * sp.invW * (kRu * cpk - cpm * wbar);
+        JT = (-dS + S * drcp * inv_rcp) * inv_rcp;
+    } else if (lane == K) {
+        const double drcpT = rho * dcpm - cpm * rho * invT;
+        JT = (-dST + S * drcpT * inv_rcp) * inv_rcp;
+    }
+    __syncthreads();
+    const double gq = wbar / rho;
+    if (lane < K) {
+        const double u = sp.W * gq * (wk - ACk);
+        for (int c = 0; c < K; c++) L.row[lane][c] += (LT)(u * m.invW[c]);
+        L.row[lane][K] = (LT)(sp.W / rho * (wTk + (wk - ACk) * invT));
+    }
+    if (lane < N) L.row[K][lane] = (LT)JT;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NP; c++)
+        Mrow[c] = (lane < N && c < N) ? (LT)((c == lane ? 1.0 : 0.0) - gamma * (double)L.row[lane][c]) : (LT)0;
+    __syncthreads();
+}
+
+// LU with row partial pivoting across lanes.  Rows stay with their lanes;
+// `pos` is the lane's current position under the row exchanges of the plain
+// algorithm (pivot = largest magnitude at or below the diagonal, ties to the
+// lowest position); perm[k] is the lane whose row ends at position k.
+template <int NP, typename LT>
+__device__ bool wave_lu(LT *Mrow, int N, int *perm, int &pos)
+{
+    const int lane = lane_id();
+    pos = lane;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        if (k < N) {
+            const bool cand = lane < N && pos >= k;
+            const LT mk = Mrow[k];
+            const int p = wave_argmax((double)mk, cand, pos);
+            perm[k] = p;
+            const LT piv = lane_value(mk, p);
+            ok = ok && (piv != (LT)0);
+            const int pos_p = uniform(__shfl(pos, p));
+            if (pos == k) pos = pos_p;
+            if (lane == p) pos = k;
+            const bool elim = cand && lane != p;
+            const LT l = elim ? mk / piv : (LT)0;
+            if (elim) Mrow[k] = l;
+#pragma unroll
+            for (int c = k + 1; c < NP; c++) {
+                const LT pc = lane_value(Mrow[c], p);
+                if (elim && c < N) Mrow[c] -= l * pc;
+            }
+        }
+    }
+    return ok;
+}
+
+// Solve M x = b with the factors of wave_lu.  b: this lane's component (lane =
+// original row); returns component `lane` of x.
+template <int NP, typename LT>
+__device__ double wave_solve(const LT *Mrow, int N, const int *perm, int pos, double bi)
+{
+    const int lane = lane_id();
+    LT v = (LT)bi;
+    // forward substitution in elimination order
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        if (k < N) {
+            const LT yk = lane_value(v, perm[k]);
+            if (pos > k && lane < N) v -= Mrow[k] * yk;
+        }
+    }
+    // backward substitution
+    LT x = (LT)0;
+#pragma unroll
+    for (int kk = 0; kk < NP; kk++) {
+        const int k = NP - 1 - kk;
+        if (k < N) {
+            LT ukk = Mrow[k];
+            const LT xk = lane_value(v / ukk, perm[k]);
+            if (lane == k) x = xk;
+            if (pos < k && lane < N) v -= Mrow[k] * xk;
+        }
+    }
+    return (double)x;
+}
+
+template <int NP, typename LT>
+__device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellIO &io,
+                         double t_end, unsigned long long *queue, double *qbuf,
+                         WaveLds<NP, LT> &L)
+{
+    using namespace bdf;
+    const int lane = lane_id();
+    const int K = m.K, N = K + 1;
+    const double rtol = io.prm->rtol, atol = io.prm->atol;
+    SpeciesLane sp;
+    {
+        const int k = lane < K ? lane : 0;
+        const double *s = m.species + k * kSpeciesLen;
+        sp.Tmid = s[0];
+#pragma unroll
+        for (int j = 0; j < kRangeLen; j++) {
+            sp.a[j] = s[1 + j];
+            sp.a_hi[j] = s[1 + kRangeLen + j];
+        }
+        sp.W = m.W[k];
+        sp.invW = m.invW[k];
+    }
+    LT Mrow[NP];
+    int perm[NP];
+    int pos = lane;
+    for (;;) {
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd(queue, 1ull);
+        c = __shfl(c, 0);
+        if (c >= (unsigned long long)io.n) break;
+        const int64_t cell = (int64_t)c;
+        const double p = io.p[cell];
+        double y0 = 0.0;
+        if (lane < K) y0 = io.Y[lane * io.ldY + cell];
+        else if (lane == K) y0 = io.T[cell];
+        int nst = 0, nfe = 0, nje = 0, nni = 0, netf = 0, ncfn = 0;
+        int status = 0;
+        bool active = lane < N;
+        // ---------------- initial derivative and step ----------------
+        double f0 = wave_rhs<NP, LT>(m, wt, L, sp, K, p, y0, qbuf);
+        nfe++;
+        double z[kQmax + 1];
+#pragma unroll
+        for (int j = 0; j <= kQmax; j++) z[j] = 0.0;
+        z[0] = y0;
+        double w = active ? 1.0 / (rtol * fabs(y0) + atol) : 0.0;
+        auto wnorm = [&](double v) { const double t = active ? v * w : 0.0; return sqrt(wave_sum(t * t) * (1.0 / N)); };
+        auto all_finite = [&](double v) { return __ballot(active && !isfinite(v)) == 0ull; };
+        if (!all_finite(f0)) {
+            status = 4;
+        }
+        double h = t_end;
+        if (status == 0 && wnorm(f0) != 0.0) {
+            double hub = t_end;
+            {
+                // hub = min over components of (0.1|y0| + 1/w)/|f0| where it binds
+                double lim = active ? 0.1 * fabs(y0) + 1.0 / w : 0.0;
+                // sequential in component order, like the definition
+                for (int i = 0; i < N; i++) {
+                    const double fi = lane_value(f0, i), li = lane_value(lim, i);
+                    if (fabs(fi) * hub > li) hub = li / fabs(fi);
+                }
+            }
+            double hg = hub;
+            for (int it = 0; it < kH0Iters; it++) {
+                const double f1 = wave_rhs<NP, LT>(m, wt, L, sp, K, p, y0 + hg * f0, qbuf);
+                nfe++;
+                if (!all_finite(f1)) {
+                    hg *= 0.1;
+                    continue;
+                }
+                const double ydd = wnorm((f1 - f0) / hg);
+                double hnew = ydd > 0.0 ? sqrt(2.0 / ydd) : hub;
+                if (hnew > hub) hnew = hub;
+                const double ratio = hnew / hg;
+                hg = hnew;
+                if (ratio >= 0.5 && ratio <= 2.0) break;
+            }
+            h = 0.5 * hg;
+            if (h > t_end) h = t_end;
+        }
+        z[1] = h * f0;
+        int q = 1, qwait = 2, nst_M = 0;
+        bool have_M = false, ehat_ok = false;
+        double gamma_M = 0.0, crate = 1.0, ehat_h = 0.0, ehat = 0.0, t = 0.0;
+        double tau[kQmax + 2];
+#pragma unroll
+        for (int j = 0; j < kQmax + 2; j++) tau[j] = 0.0;
+        // ---------------- step loop ----------------
+        while (status == 0 && t < t_end) {
+            if (nst >= io.prm->max_steps) {
+                status = 1;
+                break;
+            }
+            bool last = false;
+            if (t + h >= t_end) {
+                const double eta = (t_end - t) / h;
+                double f = 1.0;
+#pragma unroll
+                for (int j = 1; j <= kQmax; j++) {
+                    f *= eta;
+                    if (j <= q) z[j] *= f;
+                }
+                h = t_end - t;
+                last = true;
+            }
+            w = active ? 1.0 / (rtol * fabs(z[0]) + atol) : 0.0;
+            int nef = 0, ncf = 0;
+            bool force_M = false;
+            double dsm = 0.0, e = 0.0;
+            double xi[kQmax + 2], l[kQmax + 1];
+            for (;;) {
+                const double tnew = t + h;
+                if (tnew == t) {
+                    status = 2;
+                    break;
+                }
+#pragma unroll
+                for (int kk = 1; kk <= kQmax; kk++)
+#pragma unroll
+                    for (int j = kQmax; j >= kk; j--)
+                        if (j <= q) z[j - 1] += z[j];
+                {
+                    double s = h;
+                    xi[1] = 1.0;
+#pragma unroll
+                    for (int i = 2; i <= kQmax + 1; i++) {
+                        s += tau[i - 1];
+                        xi[i] = s / h;
+                    }
+                    l[0] = 1.0;
+#pragma unroll
+                    for (int j = 1; j <= kQmax; j++) l[j] = 0.0;
+#pragma unroll
+                    for (int i = 1; i <= kQmax; i++)
+                        if (i <= q)
+#pragma unroll
+                            for (int j = i; j >= 1; j--) l[j] += l[j - 1] / xi[i];
+                }
+                const double gamma = h / l[1];
+                double xq1 = h;
+#pragma unroll
+                for (int i = 1; i <= kQmax; i++)
+                    if (i <= q) xq1 += tau[i];
+                xq1 /= h;
+                const double Cq = 1.0 / (1.0 + l[1] * xq1);
+                bool jcur = false, conv = false, lu_ok = true;
+                if (!have_M || force_M || nst >= nst_M + kMsbp || fabs(gamma / gamma_M - 1.0) > kDgmax) {
+                    wave_newton_matrix<NP, LT>(m, wt, L, sp, K, p, z[0], gamma, qbuf, Mrow);
+                    nje++;
+                    lu_ok = wave_lu<NP, LT>(Mrow, N, perm, pos);
+                    gamma_M = gamma;
+                    nst_M = nst;
+                    crate = 1.0;
+                    have_M = lu_ok;
+                    jcur = true;
+                    force_M = false;
+                }
+                if (lu_ok) {
+                    double del_old = 0.0;
+                    e = 0.0;
+                    const double inv_l1 = 1.0 / l[1];
+                    for (int it = 0; it < kMaxCor; it++) {
+                        const double fy = wave_rhs<NP, LT>(m, wt, L, sp, K, p, z[0] + e, qbuf);
+                        nfe++;
+                        if (!all_finite(fy)) break;
+                        double d = active ? -(e - gamma * fy + z[1] * inv_l1) : 0.0;
+                        d = wave_solve<NP, LT>(Mrow, N, perm, pos, d);
+                        if (!active) d = 0.0;
+                        if (gamma != gamma_M) d *= 2.0 / (1.0 + gamma / gamma_M);
+                        const double dl = wnorm(d);
+                        e += d;
+                        nni++;
+                        if (it > 0) crate = fmax(kCrdown * crate, dl / del_old);
+                        const double dcon = dl * fmin(crate, 1.0) * Cq / kNlscoef;
+                        if (dcon <= 1.0) {
+                            conv = true;
+                            break;
+                        }
+                        if (it > 0 && dl > kRdiv * del_old) break;
+                        del_old = dl;
+                    }
+                }
+                if (!conv) {
+#pragma unroll
+                    for (int kk = kQmax; kk >= 1; kk--)
+#pragma unroll
+                        for (int j = kk; j <= kQmax; j++)
+                            if (j <= q && kk <= q) z[j - 1] -= z[j];
+                    if (!jcur) {
+                        force_M = true;
+                        continue;
+                    }
+                    ncfn++;
+                    if (++ncf >= kMaxNcf) {
+                        status = 3;
+                        break;
+                    }
+                    double f = 1.0;
+#pragma unroll
+                    for (int j = 1; j <= kQmax; j++) {
+                        f *= kEtaCf;
+                        if (j <= q) z[j] *= f;
+                    }
+                    h *= kEtaCf;
+                    last = false;
+                    continue;
+                }
+                dsm = Cq * wnorm(e);
+                if (dsm > 1.0) {
+#pragma unroll
+                    for (int kk = kQmax; kk >= 1; kk--)
+#pragma unroll
+                        for (int j = kk; j <= kQmax; j++)
+                            if (j <= q && kk <= q) z[j - 1] -= z[j];
+                    netf++;
+                    if (++nef >= kMaxNef) {
+                        status = 2;
+                        break;
+                    }
+                    last = false;
+                    if (nef >= kNefRestart) {
+                        h *= kEtaMinEf;
+                        q = 1;
+                        const double fr = wave_rhs<NP, LT>(m, wt, L, sp, K, p, z[0], qbuf);
+                        nfe++;
+                        if (!all_finite(fr)) {
+                            status = 4;
+                            break;
+                        }
+                        z[1] = h * fr;
+#pragma unroll
+                        for (int j = 0; j < kQmax + 2; j++) tau[j] = 0.0;
+                        qwait = 2;
+                        ehat_ok = false;
+                        continue;
+                    }
+                    double eta = 1.0 / (pow(kBiasQ * dsm, 1.0 / (q + 1)) + kAddon);
+                    eta = fmin(fmax(eta, kEtaMinEf), kEtaMaxEf);
+                    if (nef >= 2) eta = fmin(eta, kEtaNef2);
+                    double f = 1.0;
+#pragma unroll
+                    for (int j = 1; j <= kQmax; j++) {
+                        f *= eta;
+                        if (j <= q) z[j] *= f;
+                    }
+                    h *= eta;
+                    continue;
+                }
+#pragma unroll
+                for (int j = 0; j <= kQmax; j++)
+                    if (j <= q) z[j] += l[j] * e;
+                break;
+            }
+            if (status != 0) break;
+            t = last ? t_end : t + h;
+            nst++;
+            if (t >= t_end) break;
+
+            // ---------------- next step size and order ----------------
+            const double h_done = h;
+            double prod_q = 1.0;
+#pragma unroll
+            for (int i = 1; i <= kQmax; i++)
+                if (i <= q) prod_q *= xi[i];
+            double x1 = h;
+#pragma unroll
+            for (int i = 1; i <= kQmax; i++)
+                if (i <= q) x1 += tau[i];
+            x1 /= h;
+            double fact = 1.0;
+#pragma unroll
+            for (int i = 2; i <= kQmax + 1; i++)
+                if (i <= q + 1) fact *= i;
+            const double gfac = prod_q * (1.0 / l[1] + x1) / fact;
+            const double ehat_new = e / gfac;
+            if (qwait > 0) qwait--;
+            const double etamax = (nef > 0 || ncf > 0) ? 1.0 : (nst == 1 ? kEtaMaxFirst : kEtaMax);
+            double eta = 1.0;
+            int qnew = q;
+            if (etamax > 1.0) {
+                eta = 1.0 / (pow(kBiasQ * dsm, 1.0 / (q + 1)) + kAddon);
+                if (qwait == 0) {
+                    double eta_m = 0.0, eta_p = 0.0;
+                    if (q > 1) {
+                        double prod = 1.0, l1 = 0.0, zq = 0.0;
+#pragma unroll
+                        for (int j = 2; j <= kQmax; j++)
+                            if (j == q) zq = z[j];
+#pragma unroll
+                        for (int i = 1; i < kQmax; i++)
+                            if (i <= q - 1) {
+                                prod *= xi[i];
+                                l1 += 1.0 / xi[i];
+                            }
+                        const double Em = wnorm(zq) * prod / l1;
+                        eta_m = 1.0 / (pow(kBiasQm1 * Em, 1.0 / q) + kAddon);
+                    }
+                    if (q < kQmax && ehat_ok) {
+                        const double rr = pow(h_done / ehat_h, q + 1);
+                        const double dv = ehat_new - ehat * rr;
+                        double prod = 1.0, l1 = 0.0;
+#pragma unroll
+                        for (int i = 1; i <= kQmax; i++)
+                            if (i <= q + 1) {
+                                prod *= xi[i];
+                                l1 += 1.0 / xi[i];
+                            }
+                        double fact2 = fact * (q + 2);
+                        const double Ep = wnorm(dv) * prod / (fact2 * l1);
+                        eta_p = 1.0 / (pow(kBiasQp1 * Ep, 1.0 / (q + 2)) + kAddon);
+                    }
+                    if (eta_m > eta && eta_m >= eta_p) {
+                        eta = eta_m;
+                        qnew = q - 1;
+                    } else if (eta_p > eta) {
+                        eta = eta_p;
+                        qnew = q + 1;
+                    }
+                }
+                if (eta < kThresh) {
+                    eta = 1.0;
+                    qnew = q;
+                } else if (eta > etamax) {
+                    eta = etamax;
+                }
+            }
+            if (qnew == q - 1) {
+                double d[kQmax + 2];
+#pragma unroll
+                for (int j = 0; j < kQmax + 2; j++) d[j] = 0.0;
+                d[1] = 1.0;
+#pragma unroll
+                for (int i = 1; i < kQmax; i++)
+                    if (i <= q - 1)
+#pragma unroll
+                        for (int j = kQmax; j >= 1; j--)
+                            if (j <= i + 1) d[j] = d[j - 1] + xi[i] * d[j];
+                double zq = 0.0;
+#pragma unroll
+                for (int j = 2; j <= kQmax; j++)
+                    if (j == q) zq = z[j];
+#pragma unroll
+                for (int j = 1; j < kQmax; j++)
+                    if (j < q) z[j] -= d[j] * zq;
+                q = qnew;
+                qwait = q + 1;
+                ehat_ok = false;
+            } else if (qnew == q + 1) {
+                const double inv = 1.0 / x1;
+#pragma unroll
+                for (int j = 2; j <= kQmax; j++)
+                    if (j == q + 1) z[j] = 0.0;
+#pragma unroll
+                for (int j = 1; j <= kQmax; j++)
+                    if (j <= q + 1) z[j] += e * l[j - 1] * inv;
+                q = qnew;
+                qwait = q + 1;
+                ehat_ok = false;
+            } else {
+                ehat = ehat_new;
+                ehat_h = h_done;
+                ehat_ok = true;
+            }
+#pragma unroll
+            for (int i = kQmax + 1; i >= 2; i--) tau[i] = tau[i - 1];
+            tau[1] = h_done;
+            if (eta != 1.0) {
+                double f = 1.0;
+#pragma unroll
+                for (int j = 1; j <= kQmax; j++) {
+                    f *= eta;
+                    if (j <= q) z[j] *= f;
+                }
+                h *= eta;
+            }
+        }
+        if (status == 0 && !all_finite(z[0])) status = 4;
+        if (status == 0) {
+            if (lane < K) io.Y[lane * io.ldY + cell] = z[0];
+            else if (lane == K) io.T[cell] = z[0];
+        }
+        if (lane == 0) {
+            if (io.status) io.status[cell] = status;
+            if (io.counters) {
+                io.counters[0 * io.n + cell] = nst;
+                io.counters[1 * io.n + cell] = nfe;
+                io.counters[2 * io.n + cell] = nje;
+                io.counters[3 * io.n + cell] = nni;
+                io.counters[4 * io.n + cell] = netf;
+                io.counters[5 * io.n + cell] = ncfn;
+            }
+        }
+    }
+}
+
+template <int NP, typename LT>
+__global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables wt,
+                                                      double *__restrict__ T,
+                                                      const double *__restrict__ p,
+                                                      double *__restrict__ Y, int64_t ldY,
+                                                      int64_t n, double dt, BdfParams prm,
+                                                      int32_t *__restrict__ status,
+                                                      int32_t *__restrict__ counters,
+                                                      unsigned long long *__restrict__ queue,
+                                                      double *__restrict__ qscratch)
+{
+    __shared__ WaveLds<NP, LT> L;
+    CellIO io{T, p, Y, ldY, n, status, counters, &prm};
+    // per-wave reaction scratch (7 R doubles) in global memory, one slice per wave
+    double *qbuf = qscratch + (size_t)blockIdx.x * 7 * m.R;
+    run_wave<NP, LT>(m, wt, io, dt, queue, qbuf, L);
+}
+
+}  // namespace
+
+int wave_kernel_rows(int N) { return N <= 16 ? 16 : (N <= 40 ? 40 : (N <= 64 ? 64 : 0)); }
+
+template <int NP, typename LT>
+static hipError_t launch_np(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
+                            double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
+                            int32_t *status, int32_t *counters, unsigned long long *queue,
+                            double *qscratch, int max_waves, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, queue);
+    int blocks = queue_grid((const void *)bdf_wave_kernel<NP, LT>, n * 64);
+    if (blocks > max_waves) blocks = max_waves;
+    if (blocks > n) blocks = (int)n;
+    hipLaunchKernelGGL((bdf_wave_kernel<NP, LT>), dim3(blocks), dim3(64), 0, s, m, wt, T, p, Y, ldY,
+                       n, dt, prm, status, counters, queue, qscratch);
+    return hipGetLastError();
+}
+
+hipError_t launch_bdf_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
+                           double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
+                           int32_t *status, int32_t *counters, unsigned long long *queue,
+                           double *qscratch, int max_waves, bool fp32_lu, hipStream_t s)
+{
+    const int NP = wave_kernel_rows(m.K + 1);
+#define CHEM_WAVE_CASE(NPV)                                                                          \
+    if (NP == NPV)                                                                                   \
+        return fp32_lu ? launch_np<NPV, float>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters,   \
+                                              queue, qscratch, max_waves, s)                       \
+                       : launch_np<NPV, double>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters,  \
+                                               queue, qscratch, max_waves, s);
+    CHEM_WAVE_CASE(16)
+    CHEM_WAVE_CASE(40)
+    CHEM_WAVE_CASE(64)
+#undef CHEM_WAVE_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace chem

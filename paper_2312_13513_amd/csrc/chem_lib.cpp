@@ -12,6 +12,7 @@
 
 #include "chem.h"
 #include "bdf_driver.h"
+#include "bdf_wave.h"
 
 namespace {
 
@@ -157,6 +158,9 @@ struct chem_mech_s {
     unsigned next_queue = 0;
     const chem::GenEntry *gen = nullptr;    // mechanism-specialised kernels, if compiled
     std::string variant = "table";
+    chem::WaveTables wave{};                // species -> reaction incidence (wave kernel)
+    double *wave_scratch = nullptr;         // per-wave reaction buffers (7 R doubles each)
+    int wave_slots = 0;
 };
 
 namespace {
@@ -292,7 +296,30 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     const size_t off_iw = (off_w + n_w + 255) & ~size_t(255);
     const size_t off_rx = (off_iw + n_w + 255) & ~size_t(255);
     const size_t off_q = (off_rx + rx.size() * sizeof(chem::DevRxn) + 255) & ~size_t(255);
-    const size_t total = off_q + kQueues * 256;
+    // species -> (reaction, net coefficient) incidence, reactions in order
+    std::vector<int> inc_off(K + 1, 0);
+    std::vector<std::vector<std::pair<int, int>>> inc_lists(K);
+    for (int i = 0; i < R; i++) {
+        std::vector<int> net(K, 0);
+        for (auto &t : h.rxn[i].reac) net[t.first] -= t.second;
+        for (auto &t : h.rxn[i].prod) net[t.first] += t.second;
+        for (int k = 0; k < K; k++)
+            if (net[k] != 0) inc_lists[k].push_back({i, net[k]});
+    }
+    std::vector<int> inc_flat;
+    for (int k = 0; k < K; k++) {
+        inc_off[k + 1] = inc_off[k] + (int)inc_lists[k].size();
+        for (auto &pr : inc_lists[k]) {
+            inc_flat.push_back(pr.first);
+            inc_flat.push_back(pr.second);
+        }
+    }
+    if (inc_flat.empty()) inc_flat.assign(2, 0);
+    const size_t off_io = off_q + kQueues * 256;
+    const size_t off_inc = (off_io + (K + 1) * sizeof(int) + 255) & ~size_t(255);
+    const size_t off_ws = (off_inc + inc_flat.size() * sizeof(int) + 255) & ~size_t(255);
+    const int wave_slots = 4096;   // concurrent waves of the wave kernel
+    const size_t total = off_ws + (size_t)wave_slots * 7 * (R > 0 ? R : 1) * sizeof(double);
     int prev = 0;
     if ((rc = check_hip(hipGetDevice(&prev), "hipGetDevice")) != CHEM_OK) {
         delete m;
@@ -309,12 +336,14 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
         delete m;
         return fail(CHEM_ENOMEM, "hipMalloc of the mechanism tables failed");
     }
-    std::vector<char> staging(total, 0);
+    std::vector<char> staging(off_ws, 0);
     std::memcpy(staging.data(), species.data(), n_sp);
     std::memcpy(staging.data() + off_w, W.data(), n_w);
     std::memcpy(staging.data() + off_iw, invW.data(), n_w);
     std::memcpy(staging.data() + off_rx, rx.data(), rx.size() * sizeof(chem::DevRxn));
-    rc = check_hip(hipMemcpy(blk, staging.data(), total, hipMemcpyHostToDevice), "hipMemcpy");
+    std::memcpy(staging.data() + off_io, inc_off.data(), inc_off.size() * sizeof(int));
+    std::memcpy(staging.data() + off_inc, inc_flat.data(), inc_flat.size() * sizeof(int));
+    rc = check_hip(hipMemcpy(blk, staging.data(), off_ws, hipMemcpyHostToDevice), "hipMemcpy");
     hipSetDevice(prev);
     if (rc != CHEM_OK) {
         hipFree(blk);
@@ -330,6 +359,10 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     m->view.invW = (const double *)(blk + off_iw);
     m->view.rxn = (const chem::DevRxn *)(blk + off_rx);
     m->queues = (unsigned long long *)(blk + off_q);
+    m->wave.inc_off = (const int *)(blk + off_io);
+    m->wave.inc = (const int2 *)(blk + off_inc);
+    m->wave_scratch = (double *)(blk + off_ws);
+    m->wave_slots = wave_slots;
     *out = m;
     return CHEM_OK;
 }
@@ -392,23 +425,38 @@ int chem_integrate(chem_mech m, double *T, const double *p, double *Y, int64_t l
     if (!(o.rtol > 0.0) || !(o.atol > 0.0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol))
         return fail(CHEM_EINVAL, "rtol and atol must be finite and > 0");
     if (o.max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
-    if (o.precision != 0) return fail(CHEM_EUNSUP, "only precision 0 (FP64) is implemented");
-    if (o.schedule != -1 && o.schedule != 0) return fail(CHEM_EUNSUP, "unknown schedule");
+    if (o.precision != 0 && o.precision != 1) return fail(CHEM_EINVAL, "precision must be 0 or 1");
+    if (o.schedule < -1 || o.schedule > 1) return fail(CHEM_EINVAL, "unknown schedule");
     if (o.block != 0 && o.block != 64) return fail(CHEM_EUNSUP, "block must be 0 or 64");
     if (n == 0) return CHEM_OK;
     if ((status && !is_device_ptr(status)) || (counters && !is_device_ptr(counters)))
         return fail(CHEM_EINVAL, "status and counters must be device pointers or NULL");
-    if (!m->gen && !chem::thread_kernel_supports(m->host.K))
-        return fail(CHEM_EUNSUP, "no integrator kernel is built for K = " + std::to_string(m->host.K));
+    const int K = m->host.K;
+    const bool thread_ok = m->gen != nullptr || chem::thread_kernel_supports(K);
+    const bool wave_ok = chem::wave_kernel_rows(K + 1) > 0;
+    // automatic choice: the wave kernel for mixed precision and for mechanisms
+    // without a one-thread-per-cell kernel
+    const int sched = o.schedule >= 0 ? o.schedule : ((o.precision == 1 || !thread_ok) ? 1 : 0);
+    if (sched == 0 && !thread_ok)
+        return fail(CHEM_EUNSUP, "no one-thread-per-cell kernel is built for K = " + std::to_string(K));
+    if (sched == 0 && o.precision != 0)
+        return fail(CHEM_EUNSUP, "the one-thread-per-cell schedule computes in FP64 only");
+    if (sched == 1 && !wave_ok)
+        return fail(CHEM_EUNSUP, "the wave schedule supports at most 63 species");
     if (o.jac_batch < 0 || o.jac_batch > 64) return fail(CHEM_EINVAL, "jac_batch must be in 0..64");
     chem::BdfParams prm{o.rtol, o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16};
     // each call takes its own queue counter (64 rotate), so that calls in
     // flight on different streams do not share one
     unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);
-    hipError_t e = m->gen ? m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue,
-                                              (hipStream_t)stream)
-                          : chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status,
-                                                    counters, queue, (hipStream_t)stream);
+    hipError_t e;
+    if (sched == 1)
+        e = chem::launch_bdf_wave(m->view, m->wave, T, p, Y, ldY, n, dt, prm, status, counters, queue,
+                                  m->wave_scratch, m->wave_slots, o.precision == 1, (hipStream_t)stream);
+    else if (m->gen)
+        e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, (hipStream_t)stream);
+    else
+        e = chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status, counters, queue,
+                                    (hipStream_t)stream);
     return check_hip(e, "integrator launch");
 }
 

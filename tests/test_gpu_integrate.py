@@ -95,6 +95,45 @@ def compare(tag, Tg, Yg, sg, cg, To, Yo, so, co):
     return flips
 
 
+def oracle_envelope(om, T, p, Y, dt, base):
+    """Round-off conditioning of the oracle's own result: the largest change
+    of T and Y under two one-ulp perturbations of its inputs (T scaled by
+    1 + 2^-52, rtol by 1 + 2^-52).  For cells whose step sequence is decided
+    by round-off (hundreds of steps with many rejected ones), two correct FP64
+    implementations differ by about this much, whatever their summation order."""
+    To, Yo = base[0], base[1]
+    eT, eY = 0.0, 0.0
+    for args, kw in (((T * (1.0 + 2.0 ** -52), p, Y, dt), {}),
+                     ((T, p, Y, dt), {"rtol": 1e-8 * (1.0 + 2.0 ** -52)})):
+        Tp, Yp = om.integrate(*args, **kw)[:2]
+        eT = max(eT, float(np.abs(Tp - To).max()))
+        eY = max(eY, float(np.abs(Yp - Yo).max()))
+    return eT, eY
+
+
+def compare_conditioned(tag, Tg, Yg, sg, cg, To, Yo, so, co, envelope, factor=4.0):
+    """Bars for workloads whose decisions are round-off sensitive: cells whose
+    step counts agree with the oracle meet the plain bars (1e-6 K, 1e-10);
+    cells where a decision flipped stay within `factor` times the oracle's own
+    one-ulp envelope."""
+    dT = np.abs(Tg - To)
+    dY = np.abs(Yg - Yo).max(axis=0)
+    flip = (cg != co).any(axis=1)
+    same = ~flip
+    eT, eY = envelope
+    _say(f"[{tag}] n={Tg.size} cells with equal step counts {same.sum()}: max|dT|="
+         f"{dT[same].max() if same.any() else 0:.3e} K max|dY|={dY[same].max() if same.any() else 0:.3e}; "
+         f"flipped {flip.sum()}: max|dT|={dT[flip].max() if flip.any() else 0:.3e} K max|dY|="
+         f"{dY[flip].max() if flip.any() else 0:.3e}; oracle one-ulp envelope dT {eT:.3e} K dY {eY:.3e}")
+    assert np.array_equal(sg, so)
+    if same.any():
+        assert dT[same].max() < DT_TOL and dY[same].max() < DY_TOL
+    if flip.any():
+        assert dT[flip].max() <= factor * max(eT, DT_TOL)
+        assert dY[flip].max() <= factor * max(eY, DY_TOL)
+    return np.where(flip)[0]
+
+
 # --------------------------------------------------------------------------- building blocks
 
 def _states(m, n, seed):
