@@ -84,10 +84,14 @@ def cells4096(mech: Optional[Mechanism] = None, n: int = 4096, seed: int = 101) 
     return Field("cells4096", "M9", T, np.full(n, P_ATM), Y, 1e-6)
 
 
-def flame_field(mech: Mechanism, shape, seed: int, dt: float, name: str, mech_name: str) -> Field:
+def flame_field(mech: Mechanism, shape, seed: int, dt: float, name: str, mech_name: str,
+                mix_seed: Optional[int] = None) -> Field:
+    """Smooth flame field.  The unburnt/burnt end states come from the field's
+    own random stream, or from ``default_rng(mix_seed)`` when given (the same
+    mixture as the surrogate's training data of that seed)."""
     rng = np.random.default_rng(seed)
     c = c_field(shape, rng)
-    Yu, Yb = end_states(mech, rng)
+    Yu, Yb = end_states(mech, rng if mix_seed is None else np.random.default_rng(mix_seed))
     T = 300.0 + 1900.0 * c
     Y = (1.0 - c)[None, :] * Yu[:, None] + c[None, :] * Yb[:, None]
     return Field(name, mech_name, T, np.full(c.size, P_ATM), Y, dt, c=c)
@@ -126,11 +130,12 @@ def zones128(mech: Optional[Mechanism] = None, seed: int = 103, shape=(128, 128,
 
 def flame256x128x128(mech: Optional[Mechanism] = None, seed: int = 104) -> Field:
     return flame_field(mech or standard_mechanism("M35"), (256, 128, 128), seed, 1e-5,
-                       "flame256x128x128", "M35")
+                       "flame256x128x128", "M35", mix_seed=7)
 
 
 def flame256(mech: Optional[Mechanism] = None, seed: int = 105) -> Field:
-    return flame_field(mech or standard_mechanism("M35"), (256, 256, 256), seed, 1e-5, "flame256", "M35")
+    return flame_field(mech or standard_mechanism("M35"), (256, 256, 256), seed, 1e-5, "flame256", "M35",
+                       mix_seed=7)
 
 
 def subset(field: Field, idx: np.ndarray, name_suffix: str = "_sub") -> Field:

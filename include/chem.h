@@ -127,6 +127,117 @@ int chem_eval_jacobian(chem_mech mech, const double *T, const double *p, const d
 /* Thread-local description of the last error (never NULL). */
 const char *chem_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate (paper Section 2: a DNN predicts the chemical source of
+ * every cell from its temperature, pressure and mass fractions; Sections 3.1
+ * and 3.2: the network runs on the GPU with its input and output kept in
+ * device memory; training uses Adam and GELU activations).
+ *
+ * Network: x = zscore([T, p, BoxCox(max(Y,0); 0.1)]) (K + 2 inputs, padded to
+ * 64), three GELU hidden layers of h1, h2, h3 units (multiples of 64;
+ * 512/256/128 in the reference configuration), output the z-scored change
+ * of the K mass fractions over one flow step dt.  Weights and activations
+ * BF16, accumulation and biases FP32 (MFMA), Adam on FP32 master weights.
+ *
+ * Logical parameter vector (set/get/grad), FP32, in this order:
+ *   W1[h1][K+2], b1[h1], W2[h2][h1], b2[h2], W3[h3][h2], b3[h3], W4[K][h3], b4[K]
+ * (row-major, out x in).  Normalisation vector, FP64:
+ *   mu_x[K+2], sig_x[K+2], mu_y[K], sig_y[K], dt
+ * (features with sig < 1e-12 map to 0; dt is the flow step the network was
+ * trained for).
+ *
+ * A surrogate handle refers to its mechanism, which must outlive it.  The
+ * surrogate grows workspace on first use (chem_surrogate_infer at a given
+ * ncells); later calls of at most that size neither allocate nor
+ * synchronise and may be captured in a HIP graph.
+ * ------------------------------------------------------------------------ */
+typedef struct chem_surr_s *chem_surr;
+
+/* Acceptance checks of a predicted cell; a cell failing any of them is
+ * integrated instead (per-cell fallback). */
+typedef struct {
+    double elem_tol;    /* max_e |sum_k n_ke (Y'-Y)_k/W_k| / max(sum_k n_ke Y_k/W_k, 1e-12) (1e-3) */
+    double sum_tol;     /* |sum Y' - 1| (1e-3); then Y' is clipped at 0 and renormalised */
+    double neg_tol;     /* Y'_k >= -neg_tol (1e-6) */
+    double T_out_min, T_out_max;   /* recovered temperature range (250, 2600 K) */
+    double T_in_min, T_in_max;     /* input temperature inside the training box (300, 2500 K) */
+    double dT_gate;     /* |T' - T| <= dT_gate when > 0 (0 = off) */
+    int32_t reserved[8];
+} chem_surr_checks;
+
+int chem_surrogate_default_checks(chem_surr_checks *checks);
+
+/* New surrogate for mech with zero parameters and unset normalisation. */
+int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out);
+void chem_free_surrogate(chem_surr surr);
+/* dims[0..5] = K+2, h1, h2, h3, K, number of logical parameters. */
+int chem_surrogate_info(chem_surr surr, int64_t *dims);
+/* Host FP32 logical parameter vector in / out (count must match). */
+int chem_surrogate_set_params(chem_surr surr, const float *params, int64_t count);
+int chem_surrogate_get_params(chem_surr surr, float *params, int64_t count);
+/* Host FP64 normalisation vector in / out (2 (K+2) + 2 K + 1 values). */
+int chem_surrogate_set_norm(chem_surr surr, const double *norm, int64_t count);
+int chem_surrogate_get_norm(chem_surr surr, double *norm, int64_t count);
+/* Normalisation from training samples (device): states T, p, Y and the mass
+ * fractions Ynext[k * ldYn + i] of the same cells one flow step dt later.
+ * Population mean and standard deviation of each feature and of each
+ * dY_k = Ynext_k - Y_k.  Synchronises the stream. */
+int chem_surrogate_fit_norm(chem_surr surr, const double *T, const double *p, const double *Y,
+                            int64_t ldY, const double *Ynext, int64_t ldYn, int64_t n, double dt,
+                            void *hip_stream);
+/* Network input of n cells: X[i * 64 + j] BF16 bit patterns (device, n x 64). */
+int chem_surrogate_encode(chem_surr surr, const double *T, const double *p, const double *Y,
+                          int64_t ldY, int64_t n, uint16_t *X, void *hip_stream);
+/* Network output for n encoded rows: out[i * ldo + k], k < K (device FP32,
+ * ldo >= K rounded up to 16; columns K..ldo-1 are written with the padding
+ * outputs). */
+int chem_surrogate_forward(chem_surr surr, const uint16_t *X, int64_t n, float *out, int64_t ldo,
+                           void *hip_stream);
+/* Decode, temperature recovery and checks of n cells from a network output
+ * (device, layout of chem_surrogate_forward): accepted cells take the
+ * prediction in place, mask[i] = 1 marks the rejected ones (their state is
+ * unchanged).  No integration. */
+int chem_surrogate_apply(chem_surr surr, double *T, const double *p, double *Y, int64_t ldY,
+                         int64_t n, const float *out, int64_t ldo, const chem_surr_checks *checks,
+                         int32_t *mask, void *hip_stream);
+/* One flow step of n cells by the surrogate with per-cell fallback: encode,
+ * network, decode and checks; rejected cells are integrated by
+ * chem_integrate (opts) over dt.  mask (nullable): 1 for fallback cells.
+ * status (nullable): integrator status of fallback cells, 0 elsewhere.
+ * fallback_count (nullable, device int64): number of fallback cells.
+ * dt must equal the dt of the normalisation. */
+int chem_surrogate_infer(chem_surr surr, double *T, const double *p, double *Y, int64_t ldY,
+                         int64_t n, double dt, const chem_opts *opts,
+                         const chem_surr_checks *checks, int32_t *mask, int32_t *status,
+                         int64_t *fallback_count, void *hip_stream);
+/* Loss and parameter gradient of one batch: X (device, n x 64 BF16 rows as
+ * from chem_surrogate_encode), targets Yt[i * ldt + k] (device FP32 z-scored
+ * dY, ldt >= K).  Loss = mean over the n x K entries of (out - Yt)^2; the
+ * gradient is kept inside the handle.  *loss is written (host).  Synchronises. */
+int chem_surrogate_grad(chem_surr surr, const uint16_t *X, const float *Yt, int64_t ldt, int64_t n,
+                        double *loss, void *hip_stream);
+/* The handle's gradient as a host logical vector, or replaced by one. */
+int chem_surrogate_get_grads(chem_surr surr, float *grads, int64_t count);
+int chem_surrogate_set_grads(chem_surr surr, const float *grads, int64_t count);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, bias corrected) with the handle's
+ * gradient and learning rate lr; the step counter is kept in the handle. */
+int chem_surrogate_adam(chem_surr surr, double lr, void *hip_stream);
+/* Training: encodes the n samples (states T, p, Y and Ynext one flow step of
+ * the normalisation's dt later, device; the target is the z-scored
+ * Ynext - Y), then `epochs` passes of minibatches of `batch`
+ * rows in the sample order order[e * n + i] (device int32, NULL = 0..n-1 every
+ * epoch), each: forward, MSE loss, backward, Adam with a cosine learning rate
+ * from lr0 to lr1 over all minibatches.  loss_per_epoch (host, nullable)
+ * receives the mean loss of each epoch.  Allocates its own buffers and
+ * synchronises. */
+int chem_surrogate_train(chem_surr surr, const double *T, const double *p, const double *Y,
+                         int64_t ldY, const double *Ynext, int64_t ldYn, int64_t n,
+                         const int32_t *order, int32_t epochs, int32_t batch, double lr0,
+                         double lr1, double *loss_per_epoch, void *hip_stream);
+/* Versioned file: magic, dimensions, normalisation, FP32 parameters, checksum. */
+int chem_surrogate_save(chem_surr surr, const char *path);
+int chem_surrogate_load(chem_mech mech, const char *path, chem_surr *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -204,3 +204,17 @@ def encode_cells(norm, T, p, Y):
     """Network input of cells: z-scored features, FP64 -> FP32 -> BF16."""
     x = zscore(features(T, p, Y), norm["mu_x"], norm["sigma_x"])
     return to_bf16(x.astype(np.float32))
+
+
+def fit_norm(T, p, Y, Ynext, dt):
+    """Normalisation vector: population mean and standard deviation of every
+    raw feature and of every dY_k = Ynext_k - Y_k, then dt."""
+    raw = features(T, p, Y)
+    dY = (np.asarray(Ynext) - np.asarray(Y)).T
+    return np.concatenate([raw.mean(axis=0), raw.std(axis=0), dY.mean(axis=0), dY.std(axis=0), [dt]])
+
+
+def unpack_norm(norm, K):
+    nin = K + 2
+    return {"mu_x": norm[:nin], "sigma_x": norm[nin:2 * nin], "mu_y": norm[2 * nin:2 * nin + K],
+            "sigma_y": norm[2 * nin + K:2 * nin + 2 * K], "dt": float(norm[-1])}

@@ -31,6 +31,12 @@ class chem_opts(C.Structure):
                 ("jac_batch", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
+class chem_surr_checks(C.Structure):
+    _fields_ = [("elem_tol", C.c_double), ("sum_tol", C.c_double), ("neg_tol", C.c_double),
+                ("T_out_min", C.c_double), ("T_out_max", C.c_double), ("T_in_min", C.c_double),
+                ("T_in_max", C.c_double), ("dT_gate", C.c_double), ("reserved", C.c_int32 * 8)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
@@ -48,6 +54,31 @@ def _load():
     L.chem_integrate.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), vp, vp, vp]
     L.chem_eval_rhs.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, vp]
     L.chem_eval_jacobian.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, vp]
+    fp, dblp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    ckp = C.POINTER(chem_surr_checks)
+    L.chem_surrogate_default_checks.argtypes = [ckp]
+    L.chem_surrogate_create.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(vp)]
+    L.chem_free_surrogate.argtypes = [vp]
+    L.chem_free_surrogate.restype = None
+    L.chem_surrogate_info.argtypes = [vp, i64p]
+    L.chem_surrogate_set_params.argtypes = [vp, fp, i64]
+    L.chem_surrogate_get_params.argtypes = [vp, fp, i64]
+    L.chem_surrogate_set_norm.argtypes = [vp, dblp, i64]
+    L.chem_surrogate_get_norm.argtypes = [vp, dblp, i64]
+    L.chem_surrogate_fit_norm.argtypes = [vp, dp, dp, dp, i64, dp, i64, i64, C.c_double, vp]
+    L.chem_surrogate_encode.argtypes = [vp, dp, dp, dp, i64, i64, dp, vp]
+    L.chem_surrogate_forward.argtypes = [vp, dp, i64, dp, i64, vp]
+    L.chem_surrogate_apply.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, ckp, dp, vp]
+    L.chem_surrogate_infer.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), ckp,
+                                       dp, dp, dp, vp]
+    L.chem_surrogate_grad.argtypes = [vp, dp, dp, i64, i64, dblp, vp]
+    L.chem_surrogate_get_grads.argtypes = [vp, fp, i64]
+    L.chem_surrogate_set_grads.argtypes = [vp, fp, i64]
+    L.chem_surrogate_adam.argtypes = [vp, C.c_double, vp]
+    L.chem_surrogate_train.argtypes = [vp, dp, dp, dp, i64, dp, i64, i64, dp, C.c_int32, C.c_int32,
+                                       C.c_double, C.c_double, dblp, vp]
+    L.chem_surrogate_save.argtypes = [vp, C.c_char_p]
+    L.chem_surrogate_load.argtypes = [vp, C.c_char_p, C.POINTER(vp)]
     return L
 
 
@@ -56,7 +87,13 @@ _lib = _load()
 #: Symbols that include/chem.h declares (checked by the ABI test).
 EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_mechanism_info", "chem_mechanism_variant", "chem_integrate", "chem_eval_rhs", "chem_eval_jacobian",
-            "chem_last_error")
+            "chem_last_error", "chem_surrogate_default_checks", "chem_surrogate_create",
+            "chem_free_surrogate", "chem_surrogate_info", "chem_surrogate_set_params",
+            "chem_surrogate_get_params", "chem_surrogate_set_norm", "chem_surrogate_get_norm",
+            "chem_surrogate_fit_norm", "chem_surrogate_encode", "chem_surrogate_forward",
+            "chem_surrogate_apply", "chem_surrogate_infer", "chem_surrogate_grad",
+            "chem_surrogate_get_grads", "chem_surrogate_set_grads", "chem_surrogate_adam",
+            "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load")
 
 
 def lib():
@@ -160,3 +197,135 @@ class Mechanism:
 
     def jacobian(self, T, p, Y, J, stream=None):
         chem_eval_jacobian(self.handle, T, p, Y, J, stream)
+
+
+# --------------------------------------------------------------------------- surrogate
+
+def chem_surrogate_default_checks() -> chem_surr_checks:
+    c = chem_surr_checks()
+    _check(_lib.chem_surrogate_default_checks(C.byref(c)))
+    return c
+
+
+def _host_f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _host_f64(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Surrogate:
+    """Owning wrapper of a chem_surr handle (the mechanism must stay open)."""
+
+    def __init__(self, mech: Mechanism, h1: int = 512, h2: int = 256, h3: int = 128, handle: int = 0):
+        self.mech = mech
+        if not handle:
+            h = C.c_void_p()
+            _check(_lib.chem_surrogate_create(C.c_void_p(mech.handle), int(h1), int(h2), int(h3), C.byref(h)))
+            handle = h.value
+        self.handle = handle
+        dims = (C.c_int64 * 6)()
+        _check(_lib.chem_surrogate_info(C.c_void_p(self.handle), dims))
+        self.nin, self.h1, self.h2, self.h3, self.K, self.nparams = (int(v) for v in dims)
+        self.nout_pad = (self.K + 15) // 16 * 16
+        self.norm_len = 2 * self.nin + 2 * self.K + 1
+
+    @classmethod
+    def load(cls, mech: Mechanism, path: str) -> "Surrogate":
+        h = C.c_void_p()
+        _check(_lib.chem_surrogate_load(C.c_void_p(mech.handle), path.encode(), C.byref(h)))
+        return cls(mech, handle=h.value)
+
+    def close(self):
+        if self.handle:
+            _lib.chem_free_surrogate(C.c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def save(self, path: str):
+        _check(_lib.chem_surrogate_save(C.c_void_p(self.handle), path.encode()))
+
+    def set_params(self, params):
+        a, p = _host_f32(params)
+        _check(_lib.chem_surrogate_set_params(C.c_void_p(self.handle), p, a.size))
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(self.nparams, dtype=np.float32)
+        _check(_lib.chem_surrogate_get_params(C.c_void_p(self.handle), a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def set_norm(self, norm):
+        a, p = _host_f64(norm)
+        _check(_lib.chem_surrogate_set_norm(C.c_void_p(self.handle), p, a.size))
+
+    def get_norm(self):
+        import numpy as np
+        a = np.zeros(self.norm_len)
+        _check(_lib.chem_surrogate_get_norm(C.c_void_p(self.handle), a.ctypes.data_as(C.POINTER(C.c_double)), a.size))
+        return a
+
+    def fit_norm(self, T, p, Y, Ynext, dt, stream=None):
+        _check(_lib.chem_surrogate_fit_norm(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
+                                            _ptr(Ynext), Ynext.shape[1], T.shape[0], float(dt), _stream(stream)))
+
+    def encode(self, T, p, Y, X, stream=None):
+        """X: int16 GPU tensor of shape (n, 64) receiving BF16 bit patterns."""
+        _check(_lib.chem_surrogate_encode(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
+                                          T.shape[0], _ptr(X), _stream(stream)))
+
+    def forward(self, X, out, stream=None):
+        _check(_lib.chem_surrogate_forward(C.c_void_p(self.handle), _ptr(X), X.shape[0], _ptr(out),
+                                           out.shape[1], _stream(stream)))
+
+    def apply(self, T, p, Y, out, checks=None, mask=None, stream=None):
+        _check(_lib.chem_surrogate_apply(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
+                                         T.shape[0], _ptr(out), out.shape[1],
+                                         C.byref(checks) if checks is not None else None, _ptr(mask),
+                                         _stream(stream)))
+
+    def infer(self, T, p, Y, dt, opts=None, checks=None, mask=None, status=None, fallback_count=None,
+              stream=None):
+        _check(_lib.chem_surrogate_infer(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
+                                         T.shape[0], float(dt), C.byref(opts) if opts is not None else None,
+                                         C.byref(checks) if checks is not None else None, _ptr(mask),
+                                         _ptr(status), _ptr(fallback_count), _stream(stream)))
+
+    def grad(self, X, Yt, stream=None) -> float:
+        loss = C.c_double()
+        _check(_lib.chem_surrogate_grad(C.c_void_p(self.handle), _ptr(X), _ptr(Yt), Yt.shape[1], X.shape[0],
+                                        C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def get_grads(self):
+        import numpy as np
+        a = np.zeros(self.nparams, dtype=np.float32)
+        _check(_lib.chem_surrogate_get_grads(C.c_void_p(self.handle), a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def set_grads(self, g):
+        a, p = _host_f32(g)
+        _check(_lib.chem_surrogate_set_grads(C.c_void_p(self.handle), p, a.size))
+
+    def adam(self, lr: float, stream=None):
+        _check(_lib.chem_surrogate_adam(C.c_void_p(self.handle), float(lr), _stream(stream)))
+
+    def train(self, T, p, Y, Ynext, epochs: int, batch: int, lr0: float = 1e-3, lr1: float = 1e-5, order=None,
+              stream=None):
+        import numpy as np
+        losses = np.zeros(int(epochs))
+        _check(_lib.chem_surrogate_train(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
+                                         _ptr(Ynext), Ynext.shape[1], T.shape[0], _ptr(order), int(epochs), int(batch),
+                                         float(lr0), float(lr1), losses.ctypes.data_as(C.POINTER(C.c_double)),
+                                         _stream(stream)))
+        return losses

@@ -794,7 +794,9 @@ __global__ void __launch_bounds__(64) bdf_queue_kernel(Mech mech, double *__rest
                                                        unsigned long long *__restrict__ queue)
 {
     __shared__ double nord[kLdsRows * (Mech::K + 1) * 64];
-    CellIO io{T, p, Y, ldY, n, status, counters, &prm};
+    // a device-side count (cells compacted by an earlier kernel) bounds the queue
+    const int64_t nn = prm.n_dev ? (*prm.n_dev < n ? *prm.n_dev : n) : n;
+    CellIO io{T, p, Y, ldY, nn, status, counters, &prm};
     run_lanes(mech, io, dt, queue, nord);
 }
 

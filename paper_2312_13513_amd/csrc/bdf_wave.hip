@@ -727,7 +727,9 @@ __global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables 
                                                       double *__restrict__ qscratch)
 {
     __shared__ WaveLds<NP, LT> L;
-    CellIO io{T, p, Y, ldY, n, status, counters, &prm};
+    // a device-side count (cells compacted by an earlier kernel) bounds the queue
+    const int64_t nn = prm.n_dev ? (*prm.n_dev < n ? *prm.n_dev : n) : n;
+    CellIO io{T, p, Y, ldY, nn, status, counters, &prm};
     // per-wave reaction scratch (7 R doubles) in global memory, one slice per wave
     double *qbuf = qscratch + (size_t)blockIdx.x * 7 * m.R;
     run_wave<NP, LT>(m, wt, io, dt, queue, qbuf, L);

@@ -44,7 +44,8 @@ struct DevMechView {
 struct BdfParams {
     double rtol, atol;
     int32_t max_steps;
-    int32_t jac_batch;   // lanes of a wave that wait before a Jacobian is evaluated
+    int32_t jac_batch;      // lanes of a wave that wait before a Jacobian is evaluated
+    const int64_t *n_dev;   // if not NULL: integrate only the first *n_dev cells
 };
 
 // Launchers of the table-driven kernels.  Return hipError_t of the launch.

@@ -10,32 +10,17 @@
 #include <string>
 #include <vector>
 
-#include "chem.h"
-#include "bdf_driver.h"
-#include "bdf_wave.h"
+#include "host_common.h"
+
+using chem_host::check_hip;
+using chem_host::fail;
+using chem_host::HostMech;
+using chem_host::HostRxn;
+using chem_host::is_device_ptr;
 
 namespace {
 
 thread_local std::string g_err = "no error";
-
-int fail(int code, const std::string &msg)
-{
-    g_err = msg;
-    return code;
-}
-
-struct HostRxn {
-    std::vector<std::pair<int, int>> reac, prod;   // (species, coefficient)
-    double A = 0, b = 0, Ea = 0;
-};
-
-struct HostMech {
-    int K = 0, R = 0, E = 0;
-    std::vector<double> aw;                 // atomic weights, g/mol
-    std::vector<std::vector<int>> counts;   // K x E
-    std::vector<std::vector<double>> nasa;  // K x 17
-    std::vector<HostRxn> rxn;
-};
 
 // Whitespace-token reader with error reporting.
 class Tokens {
@@ -148,21 +133,6 @@ int parse_mech(const char *path, HostMech &m)
 
 }  // namespace
 
-struct chem_mech_s {
-    int device = 0;
-    HostMech host;
-    std::vector<double> W;
-    chem::DevMechView view{};
-    void *dev_block = nullptr;
-    unsigned long long *queues = nullptr;   // work-queue counters, one per in-flight call
-    unsigned next_queue = 0;
-    const chem::GenEntry *gen = nullptr;    // mechanism-specialised kernels, if compiled
-    std::string variant = "table";
-    chem::WaveTables wave{};                // species -> reaction incidence (wave kernel)
-    double *wave_scratch = nullptr;         // per-wave reaction buffers (7 R doubles each)
-    int wave_slots = 0;
-};
-
 namespace {
 constexpr int kQueues = 64;
 
@@ -191,6 +161,16 @@ void fill_range(const double *a, double *out)
     out[13] = a[4] / 4.0;
 }
 
+}  // namespace
+
+namespace chem_host {
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
 int check_hip(hipError_t e, const char *what)
 {
     if (e == hipSuccess) return CHEM_OK;
@@ -208,7 +188,57 @@ bool is_device_ptr(const void *p)
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
-}  // namespace
+}  // namespace chem_host
+
+namespace chem_host {
+
+int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
+                    double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
+                    hipStream_t stream, const int64_t *n_dev)
+{
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be finite and > 0");
+    chem_opts o;
+    chem_default_opts(&o);
+    if (opts) o = *opts;
+    if (!(o.rtol > 0.0) || !(o.atol > 0.0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol))
+        return fail(CHEM_EINVAL, "rtol and atol must be finite and > 0");
+    if (o.max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
+    if (o.precision != 0 && o.precision != 1) return fail(CHEM_EINVAL, "precision must be 0 or 1");
+    if (o.schedule < -1 || o.schedule > 1) return fail(CHEM_EINVAL, "unknown schedule");
+    if (o.block != 0 && o.block != 64) return fail(CHEM_EUNSUP, "block must be 0 or 64");
+    if (n == 0) return CHEM_OK;
+    if ((status && !is_device_ptr(status)) || (counters && !is_device_ptr(counters)))
+        return fail(CHEM_EINVAL, "status and counters must be device pointers or NULL");
+    const int K = m->host.K;
+    const bool thread_ok = m->gen != nullptr || chem::thread_kernel_supports(K);
+    const bool wave_ok = chem::wave_kernel_rows(K + 1) > 0;
+    // automatic choice: the wave kernel for mixed precision and for mechanisms
+    // without a one-thread-per-cell kernel
+    const int sched = o.schedule >= 0 ? o.schedule : ((o.precision == 1 || !thread_ok) ? 1 : 0);
+    if (sched == 0 && !thread_ok)
+        return fail(CHEM_EUNSUP, "no one-thread-per-cell kernel is built for K = " + std::to_string(K));
+    if (sched == 0 && o.precision != 0)
+        return fail(CHEM_EUNSUP, "the one-thread-per-cell schedule computes in FP64 only");
+    if (sched == 1 && !wave_ok)
+        return fail(CHEM_EUNSUP, "the wave schedule supports at most 63 species");
+    if (o.jac_batch < 0 || o.jac_batch > 64) return fail(CHEM_EINVAL, "jac_batch must be in 0..64");
+    chem::BdfParams prm{o.rtol, o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16, n_dev};
+    // each call takes its own queue counter (64 rotate), so that calls in
+    // flight on different streams do not share one
+    unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);
+    hipError_t e;
+    if (sched == 1)
+        e = chem::launch_bdf_wave(m->view, m->wave, T, p, Y, ldY, n, dt, prm, status, counters, queue,
+                                  m->wave_scratch, m->wave_slots, o.precision == 1, stream);
+    else if (m->gen)
+        e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, stream);
+    else
+        e = chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status, counters, queue,
+                                    stream);
+    return check_hip(e, "integrator launch");
+}
+
+}  // namespace chem_host
 
 extern "C" {
 
@@ -418,46 +448,8 @@ int chem_integrate(chem_mech m, double *T, const double *p, double *Y, int64_t l
 {
     int rc = check_state_args(m, T, p, Y, ldY, n);
     if (rc != CHEM_OK) return rc;
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be finite and > 0");
-    chem_opts o;
-    chem_default_opts(&o);
-    if (opts) o = *opts;
-    if (!(o.rtol > 0.0) || !(o.atol > 0.0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol))
-        return fail(CHEM_EINVAL, "rtol and atol must be finite and > 0");
-    if (o.max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
-    if (o.precision != 0 && o.precision != 1) return fail(CHEM_EINVAL, "precision must be 0 or 1");
-    if (o.schedule < -1 || o.schedule > 1) return fail(CHEM_EINVAL, "unknown schedule");
-    if (o.block != 0 && o.block != 64) return fail(CHEM_EUNSUP, "block must be 0 or 64");
-    if (n == 0) return CHEM_OK;
-    if ((status && !is_device_ptr(status)) || (counters && !is_device_ptr(counters)))
-        return fail(CHEM_EINVAL, "status and counters must be device pointers or NULL");
-    const int K = m->host.K;
-    const bool thread_ok = m->gen != nullptr || chem::thread_kernel_supports(K);
-    const bool wave_ok = chem::wave_kernel_rows(K + 1) > 0;
-    // automatic choice: the wave kernel for mixed precision and for mechanisms
-    // without a one-thread-per-cell kernel
-    const int sched = o.schedule >= 0 ? o.schedule : ((o.precision == 1 || !thread_ok) ? 1 : 0);
-    if (sched == 0 && !thread_ok)
-        return fail(CHEM_EUNSUP, "no one-thread-per-cell kernel is built for K = " + std::to_string(K));
-    if (sched == 0 && o.precision != 0)
-        return fail(CHEM_EUNSUP, "the one-thread-per-cell schedule computes in FP64 only");
-    if (sched == 1 && !wave_ok)
-        return fail(CHEM_EUNSUP, "the wave schedule supports at most 63 species");
-    if (o.jac_batch < 0 || o.jac_batch > 64) return fail(CHEM_EINVAL, "jac_batch must be in 0..64");
-    chem::BdfParams prm{o.rtol, o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16};
-    // each call takes its own queue counter (64 rotate), so that calls in
-    // flight on different streams do not share one
-    unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);
-    hipError_t e;
-    if (sched == 1)
-        e = chem::launch_bdf_wave(m->view, m->wave, T, p, Y, ldY, n, dt, prm, status, counters, queue,
-                                  m->wave_scratch, m->wave_slots, o.precision == 1, (hipStream_t)stream);
-    else if (m->gen)
-        e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, (hipStream_t)stream);
-    else
-        e = chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status, counters, queue,
-                                    (hipStream_t)stream);
-    return check_hip(e, "integrator launch");
+    return chem_host::integrate_cells(m, T, p, Y, ldY, n, dt, opts, status, counters,
+                                      (hipStream_t)stream, nullptr);
 }
 
 int chem_eval_rhs(chem_mech m, const double *T, const double *p, const double *Y, int64_t ldY,

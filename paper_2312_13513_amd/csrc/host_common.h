@@ -1,0 +1,60 @@
+// Host-side pieces shared by the integrator and surrogate halves of the C ABI:
+// the mechanism handle, error reporting and the internal integrate call.
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "chem.h"
+#include "bdf_driver.h"
+#include "bdf_wave.h"
+
+namespace chem_host {
+
+struct HostRxn {
+    std::vector<std::pair<int, int>> reac, prod;   // (species, coefficient)
+    double A = 0, b = 0, Ea = 0;
+};
+
+struct HostMech {
+    int K = 0, R = 0, E = 0;
+    std::vector<double> aw;                 // atomic weights, g/mol
+    std::vector<std::vector<int>> counts;   // K x E
+    std::vector<std::vector<double>> nasa;  // K x 17
+    std::vector<HostRxn> rxn;
+};
+
+// Records msg as the calling thread's last error and returns code.
+int fail(int code, const std::string &msg);
+// CHEM_OK for hipSuccess, else CHEM_EHIP with the runtime's message.
+int check_hip(hipError_t e, const char *what);
+bool is_device_ptr(const void *p);
+
+}  // namespace chem_host
+
+struct chem_mech_s {
+    int device = 0;
+    chem_host::HostMech host;
+    std::vector<double> W;
+    chem::DevMechView view{};
+    void *dev_block = nullptr;
+    unsigned long long *queues = nullptr;   // work-queue counters, one per in-flight call
+    unsigned next_queue = 0;
+    const chem::GenEntry *gen = nullptr;    // mechanism-specialised kernels, if compiled
+    std::string variant = "table";
+    chem::WaveTables wave{};                // species -> reaction incidence (wave kernel)
+    double *wave_scratch = nullptr;         // per-wave reaction buffers (7 R doubles each)
+    int wave_slots = 0;
+};
+
+namespace chem_host {
+
+// chem_integrate after argument checks of the state arrays; when n_dev is not
+// NULL the kernels integrate the first *n_dev cells (read on the device, at
+// most n), so that a count produced by an earlier kernel needs no host sync.
+int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
+                    double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
+                    hipStream_t stream, const int64_t *n_dev);
+
+}  // namespace chem_host

@@ -1,0 +1,603 @@
+// Learned chemistry surrogate on gfx950: BF16 MFMA GEMMs with fused
+// bias/GELU epilogues for the forward pass and for both backward products,
+// the input encoding (Box-Cox of the mass fractions, z-scores), the decode
+// with temperature recovery and the acceptance checks, cell compaction for
+// the integrator fallback, and the Adam update.
+//
+// The network follows the paper's use of a DNN for the chemistry source
+// (Section 2): fully connected layers with GELU activations trained with
+// Adam; here its input is [T, p, BoxCox(Y)] and its output the z-scored
+// change of the mass fractions over one flow step.
+
+#include "surrogate.h"
+
+namespace chem {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest, ties to even; NaN -> quiet NaN.
+__device__ __forceinline__ bf16_t to_bf16(float f)
+{
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float u)
+{
+    return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f));
+}
+
+__device__ __forceinline__ float gelu_grad(float u)
+{
+    return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) +
+           u * expf(-0.5f * u * u) * 0.39894228040143268f;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: 64 x 64 output tile per 256-thread block, four waves in 2 x 2, each
+// wave 32 x 32 = 2 x 2 MFMA 16x16x32 tiles; K in steps of 32 through LDS.
+// ---------------------------------------------------------------------------
+constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
+typedef bf16_t TileRow[kBK + kPad];
+
+// lds[r][k] = X(r0 + r, k0 + k), zero outside [0,R) x [0,Kd).
+__device__ __forceinline__ void stage_tile(const bf16_t *X, int64_t sr, int64_t sk, int R, int Kd,
+                                           int r0, int k0, TileRow *lds)
+{
+    const int t = threadIdx.x;
+    if (sk == 1) {
+        // rows contiguous along k: 16-byte chunks of 8 k-values
+        const int r = t >> 2, kc = (t & 3) * 8;
+        const int gr = r0 + r, gk = k0 + kc;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gr < R && gk < Kd) v = *(const uint4 *)(X + (int64_t)gr * sr + gk);
+        *(uint4 *)&lds[r][kc] = v;
+    } else {
+        // contiguous along r: 8 r-values of one k, transposed into LDS
+        const int k = t >> 3, rc = (t & 7) * 8;
+        const int gr = r0 + rc, gk = k0 + k;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gr < R && gk < Kd) v = *(const uint4 *)(X + (int64_t)gk * sk + gr);
+        const bf16_t *e = (const bf16_t *)&v;
+#pragma unroll
+        for (int i = 0; i < 8; i++) lds[rc + i][k] = e[i];
+    }
+}
+
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) TileRow As[kBM];
+    __shared__ __attribute__((aligned(16))) TileRow Bs[kBN];
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int kk = (lane >> 4) * 8;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+        stage_tile(g.A, g.sam, g.sak, g.M, g.K, m0, k0, As);
+        stage_tile(g.B, g.sbn, g.sbk, g.N, g.K, n0, k0, Bs);
+        __syncthreads();
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; i++) __builtin_memcpy(&a[i], &As[wm + i * 16 + (lane & 15)][kk], 16);
+#pragma unroll
+        for (int j = 0; j < 2; j++) __builtin_memcpy(&b[j], &Bs[wn + j * 16 + (lane & 15)][kk], 16);
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // D layout of a 16x16 MFMA tile: lane l holds rows 4*(l/16) + r, column l%16
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+                const int n = n0 + wn + j * 16 + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                const float v = acc[i][j][r];
+                switch (g.epi) {
+                case kEpiBiasF32:
+                    g.outf[(int64_t)m * g.ldf + n] = v + (g.bias ? g.bias[n] : 0.0f);
+                    break;
+                case kEpiBiasGeluBf16: {
+                    const float u = v + (g.bias ? g.bias[n] : 0.0f);
+                    if (g.outf) g.outf[(int64_t)m * g.ldf + n] = u;
+                    g.outh[(int64_t)m * g.ldh + n] = to_bf16(gelu(u));
+                    break;
+                }
+                case kEpiGeluGradBf16:
+                    g.outh[(int64_t)m * g.ldh + n] = to_bf16(v * gelu_grad(g.u[(int64_t)m * g.ldu + n]));
+                    break;
+                default:
+                    g.outf[(int64_t)m * g.ldf + n] = v;
+                    break;
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// encoding
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double boxcox(double y) { return (pow(fmax(y, 0.0), 0.1) - 1.0) / 0.1; }
+
+__global__ void __launch_bounds__(256) encode_kernel(const double *__restrict__ T,
+                                                     const double *__restrict__ p,
+                                                     const double *__restrict__ Y, int64_t ldY,
+                                                     int64_t n, int K, int nin_pad,
+                                                     const double *__restrict__ norm,
+                                                     bf16_t *__restrict__ X)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int nin = K + 2;
+    const double *mu = norm, *sg = norm + nin;
+    bf16_t *row = X + i * nin_pad;
+    for (int j = 0; j < nin_pad; j += 8) {
+        uint4 pk;
+        bf16_t *v = (bf16_t *)&pk;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int f = j + e;
+            double z = 0.0;
+            if (f < nin) {
+                const double raw = f == 0 ? T[i] : (f == 1 ? p[i] : boxcox(Y[(int64_t)(f - 2) * ldY + i]));
+                if (sg[f] >= 1e-12) z = (raw - mu[f]) / sg[f];
+            }
+            v[e] = to_bf16((float)z);
+        }
+        *(uint4 *)(row + j) = pk;
+    }
+}
+
+__global__ void __launch_bounds__(256) targets_kernel(const double *__restrict__ Y, int64_t ldY,
+                                                      const double *__restrict__ Yn, int64_t ldYn,
+                                                      int64_t n, int K, int nout_pad,
+                                                      const double *__restrict__ mu,
+                                                      const double *__restrict__ sg,
+                                                      float *__restrict__ Yt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < nout_pad; k++) {
+        float v = 0.0f;
+        if (k < K && sg[k] >= 1e-12) {
+            const double d = Yn[(int64_t)k * ldYn + i] - Y[(int64_t)k * ldY + i];
+            v = (float)((d - mu[k]) / sg[k]);
+        }
+        Yt[i * nout_pad + k] = v;
+    }
+}
+
+// one block per column; fixed summation order (per-thread strided partial
+// sums, then a tree), so the result does not depend on timing
+__global__ void __launch_bounds__(256) fit_norm_kernel(const double *__restrict__ T,
+                                                       const double *__restrict__ p,
+                                                       const double *__restrict__ Y, int64_t ldY,
+                                                       const double *__restrict__ Yn, int64_t ldYn,
+                                                       int64_t n, int K, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    const int nin = K + 2;
+    auto value = [&](int64_t i) -> double {
+        if (c == 0) return T[i];
+        if (c == 1) return p[i];
+        if (c < nin) return boxcox(Y[(int64_t)(c - 2) * ldY + i]);
+        return Yn[(int64_t)(c - nin) * ldYn + i] - Y[(int64_t)(c - nin) * ldY + i];
+    };
+    auto block_sum = [&](double v) -> double {
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        const double r = red[0];
+        __syncthreads();
+        return r;
+    };
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += value(i);
+    const double mean = block_sum(s) / (double)n;
+    double q = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double d = value(i) - mean;
+        q += d * d;
+    }
+    const double var = block_sum(q) / (double)n;
+    if (threadIdx.x == 0) {
+        if (c < nin) {
+            out[c] = mean;
+            out[nin + c] = sqrt(var);
+        } else {
+            out[2 * nin + (c - nin)] = mean;
+            out[2 * nin + K + (c - nin)] = sqrt(var);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// decode, temperature recovery, checks
+// ---------------------------------------------------------------------------
+constexpr double kRuS = 8.31446261815324;
+
+// mass-specific enthalpy and cp of the mixture Y[k * ys]
+__device__ void mix_h_cp(const ApplyArgs &a, double T, const double *Y, int ys, double &hm, double &cm)
+{
+    double h = 0.0, c = 0.0;
+    const double invT = 1.0 / T;
+    for (int k = 0; k < a.K; k++) {
+        const double *s = a.species + k * kSpeciesLen;
+        const double *r = (!a.two_range || T < s[0]) ? s + 1 : s + 1 + kRangeLen;
+        const double cp = r[0] + T * (r[1] + T * (r[2] + T * (r[3] + T * r[4])));
+        const double hrt = r[0] + T * (r[7] + T * (r[8] + T * (r[9] + T * r[10]))) + r[5] * invT;
+        const double y = Y[(int64_t)k * ys];
+        h += y * kRuS * T * hrt / a.W[k];
+        c += y * kRuS * cp / a.W[k];
+    }
+    hm = h;
+    cm = c;
+}
+
+__global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restrict__ T,
+                                                    const double *__restrict__ p,
+                                                    double *__restrict__ Y, int64_t ldY, int64_t n,
+                                                    int64_t base, const float *__restrict__ out,
+                                                    int nout_pad, int32_t *__restrict__ mask,
+                                                    int32_t *__restrict__ status,
+                                                    int32_t *__restrict__ list,
+                                                    int64_t *__restrict__ count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool reject = false;
+    if (i < n) {
+        (void)p;
+        const int K = a.K;
+        const double T0 = T[i];
+        double Y1[kMaxSurrSpecies];
+        bool ok = true;
+        double sum = 0.0, ymin = 1e300;
+        for (int k = 0; k < K; k++) {
+            const double y = Y[(int64_t)k * ldY + i];
+            const double v = y + a.mu_y[k] + a.sig_y[k] * (double)out[i * nout_pad + k];
+            Y1[k] = v;
+            ok = ok && isfinite(v);
+            sum += v;
+            ymin = fmin(ymin, v);
+        }
+        // element residual relative to the element content of the input
+        for (int e = 0; ok && e < a.E; e++) {
+            double res = 0.0, ref = 0.0;
+            for (int k = 0; k < K; k++) {
+                const double nk = a.counts[e * K + k] / a.W[k];
+                res += nk * (Y1[k] - Y[(int64_t)k * ldY + i]);
+                ref += nk * Y[(int64_t)k * ldY + i];
+            }
+            if (fabs(res) / fmax(ref, 1e-12) > a.elem_tol) ok = false;
+        }
+        if (ok && fabs(sum - 1.0) > a.sum_tol) ok = false;
+        if (ok && ymin < -a.neg_tol) ok = false;
+        double Tn = T0;
+        if (ok) {
+            double s2 = 0.0;
+            for (int k = 0; k < K; k++) {
+                Y1[k] = fmax(Y1[k], 0.0);
+                s2 += Y1[k];
+            }
+            for (int k = 0; k < K; k++) Y1[k] = Y1[k] / s2;
+            double h0;
+            // enthalpy of the input state
+            {
+                double h = 0.0;
+                const double invT = 1.0 / T0;
+                for (int k = 0; k < K; k++) {
+                    const double *s = a.species + k * kSpeciesLen;
+                    const double *r = (!a.two_range || T0 < s[0]) ? s + 1 : s + 1 + kRangeLen;
+                    const double hrt = r[0] + T0 * (r[7] + T0 * (r[8] + T0 * (r[9] + T0 * r[10]))) + r[5] * invT;
+                    h += Y[(int64_t)k * ldY + i] * kRuS * T0 * hrt / a.W[k];
+                }
+                h0 = h;
+            }
+            // Newton on h(T, Y2) = h0 from T0; |dT| < 1e-10 K, at most 20
+            // iterations, T kept in [200, 3500] K
+            bool conv = false;
+            double Tk = T0;
+            for (int it = 0; it < 20; it++) {
+                double hm, cm;
+                mix_h_cp(a, Tk, Y1, 1, hm, cm);
+                const double dT = -(hm - h0) / cm;
+                Tk += dT;
+                Tk = fmin(fmax(Tk, 200.0), 3500.0);
+                if (fabs(dT) < 1e-10) {
+                    conv = true;
+                    break;
+                }
+            }
+            if (!conv || !(Tk >= a.T_out_min && Tk <= a.T_out_max)) ok = false;
+            if (ok && (T0 < a.T_in_min || T0 > a.T_in_max)) ok = false;
+            if (ok && a.dT_gate > 0.0 && fabs(Tk - T0) > a.dT_gate) ok = false;
+            Tn = Tk;
+        }
+        if (ok) {
+            T[i] = Tn;
+            for (int k = 0; k < K; k++) Y[(int64_t)k * ldY + i] = Y1[k];
+        }
+        if (mask) mask[i] = ok ? 0 : 1;
+        if (status) status[i] = 0;
+        reject = !ok;
+    }
+    // wave-aggregated append of the rejected cells
+    const unsigned long long bal = __ballot(reject);
+    if (bal) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((long long)bal) - 1;
+        unsigned long long slot = 0;
+        if (lane == leader) slot = atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(bal));
+        slot = __shfl(slot, leader);
+        if (reject) {
+            const unsigned long long rank = __popcll(bal & ((1ull << lane) - 1ull));
+            list[slot + rank] = (int32_t)(base + i);
+        }
+    }
+}
+
+__global__ void zero_i64_kernel(int64_t *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) gather_cells_kernel(const int32_t *__restrict__ list,
+                                                           const int64_t *__restrict__ count,
+                                                           int64_t cap, const double *__restrict__ T,
+                                                           const double *__restrict__ p,
+                                                           const double *__restrict__ Y, int64_t ldY,
+                                                           int K, double *__restrict__ cT,
+                                                           double *__restrict__ cp,
+                                                           double *__restrict__ cY)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cnt = *count < cap ? *count : cap;
+    if (j >= cnt) return;
+    const int64_t i = list[j];
+    cT[j] = T[i];
+    cp[j] = p[i];
+    for (int k = 0; k < K; k++) cY[(int64_t)k * cap + j] = Y[(int64_t)k * ldY + i];
+}
+
+__global__ void __launch_bounds__(256) scatter_cells_kernel(const int32_t *__restrict__ list,
+                                                            const int64_t *__restrict__ count,
+                                                            int64_t cap, const double *__restrict__ cT,
+                                                            const double *__restrict__ cY,
+                                                            const int32_t *__restrict__ cstatus, int K,
+                                                            double *__restrict__ T,
+                                                            double *__restrict__ Y, int64_t ldY,
+                                                            int32_t *__restrict__ status)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cnt = *count < cap ? *count : cap;
+    if (j >= cnt) return;
+    const int64_t i = list[j];
+    T[i] = cT[j];
+    for (int k = 0; k < K; k++) Y[(int64_t)k * ldY + i] = cY[(int64_t)k * cap + j];
+    if (status) status[i] = cstatus ? cstatus[j] : 0;
+}
+
+// ---------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) gather_rows_kernel(const int32_t *__restrict__ order,
+                                                          int64_t start, int64_t rows,
+                                                          const bf16_t *__restrict__ X, int nin_pad,
+                                                          const float *__restrict__ Yt, int nout_pad,
+                                                          bf16_t *__restrict__ Xb,
+                                                          float *__restrict__ Yb)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int64_t src = order ? (int64_t)order[start + r] : start + r;
+    const uint4 *xs = (const uint4 *)(X + src * nin_pad);
+    uint4 *xd = (uint4 *)(Xb + r * nin_pad);
+    for (int j = 0; j < nin_pad / 8; j++) xd[j] = xs[j];
+    for (int j = 0; j < nout_pad; j++) Yb[r * nout_pad + j] = Yt[src * nout_pad + j];
+}
+
+__global__ void __launch_bounds__(256) loss_grad_kernel(const float *__restrict__ out,
+                                                        const float *__restrict__ Yb, int rows, int K,
+                                                        int nout_pad, bf16_t *__restrict__ dOut,
+                                                        double *__restrict__ partial)
+{
+    __shared__ double red[256];
+    const int64_t total = (int64_t)rows * nout_pad;
+    const float scale = 2.0f / ((float)rows * (float)K);
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int col = (int)(e % nout_pad);
+        float d = 0.0f;
+        if (col < K) {
+            d = out[e] - Yb[e];
+            s += (double)d * (double)d;
+        }
+        dOut[e] = to_bf16(scale * d);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void sum_partials_kernel(const double *__restrict__ partial, int np, double *acc)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < np; i++) s += partial[i];
+        *acc += s;
+    }
+}
+
+__global__ void __launch_bounds__(256) bias_grad_kernel(const bf16_t *__restrict__ d, int rows, int N,
+                                                        int ld, float *__restrict__ db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; r++) s += __uint_as_float((unsigned)d[(int64_t)r * ld + n] << 16);
+    db[n] = s;
+}
+
+__global__ void __launch_bounds__(256) adam_kernel(AdamArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const float g = a.g[i];
+    const float m = a.beta1 * a.m[i] + a.omb1 * g;
+    const float v = a.beta2 * a.v[i] + a.omb2 * g * g;
+    a.m[i] = m;
+    a.v[i] = v;
+    const float mh = m / a.bc1, vh = v / a.bc2;
+    a.p[i] -= a.lr * mh / (sqrtf(vh) + a.eps);
+}
+
+__global__ void __launch_bounds__(256) to_bf16_kernel(const float *__restrict__ src,
+                                                      bf16_t *__restrict__ dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = to_bf16(src[i]);
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_gemm_bf16(const GemmArgs &g, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM));
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode(const double *T, const double *p, const double *Y, int64_t ldY, int64_t n,
+                         int K, int nin_pad, const double *norm, bf16_t *X, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(encode_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, T, p, Y, ldY, n, K,
+                       nin_pad, norm, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_targets(const double *Y, int64_t ldY, const double *Yn, int64_t ldYn, int64_t n,
+                          int K, int nout_pad, const double *mu_y, const double *sig_y, float *Yt,
+                          hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(targets_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, Y, ldY, Yn, ldYn, n,
+                       K, nout_pad, mu_y, sig_y, Yt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_norm(const double *T, const double *p, const double *Y, int64_t ldY,
+                           const double *Yn, int64_t ldYn, int64_t n, int K, double *out,
+                           hipStream_t s)
+{
+    if (n <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fit_norm_kernel, dim3((unsigned)(2 * K + 2)), dim3(256), 0, s, T, p, Y, ldY,
+                       Yn, ldYn, n, K, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const ApplyArgs &a, double *T, const double *p, double *Y, int64_t ldY,
+                        int64_t n, int64_t base, const float *out, int nout_pad, int32_t *mask,
+                        int32_t *status, int32_t *list, int64_t *count, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(apply_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, ldY, n,
+                       base, out, nout_pad, mask, status, list, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_i64_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_cells(const int32_t *list, const int64_t *count, int64_t cap,
+                               const double *T, const double *p, const double *Y, int64_t ldY,
+                               int K, double *cT, double *cp, double *cY, hipStream_t s)
+{
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_cells_kernel, dim3(blocks_for(cap, 256)), dim3(256), 0, s, list, count,
+                       cap, T, p, Y, ldY, K, cT, cp, cY);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_cells(const int32_t *list, const int64_t *count, int64_t cap,
+                                const double *cT, const double *cY, const int32_t *cstatus, int K,
+                                double *T, double *Y, int64_t ldY, int32_t *status, hipStream_t s)
+{
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_cells_kernel, dim3(blocks_for(cap, 256)), dim3(256), 0, s, list, count,
+                       cap, cT, cY, cstatus, K, T, Y, ldY, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const int32_t *order, int64_t start, int64_t rows, const bf16_t *X,
+                              int nin_pad, const float *Yt, int nout_pad, bf16_t *Xb, float *Yb,
+                              hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for(rows, 256)), dim3(256), 0, s, order, start,
+                       rows, X, nin_pad, Yt, nout_pad, Xb, Yb);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_grad(const float *out, const float *Yb, int rows, int K, int nout_pad,
+                            bf16_t *dOut, double *loss_acc, hipStream_t s)
+{
+    // fixed grid: partial sums land in loss_acc[1 ..], summed in order into loss_acc[0]
+    constexpr int kParts = 64;
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(kParts), dim3(256), 0, s, out, Yb, rows, K, nout_pad,
+                       dOut, loss_acc + 1);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, loss_acc + 1, kParts, loss_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_bias_grad(const bf16_t *d, int rows, int N, int ld, float *db, hipStream_t s)
+{
+    hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, d, rows, N, ld, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *src, bf16_t *dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace chem

@@ -1,0 +1,838 @@
+// Host side of the learned surrogate: parameter and normalisation storage,
+// workspaces, the forward/backward/Adam sequence, training loop, inference
+// with per-cell fallback to the integrator, and the weights file.
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <iterator>
+#include <string>
+#include <vector>
+
+#include "host_common.h"
+#include "surrogate.h"
+
+using chem::bf16_t;
+using chem_host::check_hip;
+using chem_host::fail;
+using chem_host::is_device_ptr;
+
+namespace {
+
+constexpr int kInPad = 64;            // network input padded for the MFMA K steps
+constexpr int64_t kChunk = 262144;    // rows per inference pass (bounds the activations)
+constexpr double kBeta1 = 0.9, kBeta2 = 0.999, kEps = 1e-8;
+constexpr double kPi = 3.14159265358979323846;
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int grow(size_t want)
+    {
+        if (want <= bytes) return CHEM_OK;
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CHEM_ENOMEM, "surrogate workspace allocation failed");
+        }
+        bytes = want;
+        return CHEM_OK;
+    }
+    void release()
+    {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+// Carves aligned sub-buffers out of one allocation.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(int64_t count)
+    {
+        T *r = (T *)(base + off);
+        off += ((size_t)count * sizeof(T) + 255) & ~size_t(255);
+        return r;
+    }
+};
+
+template <typename T>
+size_t carve_size(int64_t count) { return ((size_t)count * sizeof(T) + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct chem_surr_s {
+    chem_mech mech = nullptr;
+    int device = 0;
+    int K = 0, E = 0, nin = 0, h[3] = {0, 0, 0}, nout_pad = 0;
+    int in_l[4], out_l[4];            // padded GEMM shapes of the four layers
+    int64_t off_W[4], off_b[4], n_pad = 0, n_logical = 0;
+    float *master = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
+    bf16_t *wbf = nullptr;
+    double *norm_dev = nullptr;       // mu_x, sig_x, mu_y, sig_y
+    double *counts_dev = nullptr;     // [E][K]
+    int64_t *scalars = nullptr;       // [0] fallback count
+    double *loss_dev = nullptr;       // [0] accumulated loss, [1..64] partials
+    void *block = nullptr;
+    std::vector<double> norm;         // host copy incl. dt
+    bool norm_set = false;
+    int64_t adam_t = 0;
+    DevBuf act;                       // activations of one chunk / batch
+    int64_t act_rows = 0;
+    bool act_train = false;
+    DevBuf fb;                        // fallback compaction
+    int64_t fb_cap = 0;
+};
+
+namespace {
+
+int check_surr(chem_surr s)
+{
+    if (!s) return fail(CHEM_EINVAL, "surrogate handle is NULL");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != s->device)
+        return fail(CHEM_EINVAL, "the current HIP device is not the surrogate's device");
+    return CHEM_OK;
+}
+
+int64_t norm_len(const chem_surr_s *s) { return 2 * (int64_t)s->nin + 2 * (int64_t)s->K + 1; }
+
+// Activation buffers of `rows` rows: X, H1..H3 (BF16), OUT (FP32); with
+// `train` also U1..U3 (FP32), Yb (FP32), dOut, D1..D3 (BF16).
+struct Acts {
+    bf16_t *X, *H[3], *dOut, *D[3];
+    float *OUT, *U[3], *Yb;
+};
+
+size_t acts_bytes(const chem_surr_s *s, int64_t rows, bool train)
+{
+    size_t b = carve_size<bf16_t>(rows * kInPad) + carve_size<float>(rows * s->nout_pad);
+    for (int l = 0; l < 3; l++) b += carve_size<bf16_t>(rows * s->h[l]);
+    if (train) {
+        for (int l = 0; l < 3; l++) b += carve_size<float>(rows * s->h[l]) + carve_size<bf16_t>(rows * s->h[l]);
+        b += carve_size<float>(rows * s->nout_pad) + carve_size<bf16_t>(rows * s->nout_pad);
+    }
+    return b;
+}
+
+int ensure_acts(chem_surr_s *s, int64_t rows, bool train)
+{
+    if (rows <= s->act_rows && (!train || s->act_train)) return CHEM_OK;
+    const int64_t r = rows > s->act_rows ? rows : s->act_rows;
+    const bool t = train || s->act_train;
+    int rc = s->act.grow(acts_bytes(s, r, t));
+    if (rc != CHEM_OK) return rc;
+    s->act_rows = r;
+    s->act_train = t;
+    return CHEM_OK;
+}
+
+Acts carve_acts(const chem_surr_s *s)
+{
+    Acts a{};
+    Carver c{(char *)s->act.p};
+    const int64_t rows = s->act_rows;
+    a.X = c.take<bf16_t>(rows * kInPad);
+    a.OUT = c.take<float>(rows * s->nout_pad);
+    for (int l = 0; l < 3; l++) a.H[l] = c.take<bf16_t>(rows * s->h[l]);
+    if (s->act_train) {
+        for (int l = 0; l < 3; l++) {
+            a.U[l] = c.take<float>(rows * s->h[l]);
+            a.D[l] = c.take<bf16_t>(rows * s->h[l]);
+        }
+        a.Yb = c.take<float>(rows * s->nout_pad);
+        a.dOut = c.take<bf16_t>(rows * s->nout_pad);
+    }
+    return a;
+}
+
+hipError_t gemm(const bf16_t *A, int64_t sam, int64_t sak, const bf16_t *B, int64_t sbn, int64_t sbk,
+                int M, int N, int K, int epi, const float *bias, float *outf, int64_t ldf, bf16_t *outh,
+                int64_t ldh, const float *u, int64_t ldu, hipStream_t st)
+{
+    chem::GemmArgs g{A, sam, sak, B, sbn, sbk, M, N, K, epi, bias, outf, ldf, outh, ldh, u, ldu};
+    return chem::launch_gemm_bf16(g, st);
+}
+
+// Forward pass of `rows` rows of X; saves pre-activations when U[0] != NULL.
+hipError_t forward(const chem_surr_s *s, const bf16_t *X, int rows, bf16_t *const H[3],
+                   float *const U[3], float *OUT, int64_t ldo, hipStream_t st)
+{
+    const bf16_t *in = X;
+    int64_t ld_in = kInPad;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < 3 && e == hipSuccess; l++) {
+        const int N = s->out_l[l], Kd = s->in_l[l];
+        e = gemm(in, ld_in, 1, s->wbf + s->off_W[l], Kd, 1, rows, N, Kd, chem::kEpiBiasGeluBf16,
+                 s->master + s->off_b[l], U[l], N, H[l], N, nullptr, 0, st);
+        in = H[l];
+        ld_in = N;
+    }
+    if (e == hipSuccess)
+        e = gemm(in, ld_in, 1, s->wbf + s->off_W[3], s->in_l[3], 1, rows, s->out_l[3], s->in_l[3],
+                 chem::kEpiBiasF32, s->master + s->off_b[3], OUT, ldo, nullptr, 0, nullptr, 0, st);
+    return e;
+}
+
+// Backward pass from dOut (rows x nout_pad BF16) into s->grad.
+hipError_t backward(const chem_surr_s *s, const Acts &a, const bf16_t *X, int rows, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    const bf16_t *d = a.dOut;
+    int64_t ldd = s->nout_pad;
+    for (int l = 3; l >= 0 && e == hipSuccess; l--) {
+        const int Nout = s->out_l[l], Kin = s->in_l[l];
+        const bf16_t *hin = l == 0 ? X : a.H[l - 1];
+        // dW[n][k] = sum_r d[r][n] h[r][k]
+        e = gemm(d, 1, ldd, hin, 1, Kin, Nout, Kin, rows, chem::kEpiF32, nullptr,
+                 s->grad + s->off_W[l], Kin, nullptr, 0, nullptr, 0, st);
+        if (e == hipSuccess) e = chem::launch_bias_grad(d, rows, Nout, (int)ldd, s->grad + s->off_b[l], st);
+        if (l > 0 && e == hipSuccess) {
+            // d_prev[r][k] = (sum_n d[r][n] W[n][k]) * gelu'(u_prev[r][k])
+            e = gemm(d, ldd, 1, s->wbf + s->off_W[l], 1, Kin, rows, Kin, Nout, chem::kEpiGeluGradBf16,
+                     nullptr, nullptr, 0, a.D[l - 1], Kin, a.U[l - 1], Kin, st);
+            d = a.D[l - 1];
+            ldd = Kin;
+        }
+    }
+    return e;
+}
+
+// logical <-> padded parameter vectors
+void logical_map(const chem_surr_s *s, std::vector<std::pair<int64_t, int64_t>> &runs)
+{
+    // (padded offset, length) runs in logical order
+    runs.clear();
+    const int in_real[4] = {s->nin, s->h[0], s->h[1], s->h[2]};
+    const int out_real[4] = {s->h[0], s->h[1], s->h[2], s->K};
+    for (int l = 0; l < 4; l++) {
+        for (int r = 0; r < out_real[l]; r++) runs.push_back({s->off_W[l] + (int64_t)r * s->in_l[l], in_real[l]});
+        runs.push_back({s->off_b[l], out_real[l]});
+    }
+}
+
+int upload_logical(chem_surr_s *s, float *dev, const float *host, int64_t count)
+{
+    if (count != s->n_logical) return fail(CHEM_EINVAL, "parameter count does not match the network");
+    std::vector<float> pad((size_t)s->n_pad, 0.0f);
+    std::vector<std::pair<int64_t, int64_t>> runs;
+    logical_map(s, runs);
+    int64_t o = 0;
+    for (auto &r : runs) {
+        std::memcpy(&pad[(size_t)r.first], host + o, (size_t)r.second * sizeof(float));
+        o += r.second;
+    }
+    return check_hip(hipMemcpy(dev, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice),
+                     "parameter upload");
+}
+
+int download_logical(chem_surr_s *s, const float *dev, float *host, int64_t count)
+{
+    if (count != s->n_logical) return fail(CHEM_EINVAL, "parameter count does not match the network");
+    std::vector<float> pad((size_t)s->n_pad);
+    int rc = check_hip(hipMemcpy(pad.data(), dev, pad.size() * sizeof(float), hipMemcpyDeviceToHost),
+                       "parameter download");
+    if (rc != CHEM_OK) return rc;
+    std::vector<std::pair<int64_t, int64_t>> runs;
+    logical_map(s, runs);
+    int64_t o = 0;
+    for (auto &r : runs) {
+        std::memcpy(host + o, &pad[(size_t)r.first], (size_t)r.second * sizeof(float));
+        o += r.second;
+    }
+    return CHEM_OK;
+}
+
+int refresh_bf16(chem_surr_s *s, hipStream_t st)
+{
+    return check_hip(chem::launch_to_bf16(s->master, s->wbf, s->n_pad, st), "bf16 weights");
+}
+
+// Fallback compaction buffers for up to n cells: list, T, p, Y (K x cap), status.
+struct Fallback {
+    int32_t *list;
+    double *T, *p, *Y;
+    int32_t *status;
+    int64_t cap;
+};
+
+int ensure_fb(chem_surr_s *s, int64_t n, Fallback &f)
+{
+    const int K = s->K;
+    if (n > s->fb_cap) {
+        s->fb_cap = 0;
+        const size_t b = carve_size<int32_t>(n) + 2 * carve_size<double>(n) + carve_size<double>(n * K) +
+                         carve_size<int32_t>(n);
+        int rc = s->fb.grow(b);
+        if (rc != CHEM_OK) return rc;
+        s->fb_cap = n;
+    }
+    Carver fc{(char *)s->fb.p};
+    f.cap = s->fb_cap;
+    f.list = fc.take<int32_t>(f.cap);
+    f.T = fc.take<double>(f.cap);
+    f.p = fc.take<double>(f.cap);
+    f.Y = fc.take<double>(f.cap * K);
+    f.status = fc.take<int32_t>(f.cap);
+    return CHEM_OK;
+}
+
+chem::ApplyArgs apply_args(const chem_surr_s *s, const chem_surr_checks &c)
+{
+    chem::ApplyArgs a{};
+    a.species = s->mech->view.species;
+    a.W = s->mech->view.W;
+    a.counts = s->counts_dev;
+    a.K = s->K;
+    a.E = s->E;
+    a.two_range = s->mech->view.two_range;
+    a.mu_y = s->norm_dev + 2 * s->nin;
+    a.sig_y = s->norm_dev + 2 * s->nin + s->K;
+    a.elem_tol = c.elem_tol;
+    a.sum_tol = c.sum_tol;
+    a.neg_tol = c.neg_tol;
+    a.T_out_min = c.T_out_min;
+    a.T_out_max = c.T_out_max;
+    a.T_in_min = c.T_in_min;
+    a.T_in_max = c.T_in_max;
+    a.dT_gate = c.dT_gate;
+    return a;
+}
+
+// Adam constants of the handle's current step (adam_t already advanced).
+chem::AdamArgs adam_args(chem_surr_s *s, double lr)
+{
+    const double t = (double)s->adam_t;
+    return chem::AdamArgs{s->master, s->am, s->av, s->grad, s->n_pad, (float)lr, (float)kBeta1,
+                          (float)kBeta2, (float)(1.0 - kBeta1), (float)(1.0 - kBeta2), (float)kEps,
+                          (float)(1.0 - std::pow(kBeta1, t)), (float)(1.0 - std::pow(kBeta2, t))};
+}
+
+unsigned long long fnv1a(const char *p, size_t n, unsigned long long h = 0xCBF29CE484222325ull)
+{
+    for (size_t i = 0; i < n; i++) {
+        h ^= (unsigned char)p[i];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chem_surrogate_default_checks(chem_surr_checks *c)
+{
+    if (!c) return fail(CHEM_EINVAL, "checks is NULL");
+    std::memset(c, 0, sizeof(*c));
+    c->elem_tol = 1e-3;
+    c->sum_tol = 1e-3;
+    c->neg_tol = 1e-6;
+    c->T_out_min = 250.0;
+    c->T_out_max = 2600.0;
+    c->T_in_min = 300.0;
+    c->T_in_max = 2500.0;
+    c->dT_gate = 0.0;
+    return CHEM_OK;
+}
+
+int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out)
+{
+    if (!mech || !out) return fail(CHEM_EINVAL, "mech and out must not be NULL");
+    *out = nullptr;
+    const int K = mech->host.K, E = mech->host.E;
+    if (K + 2 > kInPad) return fail(CHEM_EUNSUP, "the surrogate takes at most 62 species");
+    for (int v : {h1, h2, h3})
+        if (v < 64 || v % 64 != 0 || v > 4096)
+            return fail(CHEM_EINVAL, "hidden widths must be multiples of 64 in [64, 4096]");
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (hipSetDevice(mech->device) != hipSuccess) return fail(CHEM_EHIP, "hipSetDevice failed");
+    auto *s = new chem_surr_s();
+    s->mech = mech;
+    s->device = mech->device;
+    s->K = K;
+    s->E = E;
+    s->nin = K + 2;
+    s->h[0] = h1;
+    s->h[1] = h2;
+    s->h[2] = h3;
+    s->nout_pad = round_up(K, 16);
+    const int in_l[4] = {kInPad, h1, h2, h3}, out_l[4] = {h1, h2, h3, s->nout_pad};
+    int64_t off = 0;
+    s->n_logical = 0;
+    const int in_real[4] = {s->nin, h1, h2, h3}, out_real[4] = {h1, h2, h3, K};
+    for (int l = 0; l < 4; l++) {
+        s->in_l[l] = in_l[l];
+        s->out_l[l] = out_l[l];
+        s->off_W[l] = off;
+        off += (int64_t)in_l[l] * out_l[l];
+        s->off_b[l] = off;
+        off += round_up(out_l[l], 64);
+        s->n_logical += (int64_t)in_real[l] * out_real[l] + out_real[l];
+    }
+    s->n_pad = off;
+    const int64_t nn = 2 * (int64_t)s->nin + 2 * K;
+    const size_t bytes = 4 * carve_size<float>(s->n_pad) + carve_size<bf16_t>(s->n_pad) +
+                         carve_size<double>(nn) + carve_size<double>((int64_t)E * K) +
+                         carve_size<int64_t>(8) + carve_size<double>(80);
+    if (hipMalloc(&s->block, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        hipSetDevice(prev);
+        delete s;
+        return fail(CHEM_ENOMEM, "surrogate allocation failed");
+    }
+    Carver c{(char *)s->block};
+    s->master = c.take<float>(s->n_pad);
+    s->grad = c.take<float>(s->n_pad);
+    s->am = c.take<float>(s->n_pad);
+    s->av = c.take<float>(s->n_pad);
+    s->wbf = c.take<bf16_t>(s->n_pad);
+    s->norm_dev = c.take<double>(nn);
+    s->counts_dev = c.take<double>((int64_t)E * K);
+    s->scalars = c.take<int64_t>(8);
+    s->loss_dev = c.take<double>(80);
+    int rc = check_hip(hipMemset(s->block, 0, bytes), "surrogate init");
+    std::vector<double> cnt((size_t)E * K);
+    for (int e = 0; e < E; e++)
+        for (int k = 0; k < K; k++) cnt[(size_t)e * K + k] = mech->host.counts[k][e];
+    if (rc == CHEM_OK)
+        rc = check_hip(hipMemcpy(s->counts_dev, cnt.data(), cnt.size() * sizeof(double), hipMemcpyHostToDevice),
+                       "element table upload");
+    s->norm.assign((size_t)norm_len(s), 0.0);
+    hipSetDevice(prev);
+    if (rc != CHEM_OK) {
+        hipFree(s->block);
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return CHEM_OK;
+}
+
+void chem_free_surrogate(chem_surr s)
+{
+    if (!s) return;
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(s->device);
+    s->act.release();
+    s->fb.release();
+    if (s->block) hipFree(s->block);
+    hipSetDevice(prev);
+    delete s;
+}
+
+int chem_surrogate_info(chem_surr s, int64_t *dims)
+{
+    if (!s || !dims) return fail(CHEM_EINVAL, "surrogate and dims must not be NULL");
+    dims[0] = s->nin;
+    dims[1] = s->h[0];
+    dims[2] = s->h[1];
+    dims[3] = s->h[2];
+    dims[4] = s->K;
+    dims[5] = s->n_logical;
+    return CHEM_OK;
+}
+
+int chem_surrogate_set_params(chem_surr s, const float *params, int64_t count)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (!params) return fail(CHEM_EINVAL, "params is NULL");
+    rc = upload_logical(s, s->master, params, count);
+    if (rc != CHEM_OK) return rc;
+    rc = refresh_bf16(s, nullptr);
+    if (rc != CHEM_OK) return rc;
+    // a new parameter vector restarts the optimiser
+    s->adam_t = 0;
+    rc = check_hip(hipMemset(s->am, 0, 2 * carve_size<float>(s->n_pad)), "optimiser reset");
+    if (rc != CHEM_OK) return rc;
+    return check_hip(hipDeviceSynchronize(), "parameter upload");
+}
+
+int chem_surrogate_get_params(chem_surr s, float *params, int64_t count)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (!params) return fail(CHEM_EINVAL, "params is NULL");
+    rc = check_hip(hipDeviceSynchronize(), "sync");
+    if (rc != CHEM_OK) return rc;
+    return download_logical(s, s->master, params, count);
+}
+
+int chem_surrogate_set_norm(chem_surr s, const double *norm, int64_t count)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (!norm || count != norm_len(s)) return fail(CHEM_EINVAL, "normalisation vector has the wrong length");
+    for (int64_t i = 0; i < count; i++)
+        if (!std::isfinite(norm[i])) return fail(CHEM_EINVAL, "normalisation values must be finite");
+    if (!(norm[count - 1] > 0.0)) return fail(CHEM_EINVAL, "dt of the normalisation must be > 0");
+    s->norm.assign(norm, norm + count);
+    s->norm_set = true;
+    return check_hip(hipMemcpy(s->norm_dev, norm, (size_t)(count - 1) * sizeof(double), hipMemcpyHostToDevice),
+                     "normalisation upload");
+}
+
+int chem_surrogate_get_norm(chem_surr s, double *norm, int64_t count)
+{
+    if (!s || !norm || count != norm_len(s)) return fail(CHEM_EINVAL, "normalisation vector has the wrong length");
+    std::memcpy(norm, s->norm.data(), (size_t)count * sizeof(double));
+    return CHEM_OK;
+}
+
+int chem_surrogate_fit_norm(chem_surr s, const double *T, const double *p, const double *Y,
+                            int64_t ldY, const double *Yn, int64_t ldYn, int64_t n, double dt,
+                            void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (n < 2 || ldY < n || ldYn < n) return fail(CHEM_EINVAL, "need n >= 2 samples and ldY, ldYn >= n");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be finite and > 0");
+    if (!is_device_ptr(T) || !is_device_ptr(p) || !is_device_ptr(Y) || !is_device_ptr(Yn))
+        return fail(CHEM_EINVAL, "T, p, Y and Ynext must be device pointers");
+    hipStream_t st = (hipStream_t)stream;
+    rc = check_hip(chem::launch_fit_norm(T, p, Y, ldY, Yn, ldYn, n, s->K, s->norm_dev, st), "fit_norm");
+    if (rc != CHEM_OK) return rc;
+    const int64_t nn = norm_len(s) - 1;
+    rc = check_hip(hipMemcpyAsync(s->norm.data(), s->norm_dev, (size_t)nn * sizeof(double),
+                                  hipMemcpyDeviceToHost, st), "normalisation download");
+    if (rc != CHEM_OK) return rc;
+    rc = check_hip(hipStreamSynchronize(st), "sync");
+    s->norm[(size_t)nn] = dt;
+    s->norm_set = true;
+    return rc;
+}
+
+int chem_surrogate_encode(chem_surr s, const double *T, const double *p, const double *Y, int64_t ldY,
+                          int64_t n, uint16_t *X, void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK || n == 0) return rc;
+    if (n < 0 || ldY < n) return fail(CHEM_EINVAL, "need ncells >= 0 and ldY >= ncells");
+    if (!s->norm_set) return fail(CHEM_EINVAL, "the surrogate has no normalisation");
+    if (!is_device_ptr(T) || !is_device_ptr(p) || !is_device_ptr(Y) || !is_device_ptr(X))
+        return fail(CHEM_EINVAL, "T, p, Y and X must be device pointers");
+    return check_hip(chem::launch_encode(T, p, Y, ldY, n, s->K, kInPad, s->norm_dev, X, (hipStream_t)stream),
+                     "encode");
+}
+
+int chem_surrogate_forward(chem_surr s, const uint16_t *X, int64_t n, float *out, int64_t ldo, void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK || n == 0) return rc;
+    if (n < 0 || ldo < s->nout_pad) return fail(CHEM_EINVAL, "need ncells >= 0 and ldo >= K rounded up to 16");
+    if (!is_device_ptr(X) || !is_device_ptr(out)) return fail(CHEM_EINVAL, "X and out must be device pointers");
+    const int64_t rows = n < kChunk ? n : kChunk;
+    rc = ensure_acts(s, rows, false);
+    if (rc != CHEM_OK) return rc;
+    Acts a = carve_acts(s);
+    float *noU[3] = {nullptr, nullptr, nullptr};
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t r0 = 0; r0 < n; r0 += kChunk) {
+        const int rr = (int)(n - r0 < kChunk ? n - r0 : kChunk);
+        hipError_t e = forward(s, X + r0 * kInPad, rr, a.H, noU, out + r0 * ldo, ldo, st);
+        if (e != hipSuccess) return check_hip(e, "forward");
+    }
+    return CHEM_OK;
+}
+
+int chem_surrogate_apply(chem_surr s, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
+                         const float *out, int64_t ldo, const chem_surr_checks *checks, int32_t *mask,
+                         void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK || n == 0) return rc;
+    if (n < 0 || ldY < n || ldo < s->nout_pad) return fail(CHEM_EINVAL, "bad sizes");
+    if (n > INT32_MAX) return fail(CHEM_EINVAL, "ncells must fit in int32");
+    if (!s->norm_set) return fail(CHEM_EINVAL, "the surrogate has no normalisation");
+    if (!is_device_ptr(T) || !is_device_ptr(p) || !is_device_ptr(Y) || !is_device_ptr(out) ||
+        (mask && !is_device_ptr(mask)))
+        return fail(CHEM_EINVAL, "arrays must be device pointers");
+    chem_surr_checks c;
+    chem_surrogate_default_checks(&c);
+    if (checks) c = *checks;
+    if (ldo != s->nout_pad) return fail(CHEM_EINVAL, "ldo must equal K rounded up to 16 here");
+    Fallback fb;
+    rc = ensure_fb(s, n, fb);
+    if (rc != CHEM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = check_hip(chem::launch_zero_i64(s->scalars, 1, st), "zero");
+    if (rc != CHEM_OK) return rc;
+    return check_hip(chem::launch_apply(apply_args(s, c), T, p, Y, ldY, n, 0, out, (int)ldo, mask, nullptr,
+                                        fb.list, s->scalars, st),
+                     "apply");
+}
+
+int chem_surrogate_infer(chem_surr s, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
+                         double dt, const chem_opts *opts, const chem_surr_checks *checks,
+                         int32_t *mask, int32_t *status, int64_t *fallback_count, void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK || n == 0) return rc;
+    if (n < 0 || ldY < n) return fail(CHEM_EINVAL, "need ncells >= 0 and ldY >= ncells");
+    if (n > INT32_MAX) return fail(CHEM_EINVAL, "ncells must fit in int32");
+    if (!s->norm_set) return fail(CHEM_EINVAL, "the surrogate has no normalisation");
+    const double tdt = s->norm.back();
+    if (!(std::fabs(dt - tdt) <= 1e-12 * tdt))
+        return fail(CHEM_EINVAL, "dt differs from the flow step the surrogate was trained for");
+    if (!is_device_ptr(T) || !is_device_ptr(p) || !is_device_ptr(Y) || (mask && !is_device_ptr(mask)) ||
+        (status && !is_device_ptr(status)) || (fallback_count && !is_device_ptr(fallback_count)))
+        return fail(CHEM_EINVAL, "arrays must be device pointers");
+    chem_surr_checks c;
+    chem_surrogate_default_checks(&c);
+    if (checks) c = *checks;
+    const int K = s->K;
+    const int64_t rows = n < kChunk ? n : kChunk;
+    rc = ensure_acts(s, rows, false);
+    if (rc != CHEM_OK) return rc;
+    Fallback fb;
+    rc = ensure_fb(s, n, fb);
+    if (rc != CHEM_OK) return rc;
+    Acts a = carve_acts(s);
+    float *noU[3] = {nullptr, nullptr, nullptr};
+    hipStream_t st = (hipStream_t)stream;
+    int64_t *count = fallback_count ? fallback_count : s->scalars;
+    rc = check_hip(chem::launch_zero_i64(count, 1, st), "zero");
+    if (rc != CHEM_OK) return rc;
+    const chem::ApplyArgs aa = apply_args(s, c);
+    for (int64_t r0 = 0; r0 < n; r0 += kChunk) {
+        const int rr = (int)(n - r0 < kChunk ? n - r0 : kChunk);
+        hipError_t e = chem::launch_encode(T + r0, p + r0, Y + r0, ldY, rr, K, kInPad, s->norm_dev, a.X, st);
+        if (e == hipSuccess) e = forward(s, a.X, rr, a.H, noU, a.OUT, s->nout_pad, st);
+        if (e == hipSuccess)
+            e = chem::launch_apply(aa, T + r0, p + r0, Y + r0, ldY, rr, r0, a.OUT, s->nout_pad,
+                                   mask ? mask + r0 : nullptr, status ? status + r0 : nullptr, fb.list,
+                                   count, st);
+        if (e != hipSuccess) return check_hip(e, "surrogate pass");
+    }
+    rc = check_hip(chem::launch_gather_cells(fb.list, count, fb.cap, T, p, Y, ldY, K, fb.T, fb.p, fb.Y, st),
+                   "gather");
+    if (rc != CHEM_OK) return rc;
+    rc = chem_host::integrate_cells(s->mech, fb.T, fb.p, fb.Y, fb.cap, fb.cap, dt, opts, fb.status, nullptr, st,
+                                    count);
+    if (rc != CHEM_OK) return rc;
+    return check_hip(chem::launch_scatter_cells(fb.list, count, fb.cap, fb.T, fb.Y, fb.status, K, T, Y, ldY,
+                                                status, st),
+                     "scatter");
+}
+
+int chem_surrogate_grad(chem_surr s, const uint16_t *X, const float *Yt, int64_t ldt, int64_t n,
+                        double *loss, void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (n < 1 || n > (1 << 20) || ldt < s->K) return fail(CHEM_EINVAL, "need 1 <= n <= 2^20 and ldt >= K");
+    if (!is_device_ptr(X) || !is_device_ptr(Yt)) return fail(CHEM_EINVAL, "X and Yt must be device pointers");
+    rc = ensure_acts(s, n, true);
+    if (rc != CHEM_OK) return rc;
+    Acts a = carve_acts(s);
+    hipStream_t st = (hipStream_t)stream;
+    // targets into the padded layout
+    rc = check_hip(hipMemsetAsync(a.Yb, 0, (size_t)n * s->nout_pad * sizeof(float), st), "clear");
+    if (rc != CHEM_OK) return rc;
+    rc = check_hip(hipMemcpy2DAsync(a.Yb, (size_t)s->nout_pad * sizeof(float), Yt, (size_t)ldt * sizeof(float),
+                                    (size_t)s->K * sizeof(float), (size_t)n, hipMemcpyDeviceToDevice, st),
+                   "targets");
+    if (rc != CHEM_OK) return rc;
+    rc = check_hip(hipMemsetAsync(s->loss_dev, 0, sizeof(double), st), "clear");
+    if (rc != CHEM_OK) return rc;
+    hipError_t e = forward(s, X, (int)n, a.H, a.U, a.OUT, s->nout_pad, st);
+    if (e == hipSuccess) e = chem::launch_loss_grad(a.OUT, a.Yb, (int)n, s->K, s->nout_pad, a.dOut, s->loss_dev, st);
+    if (e == hipSuccess) e = backward(s, a, X, (int)n, st);
+    if (e != hipSuccess) return check_hip(e, "gradient");
+    double acc = 0.0;
+    rc = check_hip(hipMemcpyAsync(&acc, s->loss_dev, sizeof(double), hipMemcpyDeviceToHost, st), "loss");
+    if (rc != CHEM_OK) return rc;
+    rc = check_hip(hipStreamSynchronize(st), "sync");
+    if (loss) *loss = acc / ((double)n * s->K);
+    return rc;
+}
+
+int chem_surrogate_get_grads(chem_surr s, float *grads, int64_t count)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (!grads) return fail(CHEM_EINVAL, "grads is NULL");
+    rc = check_hip(hipDeviceSynchronize(), "sync");
+    if (rc != CHEM_OK) return rc;
+    return download_logical(s, s->grad, grads, count);
+}
+
+int chem_surrogate_set_grads(chem_surr s, const float *grads, int64_t count)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (!grads) return fail(CHEM_EINVAL, "grads is NULL");
+    return upload_logical(s, s->grad, grads, count);
+}
+
+int chem_surrogate_adam(chem_surr s, double lr, void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (!(lr >= 0.0) || !std::isfinite(lr)) return fail(CHEM_EINVAL, "lr must be finite and >= 0");
+    s->adam_t++;
+    chem::AdamArgs a = adam_args(s, lr);
+    hipStream_t st = (hipStream_t)stream;
+    rc = check_hip(chem::launch_adam(a, st), "adam");
+    if (rc != CHEM_OK) return rc;
+    return refresh_bf16(s, st);
+}
+
+int chem_surrogate_train(chem_surr s, const double *T, const double *p, const double *Y, int64_t ldY,
+                         const double *Yn, int64_t ldYn, int64_t n, const int32_t *order, int32_t epochs,
+                         int32_t batch, double lr0, double lr1, double *loss_per_epoch, void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (n < 1 || ldY < n || ldYn < n) return fail(CHEM_EINVAL, "need n >= 1 and ldY, ldYn >= n");
+    if (n > INT32_MAX) return fail(CHEM_EINVAL, "n must fit in int32");
+    if (epochs < 1 || batch < 1 || batch > (1 << 20)) return fail(CHEM_EINVAL, "bad epochs or batch");
+    if (!(lr0 >= 0.0) || !(lr1 >= 0.0)) return fail(CHEM_EINVAL, "learning rates must be >= 0");
+    if (!s->norm_set) return fail(CHEM_EINVAL, "the surrogate has no normalisation");
+    if (!is_device_ptr(T) || !is_device_ptr(p) || !is_device_ptr(Y) || !is_device_ptr(Yn) ||
+        (order && !is_device_ptr(order)))
+        return fail(CHEM_EINVAL, "arrays must be device pointers");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t rows = batch < n ? batch : n;
+    rc = ensure_acts(s, rows, true);
+    if (rc != CHEM_OK) return rc;
+    DevBuf data;
+    rc = data.grow(carve_size<bf16_t>(n * kInPad) + carve_size<float>(n * s->nout_pad));
+    if (rc != CHEM_OK) return rc;
+    Carver dc{(char *)data.p};
+    bf16_t *Xall = dc.take<bf16_t>(n * kInPad);
+    float *Yall = dc.take<float>(n * s->nout_pad);
+    Acts a = carve_acts(s);
+    hipError_t e = chem::launch_encode(T, p, Y, ldY, n, s->K, kInPad, s->norm_dev, Xall, st);
+    if (e == hipSuccess)
+        e = chem::launch_targets(Y, ldY, Yn, ldYn, n, s->K, s->nout_pad, s->norm_dev + 2 * s->nin,
+                                 s->norm_dev + 2 * s->nin + s->K, Yall, st);
+    const int64_t per_epoch = (n + batch - 1) / batch;
+    const int64_t total = per_epoch * epochs;
+    int64_t step = 0;
+    for (int ep = 0; ep < epochs && e == hipSuccess; ep++) {
+        e = hipMemsetAsync(s->loss_dev, 0, sizeof(double), st);
+        for (int64_t b = 0; b < per_epoch && e == hipSuccess; b++, step++) {
+            const int64_t start = b * batch;
+            const int rr = (int)(n - start < batch ? n - start : batch);
+            e = chem::launch_gather_rows(order ? order + (int64_t)ep * n : nullptr, start, rr, Xall, kInPad,
+                                         Yall, s->nout_pad, a.X, a.Yb, st);
+            if (e == hipSuccess) e = forward(s, a.X, rr, a.H, a.U, a.OUT, s->nout_pad, st);
+            if (e == hipSuccess)
+                e = chem::launch_loss_grad(a.OUT, a.Yb, rr, s->K, s->nout_pad, a.dOut, s->loss_dev, st);
+            if (e == hipSuccess) e = backward(s, a, a.X, rr, st);
+            if (e == hipSuccess) {
+                const double lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(kPi * (double)step / (double)total));
+                s->adam_t++;
+                e = chem::launch_adam(adam_args(s, lr), st);
+                if (e == hipSuccess) e = chem::launch_to_bf16(s->master, s->wbf, s->n_pad, st);
+            }
+        }
+        if (e == hipSuccess && loss_per_epoch) {
+            double acc = 0.0;
+            e = hipMemcpyAsync(&acc, s->loss_dev, sizeof(double), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            loss_per_epoch[ep] = acc / ((double)n * s->K);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    data.release();
+    return check_hip(e, "training");
+}
+
+int chem_surrogate_save(chem_surr s, const char *path)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (!path) return fail(CHEM_EINVAL, "path is NULL");
+    std::vector<float> params((size_t)s->n_logical);
+    rc = chem_surrogate_get_params(s, params.data(), s->n_logical);
+    if (rc != CHEM_OK) return rc;
+    std::string buf("CHEMSURR", 8);
+    auto put = [&](const void *d, size_t n) { buf.append((const char *)d, n); };
+    const int32_t ver = 1, hdr[6] = {s->K, s->nin, s->h[0], s->h[1], s->h[2], s->K};
+    const double lam = 0.1;
+    put(&ver, 4);
+    put(hdr, sizeof(hdr));
+    put(&lam, 8);
+    const int64_t nn = (int64_t)s->norm.size(), np = s->n_logical;
+    const int32_t nset = s->norm_set ? 1 : 0;
+    put(&nset, 4);
+    put(&nn, 8);
+    put(s->norm.data(), (size_t)nn * 8);
+    put(&np, 8);
+    put(params.data(), (size_t)np * 4);
+    const unsigned long long sum = fnv1a(buf.data(), buf.size());
+    put(&sum, 8);
+    std::ofstream f(path, std::ios::binary);
+    if (!f || !f.write(buf.data(), (std::streamsize)buf.size())) return fail(CHEM_EINVAL, "cannot write the file");
+    return CHEM_OK;
+}
+
+int chem_surrogate_load(chem_mech mech, const char *path, chem_surr *out)
+{
+    if (!mech || !path || !out) return fail(CHEM_EINVAL, "mech, path and out must not be NULL");
+    *out = nullptr;
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return fail(CHEM_EINVAL, "cannot open the file");
+    std::string buf((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    const size_t fixed = 8 + 4 + 24 + 8 + 4 + 8;
+    if (buf.size() < fixed + 8 + 8 || buf.compare(0, 8, "CHEMSURR") != 0)
+        return fail(CHEM_EINVAL, "not a surrogate file");
+    unsigned long long sum = 0;
+    std::memcpy(&sum, buf.data() + buf.size() - 8, 8);
+    if (fnv1a(buf.data(), buf.size() - 8) != sum) return fail(CHEM_EINVAL, "surrogate file checksum mismatch");
+    size_t o = 8;
+    auto get = [&](void *d, size_t n) -> bool {
+        if (o + n > buf.size() - 8) return false;
+        std::memcpy(d, buf.data() + o, n);
+        o += n;
+        return true;
+    };
+    int32_t ver = 0, hdr[6] = {0, 0, 0, 0, 0, 0}, nset = 0;
+    double lam = 0;
+    int64_t nn = 0, np = 0;
+    if (!get(&ver, 4) || ver != 1 || !get(hdr, sizeof(hdr)) || !get(&lam, 8) || !get(&nset, 4) || !get(&nn, 8))
+        return fail(CHEM_EINVAL, "bad surrogate header");
+    if (hdr[0] != mech->host.K || hdr[1] != mech->host.K + 2 || lam != 0.1)
+        return fail(CHEM_EINVAL, "surrogate does not match the mechanism");
+    chem_surr s = nullptr;
+    int rc = chem_surrogate_create(mech, hdr[2], hdr[3], hdr[4], &s);
+    if (rc != CHEM_OK) return rc;
+    std::vector<double> norm((size_t)(nn > 0 && nn < (1 << 20) ? nn : 0));
+    std::vector<float> params;
+    bool ok = nn == norm_len(s) && get(norm.data(), (size_t)nn * 8) && get(&np, 8) && np == s->n_logical;
+    if (ok) {
+        params.resize((size_t)np);
+        ok = get(params.data(), (size_t)np * 4);
+    }
+    if (!ok) {
+        chem_free_surrogate(s);
+        return fail(CHEM_EINVAL, "truncated or inconsistent surrogate file");
+    }
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(mech->device);
+    rc = chem_surrogate_set_params(s, params.data(), np);
+    if (rc == CHEM_OK && nset) rc = chem_surrogate_set_norm(s, norm.data(), nn);
+    hipSetDevice(prev);
+    if (rc != CHEM_OK) {
+        chem_free_surrogate(s);
+        return rc;
+    }
+    *out = s;
+    return CHEM_OK;
+}
+
+}  // extern "C"
