@@ -72,14 +72,15 @@ __device__ __forceinline__ int wave_argmax(double v, bool cand, int pos)
 template <int NP, typename LT>
 struct WaveLds {
     double C[kWaveLanes + 1], g[kWaveLanes + 1], h[kWaveLanes + 1];
-    LT row[NP][NP + 2];   // Jacobian rows; column NP+1 collects sentinel slots
+    LT row[NP][NP + 2];   // Jacobian rows, then the LU factors of I - gamma J;
+                          // column NP+1 collects sentinel slots
+    int perm[NP];         // pivot row of each elimination step
 };
 
-// Species data of this lane, loaded once per kernel.
+// Species data of this lane: its NASA block stays in the (cached) mechanism
+// table and is read when the thermo is evaluated.
 struct SpeciesLane {
-    double a[kRangeLen];   // NASA block for the lane's species (single range)
-    double a_hi[kRangeLen];
-    double Tmid;
+    const double *blk;   // Tmid, low range, high range
     double W, invW;
 };
 
@@ -88,9 +89,10 @@ __device__ __forceinline__ void lane_thermo(const SpeciesLane &s, bool two_range
                                             double &g, double &dcp)
 {
     double a[kRangeLen];
-    const bool low = !two_range || T < s.Tmid;
+    const bool low = !two_range || T < s.blk[0];
+    const double *src = s.blk + 1 + (low ? 0 : kRangeLen);
 #pragma unroll
-    for (int j = 0; j < kRangeLen; j++) a[j] = low ? s.a[j] : s.a_hi[j];
+    for (int j = 0; j < kRangeLen; j++) a[j] = src[j];
     cp = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
     h = a[0] + T * (a[7] + T * (a[8] + T * (a[9] + T * a[10]))) + a[5] * invT;
     g = h - (a[0] * lnT + T * (a[1] + T * (a[11] + T * (a[12] + T * a[13]))) + a[6]);
@@ -145,9 +147,9 @@ __device__ double wave_rhs(const DevMechView &m, const WaveTables &wt, WaveLds<N
 
 // Row `lane` of M = I - gamma J at the state yi.
 template <int NP, typename LT>
-__device__ void wave_newton_matrix(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT> &L,
+__device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT> &L,
                                    const SpeciesLane &sp, int K, double p, double yi, double gamma,
-                                   double *qbuf, LT *Mrow)
+                                   double *qbuf)
 {
     const int lane = lane_id();
     const int N = K + 1;
@@ -248,75 +250,70 @@ __device__ void wave_newton_matrix(const DevMechView &m, const WaveTables &wt, W
     }
     if (lane < N) L.row[K][lane] = (LT)JT;
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NP; c++)
-        Mrow[c] = (lane < N && c < N) ? (LT)((c == lane ? 1.0 : 0.0) - gamma * (double)L.row[lane][c]) : (LT)0;
+    if (lane < N)
+        for (int c = 0; c < N; c++)
+            L.row[lane][c] = (LT)((c == lane ? 1.0 : 0.0) - gamma * (double)L.row[lane][c]);
     __syncthreads();
 }
 
-// LU with row partial pivoting across lanes.  Rows stay with their lanes;
-// `pos` is the lane's current position under the row exchanges of the plain
-// algorithm (pivot = largest magnitude at or below the diagonal, ties to the
-// lowest position); perm[k] is the lane whose row ends at position k.
+// LU with row partial pivoting of the Newton matrix in LDS, in place: at
+// step k the pivot is the largest magnitude in column k at or below the
+// diagonal (ties to the lowest row), rows k and p are exchanged, and lane r
+// eliminates its row r > k against the pivot row (read by every lane from
+// the same LDS address).  perm[k] records p.
 template <int NP, typename LT>
-__device__ bool wave_lu(LT *Mrow, int N, int *perm, int &pos)
+__device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N)
 {
     const int lane = lane_id();
-    pos = lane;
     bool ok = true;
-#pragma unroll
-    for (int k = 0; k < NP; k++) {
-        if (k < N) {
-            const bool cand = lane < N && pos >= k;
-            const LT mk = Mrow[k];
-            const int p = wave_argmax((double)mk, cand, pos);
-            perm[k] = p;
-            const LT piv = lane_value(mk, p);
-            ok = ok && (piv != (LT)0);
-            const int pos_p = uniform(__shfl(pos, p));
-            if (pos == k) pos = pos_p;
-            if (lane == p) pos = k;
-            const bool elim = cand && lane != p;
-            const LT l = elim ? mk / piv : (LT)0;
-            if (elim) Mrow[k] = l;
-#pragma unroll
-            for (int c = k + 1; c < NP; c++) {
-                const LT pc = lane_value(Mrow[c], p);
-                if (elim && c < N) Mrow[c] -= l * pc;
-            }
+    for (int k = 0; k < N; k++) {
+        const bool cand = lane >= k && lane < N;
+        const int p = wave_argmax(cand ? (double)L.row[lane][k] : 0.0, cand, lane);
+        if (lane == 0) L.perm[k] = p;
+        if (p != k && lane < N) {
+            const LT a = L.row[k][lane], b = L.row[p][lane];
+            L.row[k][lane] = b;
+            L.row[p][lane] = a;
         }
+        __syncthreads();
+        const LT piv = L.row[k][k];
+        ok = ok && (piv != (LT)0);
+        if (lane > k && lane < N) {
+            const LT l = L.row[lane][k] / piv;
+            L.row[lane][k] = l;
+            for (int c = k + 1; c < N; c++) L.row[lane][c] -= l * L.row[k][c];
+        }
+        __syncthreads();
     }
     return ok;
 }
 
-// Solve M x = b with the factors of wave_lu.  b: this lane's component (lane =
-// original row); returns component `lane` of x.
+// Solve M x = b with the factors of wave_lu.  Lane i passes b_i and receives
+// x_i: the recorded row exchanges, then forward (unit lower) and backward
+// substitution, each step broadcasting one component from its lane.
 template <int NP, typename LT>
-__device__ double wave_solve(const LT *Mrow, int N, const int *perm, int pos, double bi)
+__device__ __forceinline__ double wave_solve(const WaveLds<NP, LT> &L, int N, double bi)
 {
     const int lane = lane_id();
-    LT v = (LT)bi;
-    // forward substitution in elimination order
-#pragma unroll
-    for (int k = 0; k < NP; k++) {
-        if (k < N) {
-            const LT yk = lane_value(v, perm[k]);
-            if (pos > k && lane < N) v -= Mrow[k] * yk;
+    LT x = (LT)bi;
+    for (int k = 0; k < N; k++) {
+        const int p = uniform(L.perm[k]);
+        if (p != k) {
+            const LT a = lane_value(x, k), b = lane_value(x, p);
+            if (lane == k) x = b;
+            if (lane == p) x = a;
         }
     }
-    // backward substitution
-    LT x = (LT)0;
-#pragma unroll
-    for (int kk = 0; kk < NP; kk++) {
-        const int k = NP - 1 - kk;
-        if (k < N) {
-            LT ukk = Mrow[k];
-            const LT xk = lane_value(v / ukk, perm[k]);
-            if (lane == k) x = xk;
-            if (pos < k && lane < N) v -= Mrow[k] * xk;
-        }
+    for (int k = 0; k < N; k++) {
+        const LT xk = lane_value(x, k);
+        if (lane > k && lane < N) x -= L.row[lane][k] * xk;
     }
-    return (double)x;
+    for (int k = N - 1; k >= 0; k--) {
+        if (lane == k) x = x / L.row[k][k];
+        const LT xk = lane_value(x, k);
+        if (lane < k) x -= L.row[lane][k] * xk;
+    }
+    return lane < N ? (double)x : 0.0;
 }
 
 template <int NP, typename LT>
@@ -331,19 +328,10 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
     SpeciesLane sp;
     {
         const int k = lane < K ? lane : 0;
-        const double *s = m.species + k * kSpeciesLen;
-        sp.Tmid = s[0];
-#pragma unroll
-        for (int j = 0; j < kRangeLen; j++) {
-            sp.a[j] = s[1 + j];
-            sp.a_hi[j] = s[1 + kRangeLen + j];
-        }
+        sp.blk = m.species + k * kSpeciesLen;
         sp.W = m.W[k];
         sp.invW = m.invW[k];
     }
-    LT Mrow[NP];
-    int perm[NP];
-    int pos = lane;
     for (;;) {
         unsigned long long c = 0;
         if (lane == 0) c = atomicAdd(queue, 1ull);
@@ -467,9 +455,9 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                 const double Cq = 1.0 / (1.0 + l[1] * xq1);
                 bool jcur = false, conv = false, lu_ok = true;
                 if (!have_M || force_M || nst >= nst_M + kMsbp || fabs(gamma / gamma_M - 1.0) > kDgmax) {
-                    wave_newton_matrix<NP, LT>(m, wt, L, sp, K, p, z[0], gamma, qbuf, Mrow);
+                    wave_newton_matrix<NP, LT>(m, wt, L, sp, K, p, z[0], gamma, qbuf);
                     nje++;
-                    lu_ok = wave_lu<NP, LT>(Mrow, N, perm, pos);
+                    lu_ok = wave_lu<NP, LT>(L, N);
                     gamma_M = gamma;
                     nst_M = nst;
                     crate = 1.0;
@@ -486,7 +474,7 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                         nfe++;
                         if (!all_finite(fy)) break;
                         double d = active ? -(e - gamma * fy + z[1] * inv_l1) : 0.0;
-                        d = wave_solve<NP, LT>(Mrow, N, perm, pos, d);
+                        d = wave_solve<NP, LT>(L, N, d);
                         if (!active) d = 0.0;
                         if (gamma != gamma_M) d *= 2.0 / (1.0 + gamma / gamma_M);
                         const double dl = wnorm(d);
@@ -730,8 +718,10 @@ __global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables 
     // a device-side count (cells compacted by an earlier kernel) bounds the queue
     const int64_t nn = prm.n_dev ? (*prm.n_dev < n ? *prm.n_dev : n) : n;
     CellIO io{T, p, Y, ldY, nn, status, counters, &prm};
-    // per-wave reaction scratch (7 R doubles) in global memory, one slice per wave
-    double *qbuf = qscratch + (size_t)blockIdx.x * 7 * m.R;
+    // reaction scratch of the right-hand side and the Jacobian (7 R doubles):
+    // LDS (dynamic shared memory) when it fits, else a global slice per wave
+    extern __shared__ double qlds[];
+    double *qbuf = qscratch ? qscratch + (size_t)blockIdx.x * 7 * m.R : qlds;
     run_wave<NP, LT>(m, wt, io, dt, queue, qbuf, L);
 }
 
@@ -746,11 +736,22 @@ static hipError_t launch_np(const DevMechView &m, const WaveTables &wt, double *
                             double *qscratch, int max_waves, hipStream_t s)
 {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, queue);
-    int blocks = queue_grid((const void *)bdf_wave_kernel<NP, LT>, n * 64);
+    const size_t qbytes = (size_t)7 * (m.R > 0 ? m.R : 1) * sizeof(double);
+    const bool in_lds = qbytes <= 32768;
+    int blocks = 0;
+    {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)bdf_wave_kernel<NP, LT>, 64,
+                                                          in_lds ? qbytes : 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        blocks = cus * per_cu;
+    }
     if (blocks > max_waves) blocks = max_waves;
     if (blocks > n) blocks = (int)n;
-    hipLaunchKernelGGL((bdf_wave_kernel<NP, LT>), dim3(blocks), dim3(64), 0, s, m, wt, T, p, Y, ldY,
-                       n, dt, prm, status, counters, queue, qscratch);
+    hipLaunchKernelGGL((bdf_wave_kernel<NP, LT>), dim3(blocks), dim3(64), in_lds ? qbytes : 0, s, m, wt, T,
+                       p, Y, ldY, n, dt, prm, status, counters, queue, in_lds ? nullptr : qscratch);
     return hipGetLastError();
 }
 
