@@ -27,46 +27,64 @@ constexpr int kWaveLanes = 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-__device__ __forceinline__ double wave_sum(double v)
+// Cross-lane moves of a double through DPP (row-local permutations).  Every
+// lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// value of lane src (src wave-uniform), for every lane regardless of EXEC
-__device__ __forceinline__ double lane_value(double v, int src)
+__device__ __forceinline__ double readlane_f64(double v, int src)
 {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+
+// Sum over the 64 lanes, the same value in every lane: pairwise within quads
+// (xor 1, xor 2), then the mirrored halves of 8 and of 16 lanes (each a
+// commutative pair, so all lanes of a row agree), then the four row sums in
+// a fixed order.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    return ((readlane_f64(v, 15) + readlane_f64(v, 31)) + readlane_f64(v, 47)) + readlane_f64(v, 63);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return fmax(fmax(readlane_f64(v, 15), readlane_f64(v, 31)), fmax(readlane_f64(v, 47), readlane_f64(v, 63)));
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// value of lane src (src wave-uniform), for every lane regardless of EXEC
+__device__ __forceinline__ double lane_value(double v, int src) { return readlane_f64(v, src); }
 __device__ __forceinline__ float lane_value(float v, int src)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
-// Lane holding the largest |v| among candidates; ties go to the smallest pos.
-__device__ __forceinline__ int wave_argmax(double v, bool cand, int pos)
+// Lowest candidate lane holding the largest |v| (-1 if no candidate has a
+// comparable value).
+__device__ __forceinline__ int wave_argmax(double v, bool cand)
 {
-    double a = cand ? fabs(v) : -1.0;
-    int key = cand ? pos : (1 << 30);
-    int idx = lane_id();
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double oa = __shfl_xor(a, off);
-        const int ok = __shfl_xor(key, off);
-        const int oi = __shfl_xor(idx, off);
-        if (oa > a || (oa == a && ok < key)) {
-            a = oa;
-            key = ok;
-            idx = oi;
-        }
-    }
-    return uniform(idx);
+    const double a = cand ? fabs(v) : -1.0;
+    const double best = wave_max(a);
+    const unsigned long long hit = __ballot(cand && a == best);
+    return hit ? (int)__ffsll((long long)hit) - 1 : -1;
 }
 
 template <int NP, typename LT>
@@ -268,7 +286,11 @@ __device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N)
     bool ok = true;
     for (int k = 0; k < N; k++) {
         const bool cand = lane >= k && lane < N;
-        const int p = wave_argmax(cand ? (double)L.row[lane][k] : 0.0, cand, lane);
+        int p = wave_argmax(cand ? (double)L.row[lane][k] : 0.0, cand);
+        if (p < 0) {   // no comparable value (NaN column): keep the row, fail below
+            p = k;
+            ok = false;
+        }
         if (lane == 0) L.perm[k] = p;
         if (p != k && lane < N) {
             const LT a = L.row[k][lane], b = L.row[p][lane];
@@ -281,6 +303,7 @@ __device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N)
         if (lane > k && lane < N) {
             const LT l = L.row[lane][k] / piv;
             L.row[lane][k] = l;
+#pragma unroll 4
             for (int c = k + 1; c < N; c++) L.row[lane][c] -= l * L.row[k][c];
         }
         __syncthreads();
