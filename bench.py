@@ -1,17 +1,32 @@
-"""Benchmark: chemistry cell-steps/s of the plain FP64 GPU integrator on the
-64^3 flame field (262,144 cells, 9-species / 21-reaction synthetic mechanism,
-dt = 1e-6 s, rtol 1e-8, atol 1e-12).
+"""Benchmark of the per-cell chemistry integration on one MI355X.
 
-One step = one call of chem_integrate over all cells, starting from the same
-pristine field (restored by a device-to-device copy inside the step, so the
-copy is timed too).  Prints ONE JSON line with the metric, the roofline of the
-integrator kernel (algorithmic FP64 flops from the per-cell counters, kernel
-time from HIP events on the launch stream) and the CPU oracle timed on the
-host cores.
+Default workload (``--workload flame64``): the plain FP64 GPU integrator on
+the 64^3 flame field (262,144 cells, 9-species / 21-reaction synthetic
+mechanism, dt = 1e-6 s, rtol 1e-8, atol 1e-12).  One step = one call of
+chem_integrate over all cells, starting from the same pristine field
+(restored by a device-to-device copy inside the step, so the copy is timed
+too).  Prints ONE JSON line: the metric, the roofline of the integrator
+kernel (algorithmic flops from the per-cell counters over the kernel time
+from HIP events on the launch stream), HBM traffic from the committed
+profiler summary when it was taken on the same kernel sources, and the CPU
+oracle timed on the host cores.
+
+Other workloads (``--workload``):
+  cells4096  4,096 cells, 9 species, dt = 1e-6 (the parity case);
+  zones128   128^3 = 2,097,152 cells of the 35-species mechanism, 60 % cold /
+             10 % flame front / 30 % burnt, dt = 1e-5, FP32 Jacobian/LU with
+             FP64 residuals and state, wave-per-cell schedule;
+  surrogate  the learned surrogate with per-cell fallback on the 256x128x128
+             flame field (4,194,304 cells, 35 species, dt = 1e-5): training
+             states labelled by the GPU integrator, training on the GPU, then
+             timed inference steps against the plain integrator on the same
+             cells and the oracle on a sample.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -25,8 +40,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "chemistry cell-steps/sec at dt=1e-6 s: plain FP64 vs surrogate; max |dT| vs oracle"
-FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense
-TRANSCENDENTAL_FLOPS = 20        # exp / log / pow / sqrt counted as 20 flops
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, dense (FP32 without packing runs at the same rate)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
 
 
 def algorithmic_flops(K: int, R: int, counters: np.ndarray) -> dict:
@@ -54,14 +69,319 @@ def algorithmic_flops(K: int, R: int, counters: np.ndarray) -> dict:
             "per_solve": f_solve, "per_step": f_step}
 
 
+def kernel_sources_sha() -> str:
+    """Digest of every source the integrator kernels are built from."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2312_13513_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "paper_2312_13513_amd", "codegen.py"))
+    for f in files:
+        if os.path.isfile(f):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload: str, kernel: str):
+    """HBM bytes per launch recorded by the profiler for this workload and
+    kernel, if the record was taken on the current kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha = kernel_sources_sha()
+    for line in open(TRAFFIC_FILE):
+        parts = line.split()
+        if len(parts) >= 5 and not line.startswith("#") and parts[0] == workload and parts[1] == kernel \
+                and parts[2] == sha:
+            return float(parts[3]) + float(parts[4])
+    return None
+
+
+def kernel_name(mech, schedule: int, precision: int) -> str:
+    if schedule == 1 or precision == 1 or (mech.variant == "table" and mech.K > 9):
+        np_rows = 16 if mech.N <= 16 else (40 if mech.N <= 40 else 64)
+        return f"bdf_wave_kernel<{np_rows},{'float' if precision == 1 else 'double'}>"
+    if mech.variant.startswith("specialised:"):
+        return f"bdf_queue_kernel<GenMech_{mech.variant.split(':')[1]}>"
+    return f"bdf_queue_kernel<TableMech<{mech.K}>>"
+
+
+def mech_file(name: str):
+    from chemgen.mechanism import standard_mechanism
+    mpy = standard_mechanism(name)
+    path = os.path.join(tempfile.mkdtemp(), f"{name}.mech")
+    mpy.write(path)
+    return mpy, path
+
+
+def time_oracle(path, field, target_s: float, max_cells: int):
+    """The oracle on a seeded sample of the field, repeated until target_s."""
+    import oracle
+    from chemgen.fields import seeded_sample
+    om = oracle.OracleMech(path)
+    idx = seeded_sample(field.n, min(max_cells, field.n), seed=5)
+    reps, total, used, out = 0, 0.0, 0, None
+    while total < target_s or reps == 0:
+        t1 = time.perf_counter()
+        res = om.integrate(field.T[idx], field.p[idx], field.Y[:, idx], field.dt)
+        total += time.perf_counter() - t1
+        reps += 1
+        used = res[4]
+        out = res
+    return idx, out, reps * idx.size / total, used, reps, total
+
+
+def run_integrator(args, workload: str):
+    import torch
+
+    from chemgen import fields as F
+    from paper_2312_13513_amd import chem
+
+    if workload == "flame64":
+        mname, make, precision, schedule = "M9", F.flame64, 0, -1
+        desc = "flame64: 262,144 cells (64^3 smooth flame field), synthetic 9-species/21-reaction mechanism"
+    elif workload == "cells4096":
+        mname, make, precision, schedule = "M9", F.cells4096, 0, -1
+        desc = "cells4096: 4,096 cells, T U[900,2200] K, Y Dirichlet(1), 9-species/21-reaction mechanism"
+    else:
+        mname, make, precision, schedule = "M35", F.zones128, 1, 1
+        desc = ("zones128: 2,097,152 cells (128^3; 60% cold, 10% flame front, 30% burnt), synthetic "
+                "35-species/200-reaction mechanism, FP32 Jacobian/LU with FP64 residuals and state")
+    mpy, path = mech_file(mname)
+    field = make(mpy)
+    dev = torch.device("cuda:0")
+    mech = chem.Mechanism(path, 0)
+    n, K, R = field.n, mpy.K, mpy.R
+    opts = chem.chem_default_opts()
+    opts.precision = precision
+    opts.schedule = schedule
+    T0 = torch.tensor(field.T, dtype=torch.float64, device=dev)
+    p0 = torch.tensor(field.p, dtype=torch.float64, device=dev)
+    Y0 = torch.tensor(field.Y, dtype=torch.float64, device=dev)
+    T, Y = T0.clone(), Y0.clone()
+    status = torch.zeros(n, dtype=torch.int32, device=dev)
+    counters = torch.zeros(6 * n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        T.copy_(T0)
+        Y.copy_(Y0)
+        if ev is not None:
+            ev[0].record(stream)
+        mech.integrate(T, p0, Y, field.dt, opts=opts, status=status, counters=counters, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg_kern_s = float(np.mean([a.elapsed_time(b) for a, b in events])) * 1e-3
+
+    st = status.cpu().numpy()
+    cnt = counters.cpu().numpy().reshape(6, n)
+    Tg, Yg = T.cpu().numpy(), Y.cpu().numpy()
+    fl = algorithmic_flops(K, R, cnt)
+    achieved = fl["total"] / avg_kern_s / 1e12
+    kname = kernel_name(mech, schedule, precision)
+    traffic = traffic_for(workload, kname)
+    result = {
+        "metric": METRIC,
+        "value": n * args.steps / wall,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{desc}, dt={field.dt:g} s, rtol 1e-8, atol 1e-12",
+                   "ncells": n, "species": K, "reactions": R, "dt": field.dt,
+                   "schedule": "wave per cell" if kname.startswith("bdf_wave") else "thread per cell"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kname,
+                     "kernel_ms": avg_kern_s * 1e3, "flops_per_launch": fl["total"],
+                     "sources": kernel_sources_sha()},
+        "substeps": {"mean": float(cnt[0].mean()), "max": int(cnt[0].max()), "p50": float(np.median(cnt[0])),
+                     "rhs_per_cell": float(cnt[1].mean()), "jac_per_cell": float(cnt[2].mean())},
+        "status_ok_frac": float(np.mean(st == 0)),
+    }
+    if field.zone is not None:
+        result["substeps"]["per_zone_mean"] = {name: float(cnt[0][field.zone == z].mean())
+                                               for z, name in enumerate(("cold", "front", "burnt"))}
+    if not args.no_cpu_baseline:
+        max_cells = args.cpu_sample or (field.n if mname == "M9" else 16384)
+        idx, (To, Yo, so, co, _), rate, used, reps, total = time_oracle(path, field, args.cpu_seconds, max_cells)
+        result["cpu_baseline"] = {
+            "value": rate, "unit": "cell-steps/s", "cores": int(used), "kind": "oracle",
+            "sample": f"{idx.size} cells of the same field ({'all' if idx.size == n else 'seeded sample'}), "
+                      f"{reps} pass(es), {total:.2f} s wall on {used} threads of {os.cpu_count()} host CPUs"}
+        result["max_dT_vs_oracle"] = float(np.abs(Tg[idx] - To).max())
+        result["max_dY_vs_oracle"] = float(np.abs(Yg[:, idx] - Yo).max())
+        result["steps_equal_frac"] = float(np.mean(cnt[0][idx] == co[:, 0]))
+    mech.close()
+    return result
+
+
+def run_surrogate(args):
+    import torch
+
+    from chemgen import fields as F
+    from chemgen.surrogate_data import epoch_orders, flame_like_states, init_params, network_dims, \
+        trajectory_starts
+    from paper_2312_13513_amd import chem
+
+    dev = torch.device("cuda:0")
+    mpy, path = mech_file("M35")
+    mech = chem.Mechanism(path, 0)
+    dt, K = 1e-5, mpy.K
+
+    def t(a, dtype=torch.float64):
+        return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=dev)
+
+    log = {}
+    # ---- training data: flame-like states and integrator trajectories, labelled on the GPU
+    t0 = time.perf_counter()
+    n_half = args.train_samples // 2
+    T1, p1, Y1 = flame_like_states(mpy, n_half, seed=7)
+    n_traj = max(1, n_half // args.traj_steps)
+    T2, p2, Y2 = trajectory_starts(mpy, n_traj, seed=8)
+    Tt, pt, Yt = t(T2), t(p2), t(Y2)
+    Ts, Ys = [], []
+    for _ in range(args.traj_steps):
+        mech.integrate(Tt, pt, Yt, dt)
+        Ts.append(Tt.clone())
+        Ys.append(Yt.clone())
+    Td = torch.cat([t(T1)] + Ts)
+    pd = torch.cat([t(p1), t(np.full(n_traj * args.traj_steps, p2[0]))])
+    Yd = torch.cat([t(Y1)] + Ys, dim=1).contiguous()
+    del Ts, Ys
+    Yn = Yd.clone()
+    Tn = Td.clone()
+    mech.integrate(Tn, pd, Yn, dt)
+    torch.cuda.synchronize()
+    n_train = Td.shape[0]
+    log["label_s"] = time.perf_counter() - t0
+    # ---- training on the GPU
+    t0 = time.perf_counter()
+    surr = chem.Surrogate(mech, 512, 256, 128)
+    surr.set_params(init_params(network_dims(K), 9))
+    surr.fit_norm(Td, pd, Yd, Yn, dt)
+    order = t(epoch_orders(n_train, args.epochs, 10), torch.int32)
+    losses = surr.train(Td, pd, Yd, Yn, epochs=args.epochs, batch=4096, lr0=1e-3, lr1=1e-5, order=order)
+    log["train_s"] = time.perf_counter() - t0
+    del Td, pd, Yd, Yn, Tn, order
+    torch.cuda.empty_cache()
+    # ---- the served field
+    field = F.flame256x128x128(mpy) if args.field == "flame256x128x128" else F.flame256(mpy)
+    n = field.n
+    T0, p0, Y0 = t(field.T), t(field.p), t(field.Y)
+    T, Y = T0.clone(), Y0.clone()
+    mask = torch.zeros(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        T.copy_(T0)
+        Y.copy_(Y0)
+        if ev is not None:
+            ev[0].record(stream)
+        surr.infer(T, p0, Y, dt, mask=mask, fallback_count=cnt, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    Ts_, Ys_ = T.cpu().numpy(), Y.cpu().numpy()
+    nfb = int(cnt.item())
+    # forward pass alone: algorithmic MFMA flops over its time
+    X = torch.zeros((min(n, 262144), 64), dtype=torch.int16, device=dev)
+    out = torch.zeros((X.shape[0], surr.nout_pad), dtype=torch.float32, device=dev)
+    surr.encode(T0[:X.shape[0]], p0[:X.shape[0]], Y0[:, :X.shape[0]].contiguous(), X)
+    surr.forward(X, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        surr.forward(X, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+    fwd_flops = 2.0 * X.shape[0] * ((K + 2) * 512 + 512 * 256 + 256 * 128 + 128 * K)
+    # ---- plain integrator on the same cells (one timed step)
+    Tp, Yp = T0.clone(), Y0.clone()
+    opts = chem.chem_default_opts()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mech.integrate(Tp, p0, Yp, dt, opts=opts)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    Tp_ = Tp.cpu().numpy()
+    result = {
+        "metric": METRIC, "value": n * args.steps / wall, "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64",
+        "data": "synthetic",
+        "config": {"workload": f"surrogate + fallback: {field.name} ({n} cells), synthetic 35-species/200-reaction "
+                               f"mechanism, dt=1e-5 s; MLP 37-512-256-128-35 GELU, BF16 MFMA, trained on "
+                               f"{n_train} integrator-labelled states for {args.epochs} epochs",
+                   "ncells": n, "species": K, "dt": dt},
+        "roofline": {"bound": "mfma", "achieved": fwd_flops / (fwd_ms * 1e-3) / 1e12, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": fwd_flops / (fwd_ms * 1e-3) / 1e12 / 2500.0, "traffic": None,
+                     "kernel": "gemm_bf16_kernel (forward, 4 layers)", "kernel_ms": fwd_ms,
+                     "rows": int(X.shape[0])},
+        "fallback_frac": nfb / n,
+        "surrogate_step_ms": kern_ms,
+        "plain_gpu": {"value": n / plain_s, "unit": "cell-steps/s", "ms_per_step": plain_s * 1e3},
+        "speedup_vs_plain_gpu": (n * args.steps / wall) / (n / plain_s),
+        "max_dT_vs_plain_gpu": float(np.abs(Ts_ - Tp_).max()),
+        "train": {"samples": n_train, "epochs": args.epochs, "loss_first": float(losses[0]),
+                  "loss_last": float(losses[-1]), "label_s": log["label_s"], "train_s": log["train_s"]},
+    }
+    if not args.no_cpu_baseline:
+        from chemgen.fields import subset
+        idx, (To, Yo, so, co, _), rate, used, reps, total = time_oracle(path, field, args.cpu_seconds,
+                                                                        args.cpu_sample or 8192)
+        result["cpu_baseline"] = {
+            "value": rate, "unit": "cell-steps/s", "cores": int(used), "kind": "oracle",
+            "sample": f"{idx.size} cells of the same field (seeded sample), {reps} pass(es), {total:.2f} s wall "
+                      f"on {used} threads of {os.cpu_count()} host CPUs"}
+        result["max_dT_vs_oracle"] = float(np.abs(Ts_[idx] - To).max())
+        result["max_dY_vs_oracle"] = float(np.abs(Ys_[:, idx] - Yo).max())
+    surr.close()
+    mech.close()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="flame64", choices=("flame64", "cells4096", "zones128", "surrogate"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="cells for the oracle timing (0 = the whole field)")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="cells for the oracle timing (0 = workload default)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="repeat the oracle sample until this long")
+    ap.add_argument("--train-samples", type=int, default=2 * 1024 * 1024)
+    ap.add_argument("--traj-steps", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--field", default="flame256x128x128", choices=("flame256x128x128", "flame256"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB three times (scales the HBM "
                          "byte counters of a profiler run)")
@@ -79,107 +399,10 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the per-cell "
               "chemistry shards trivially across GPUs but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
-
-    import torch
-
-    from chemgen.fields import flame64
-    from chemgen.mechanism import standard_mechanism
-    from paper_2312_13513_amd import chem
-
-    dev = torch.device("cuda:0")
-    mech_py = standard_mechanism("M9")
-    field = flame64(mech_py)
-    n, K, R = field.n, mech_py.K, mech_py.R
-    tmp = tempfile.mkdtemp()
-    mech_path = os.path.join(tmp, "M9.mech")
-    mech_py.write(mech_path)
-    mech = chem.Mechanism(mech_path, 0)
-
-    T0 = torch.tensor(field.T, dtype=torch.float64, device=dev)
-    p0 = torch.tensor(field.p, dtype=torch.float64, device=dev)
-    Y0 = torch.tensor(field.Y, dtype=torch.float64, device=dev)
-    T, Y = T0.clone(), Y0.clone()
-    status = torch.zeros(n, dtype=torch.int32, device=dev)
-    counters = torch.zeros(6 * n, dtype=torch.int32, device=dev)
-    opts = chem.chem_default_opts()
-    stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        T.copy_(T0)
-        Y.copy_(Y0)
-        if ev is not None:
-            ev[0].record(stream)
-        mech.integrate(T, p0, Y, field.dt, opts=opts, status=status, counters=counters, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(events[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in events]
-    avg_kern_s = float(np.mean(kern_ms)) * 1e-3
-
-    st = status.cpu().numpy()
-    cnt = counters.cpu().numpy().reshape(6, n)
-    Tg, Yg = T.cpu().numpy(), Y.cpu().numpy()
-    fl = algorithmic_flops(K, R, cnt)
-    achieved = fl["total"] / avg_kern_s / 1e12
-    value = n * args.steps / wall
-
-    result = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "flame64: 262,144 cells (64^3 smooth flame field), synthetic "
-                               "9-species/21-reaction mechanism, dt=1e-6 s, rtol 1e-8, atol 1e-12, "
-                               "plain FP64 BDF, one thread per cell",
-                   "ncells": n, "species": K, "reactions": R, "dt": field.dt},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "bdf_thread_kernel<9>", "kernel_ms": avg_kern_s * 1e3,
-                     "flops_per_launch": fl["total"]},
-        "substeps": {"mean": float(cnt[0].mean()), "max": int(cnt[0].max()),
-                     "p50": float(np.median(cnt[0])), "rhs_per_cell": float(cnt[1].mean()),
-                     "jac_per_cell": float(cnt[2].mean())},
-        "status_ok_frac": float(np.mean(st == 0)),
-    }
-
-    if not args.no_cpu_baseline:
-        import oracle
-        om = oracle.OracleMech(mech_path)
-        if args.cpu_sample and args.cpu_sample < n:
-            from chemgen.fields import seeded_sample
-            idx = seeded_sample(n, args.cpu_sample, seed=5)
-        else:
-            idx = np.arange(n)
-        t1 = time.perf_counter()
-        To, Yo, so, co, used = om.integrate(field.T[idx], field.p[idx], field.Y[:, idx], field.dt)
-        tc = time.perf_counter() - t1
-        result["cpu_baseline"] = {
-            "value": idx.size / tc, "unit": "cell-steps/s", "cores": int(used), "kind": "oracle",
-            "sample": f"{idx.size} cells of the same field ({'all' if idx.size == n else 'seeded sample'}), "
-                      f"one flow step, {tc:.2f} s wall on {used} threads of {os.cpu_count()} host CPUs"}
-        result["max_dT_vs_oracle"] = float(np.abs(Tg[idx] - To).max())
-        result["max_dY_vs_oracle"] = float(np.abs(Yg[:, idx] - Yo).max())
-        result["steps_equal_frac"] = float(np.mean(cnt[0][idx] == co[:, 0]))
-    mech.close()
+    if args.workload == "surrogate":
+        result = run_surrogate(args)
+    else:
+        result = run_integrator(args, args.workload)
     print(json.dumps(result), flush=True)
 
 
