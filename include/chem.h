@@ -67,7 +67,8 @@ typedef struct {
                            state, norms, error control and equilibrium constants
                            stay FP64 (wave schedule only; results then differ
                            from FP64 at the level of the integration tolerance) */
-    int32_t schedule;   /* -1 = library choice (one thread per cell when such a
+    int32_t schedule;   /* -2 = the autotuned choice (chem_autotune), else as -1;
+                           -1 = library choice (one thread per cell when such a
                            kernel exists and precision is 0, else one wave per
                            cell), 0 = one thread per cell (K <= 9 table kernel or
                            a compiled-in mechanism), 1 = one 64-lane wave per
@@ -112,6 +113,35 @@ const char *chem_mechanism_variant(chem_mech mech);
 int chem_integrate(chem_mech mech, double *T, const double *p, double *Y, int64_t ldY,
                    int64_t ncells, double dt, const chem_opts *opts, int32_t *status,
                    int32_t *counters, void *hip_stream);
+
+/* Advance the listed cells only, in list order: work item j integrates cell
+ * cell_idx[j] of the arrays (sizes as chem_integrate; status and counters,
+ * if given, are indexed by cell).  cell_idx is a device array of nidx
+ * indices; an index outside [0, ncells) is skipped.  The list order is the
+ * order in which the work queue hands cells to the lanes (e.g. from
+ * chem_lpt_order).  nidx == 0 is a no-op. */
+int chem_integrate_indexed(chem_mech mech, double *T, const double *p, double *Y, int64_t ldY,
+                           int64_t ncells, const int32_t *cell_idx, int64_t nidx, double dt,
+                           const chem_opts *opts, int32_t *status, int32_t *counters,
+                           void *hip_stream);
+
+/* Longest-processing-time-first order: order[0..n) (device) receives the
+ * indices 0..n-1 sorted by descending cost[i] (device int32, e.g. the step
+ * counts of the previous flow step), ties in index order.  A planning call:
+ * allocates temporary device memory and synchronises the stream. */
+int chem_lpt_order(const int32_t *cost, int64_t n, int32_t *order, void *hip_stream);
+
+/* Autotuner: times every schedule that can serve the mechanism at
+ * opts->precision (one thread per cell with jac_batch 4, 16, 64; one wave
+ * per cell), each in natural and in LPT order, on a strided sample of at
+ * most max_sample cells (0 = 65,536) of the given states (not modified),
+ * and returns the fastest as *best (schedule, jac_batch filled in),
+ * *use_lpt (1 if the LPT order was faster) and *best_ms.  The choice is also
+ * kept in the handle: opts.schedule = -2 then selects it.  Allocates and
+ * synchronises (a planning call). */
+int chem_autotune(chem_mech mech, const double *T, const double *p, const double *Y, int64_t ldY,
+                  int64_t ncells, double dt, const chem_opts *opts, int32_t max_sample,
+                  chem_opts *best, int32_t *use_lpt, double *best_ms, void *hip_stream);
 
 /* Right-hand side of the reactor ODE at the given states (diagnostics and
  * parity tests of the kernels' building blocks).  F has N = K+1 rows of

@@ -54,6 +54,11 @@ def _load():
     L.chem_integrate.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), vp, vp, vp]
     L.chem_eval_rhs.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, vp]
     L.chem_eval_jacobian.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, vp]
+    L.chem_integrate_indexed.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, C.c_double, C.POINTER(chem_opts),
+                                         vp, vp, vp]
+    L.chem_lpt_order.argtypes = [dp, i64, dp, vp]
+    L.chem_autotune.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), C.c_int32,
+                                C.POINTER(chem_opts), i32p, C.POINTER(C.c_double), vp]
     fp, dblp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int64)
     ckp = C.POINTER(chem_surr_checks)
     L.chem_surrogate_default_checks.argtypes = [ckp]
@@ -87,7 +92,8 @@ _lib = _load()
 #: Symbols that include/chem.h declares (checked by the ABI test).
 EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_mechanism_info", "chem_mechanism_variant", "chem_integrate", "chem_eval_rhs", "chem_eval_jacobian",
-            "chem_last_error", "chem_surrogate_default_checks", "chem_surrogate_create",
+            "chem_last_error", "chem_integrate_indexed", "chem_lpt_order", "chem_autotune",
+            "chem_surrogate_default_checks", "chem_surrogate_create",
             "chem_free_surrogate", "chem_surrogate_info", "chem_surrogate_set_params",
             "chem_surrogate_get_params", "chem_surrogate_set_norm", "chem_surrogate_get_norm",
             "chem_surrogate_fit_norm", "chem_surrogate_encode", "chem_surrogate_forward",
@@ -192,11 +198,33 @@ class Mechanism:
     def integrate(self, T, p, Y, dt, opts=None, status=None, counters=None, stream=None):
         chem_integrate(self.handle, T, p, Y, dt, opts, status, counters, stream)
 
+    def integrate_indexed(self, T, p, Y, idx, dt, opts=None, status=None, counters=None, stream=None):
+        """Advance cells idx (int32 GPU tensor) of the arrays, in list order."""
+        _check(_lib.chem_integrate_indexed(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
+                                           T.shape[0], _ptr(idx), idx.shape[0], float(dt),
+                                           C.byref(opts) if opts is not None else None, _ptr(status),
+                                           _ptr(counters), _stream(stream)))
+
+    def autotune(self, T, p, Y, dt, opts=None, max_sample: int = 0, stream=None):
+        """Returns (best chem_opts, use_lpt, best_ms) and keeps the choice (schedule -2)."""
+        best = chem_opts()
+        lpt = C.c_int32()
+        ms = C.c_double()
+        _check(_lib.chem_autotune(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1], T.shape[0],
+                                  float(dt), C.byref(opts) if opts is not None else None, int(max_sample),
+                                  C.byref(best), C.byref(lpt), C.byref(ms), _stream(stream)))
+        return best, bool(lpt.value), ms.value
+
     def rhs(self, T, p, Y, F, stream=None):
         chem_eval_rhs(self.handle, T, p, Y, F, stream)
 
     def jacobian(self, T, p, Y, J, stream=None):
         chem_eval_jacobian(self.handle, T, p, Y, J, stream)
+
+
+def chem_lpt_order(cost, order, stream=None) -> None:
+    """order (int32 GPU tensor) <- indices sorted by descending cost (int32 GPU tensor)."""
+    _check(_lib.chem_lpt_order(_ptr(cost), cost.shape[0], _ptr(order), _stream(stream)))
 
 
 # --------------------------------------------------------------------------- surrogate

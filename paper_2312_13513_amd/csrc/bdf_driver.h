@@ -291,10 +291,23 @@ struct CellIO {
     double *T;
     const double *p;
     double *Y;
-    int64_t ldY, n;
+    int64_t ldY, n;              // n: cells in the arrays (stride of the counter rows)
     int32_t *status, *counters;
     const BdfParams *prm;
+    int64_t nq;                  // work items of the queue
+    const int32_t *idx;          // work item -> cell (NULL: identity)
 };
+
+// Work items of one launch: the index list or all cells, bounded by a
+// device-side count when one is given.
+__device__ __forceinline__ CellIO make_cell_io(double *T, const double *p, double *Y, int64_t ldY,
+                                               int64_t n, int32_t *status, int32_t *counters,
+                                               const BdfParams &prm)
+{
+    int64_t nq = prm.idx ? prm.n_idx : n;
+    if (prm.n_dev && *prm.n_dev < nq) nq = *prm.n_dev;
+    return CellIO{T, p, Y, ldY, n, status, counters, &prm, nq, prm.idx};
+}
 
 template <int N>
 __device__ __forceinline__ void finish_cell(LaneState<N> &S, const CellIO &io, int st)
@@ -612,8 +625,12 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
                 if (want) {
                     const unsigned long long rank = __popcll(mask & ((1ull << lane) - 1ull));
                     const unsigned long long c = base + rank;
-                    if (c < (unsigned long long)io.n) {
-                        S.cell = (int64_t)c;
+                    const int64_t cc = c < (unsigned long long)io.nq
+                                           ? (io.idx ? (int64_t)io.idx[c] : (int64_t)c) : -1;
+                    if (c < (unsigned long long)io.nq && (cc < 0 || cc >= io.n)) {
+                        // an index outside the arrays is skipped: this lane fetches again
+                    } else if (c < (unsigned long long)io.nq) {
+                        S.cell = cc;
                         const int64_t i = S.cell;
 #pragma unroll
                         for (int k = 0; k < K; k++) S.z(0, k) = io.Y[k * io.ldY + i];
@@ -794,9 +811,7 @@ __global__ void __launch_bounds__(64) bdf_queue_kernel(Mech mech, double *__rest
                                                        unsigned long long *__restrict__ queue)
 {
     __shared__ double nord[kLdsRows * (Mech::K + 1) * 64];
-    // a device-side count (cells compacted by an earlier kernel) bounds the queue
-    const int64_t nn = prm.n_dev ? (*prm.n_dev < n ? *prm.n_dev : n) : n;
-    CellIO io{T, p, Y, ldY, nn, status, counters, &prm};
+    const CellIO io = make_cell_io(T, p, Y, ldY, n, status, counters, prm);
     run_lanes(mech, io, dt, queue, nord);
 }
 

@@ -359,8 +359,9 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
         unsigned long long c = 0;
         if (lane == 0) c = atomicAdd(queue, 1ull);
         c = __shfl(c, 0);
-        if (c >= (unsigned long long)io.n) break;
-        const int64_t cell = (int64_t)c;
+        if (c >= (unsigned long long)io.nq) break;
+        const int64_t cell = io.idx ? (int64_t)io.idx[c] : (int64_t)c;
+        if (cell < 0 || cell >= io.n) continue;   // an index outside the arrays is skipped
         const double p = io.p[cell];
         double y0 = 0.0;
         if (lane < K) y0 = io.Y[lane * io.ldY + cell];
@@ -738,9 +739,7 @@ __global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables 
                                                       double *__restrict__ qscratch)
 {
     __shared__ WaveLds<NP, LT> L;
-    // a device-side count (cells compacted by an earlier kernel) bounds the queue
-    const int64_t nn = prm.n_dev ? (*prm.n_dev < n ? *prm.n_dev : n) : n;
-    CellIO io{T, p, Y, ldY, nn, status, counters, &prm};
+    const CellIO io = make_cell_io(T, p, Y, ldY, n, status, counters, prm);
     // reaction scratch of the right-hand side and the Jacobian (7 R doubles):
     // LDS (dynamic shared memory) when it fits, else a global slice per wave
     extern __shared__ double qlds[];

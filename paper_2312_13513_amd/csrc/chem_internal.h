@@ -45,7 +45,9 @@ struct BdfParams {
     double rtol, atol;
     int32_t max_steps;
     int32_t jac_batch;      // lanes of a wave that wait before a Jacobian is evaluated
-    const int64_t *n_dev;   // if not NULL: integrate only the first *n_dev cells
+    const int64_t *n_dev;   // if not NULL: at most *n_dev cells (read on the device)
+    const int32_t *idx;     // if not NULL: integrate cells idx[0 .. n_idx) in this order
+    int64_t n_idx;
 };
 
 // Launchers of the table-driven kernels.  Return hipError_t of the launch.

@@ -194,7 +194,7 @@ namespace chem_host {
 
 int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
                     double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
-                    hipStream_t stream, const int64_t *n_dev)
+                    hipStream_t stream, const int64_t *n_dev, const int32_t *idx, int64_t n_idx)
 {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be finite and > 0");
     chem_opts o;
@@ -204,7 +204,12 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
         return fail(CHEM_EINVAL, "rtol and atol must be finite and > 0");
     if (o.max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
     if (o.precision != 0 && o.precision != 1) return fail(CHEM_EINVAL, "precision must be 0 or 1");
-    if (o.schedule < -1 || o.schedule > 1) return fail(CHEM_EINVAL, "unknown schedule");
+    if (o.schedule < -2 || o.schedule > 1) return fail(CHEM_EINVAL, "unknown schedule");
+    if (o.schedule == -2) {
+        const auto &tu = m->tuned[o.precision == 1 ? 1 : 0];
+        o.schedule = tu.valid ? tu.schedule : -1;
+        if (tu.valid && o.jac_batch == 0) o.jac_batch = tu.jac_batch;
+    }
     if (o.block != 0 && o.block != 64) return fail(CHEM_EUNSUP, "block must be 0 or 64");
     if (n == 0) return CHEM_OK;
     if ((status && !is_device_ptr(status)) || (counters && !is_device_ptr(counters)))
@@ -222,7 +227,7 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
     if (sched == 1 && !wave_ok)
         return fail(CHEM_EUNSUP, "the wave schedule supports at most 63 species");
     if (o.jac_batch < 0 || o.jac_batch > 64) return fail(CHEM_EINVAL, "jac_batch must be in 0..64");
-    chem::BdfParams prm{o.rtol, o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16, n_dev};
+    chem::BdfParams prm{o.rtol, o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16, n_dev, idx, n_idx};
     // each call takes its own queue counter (64 rotate), so that calls in
     // flight on different streams do not share one
     unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);

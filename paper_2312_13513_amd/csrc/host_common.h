@@ -46,6 +46,11 @@ struct chem_mech_s {
     chem::WaveTables wave{};                // species -> reaction incidence (wave kernel)
     double *wave_scratch = nullptr;         // per-wave reaction buffers (7 R doubles each)
     int wave_slots = 0;
+    // autotuned schedule per precision (used when opts.schedule == -2)
+    struct Tuned {
+        bool valid = false;
+        int schedule = -1, jac_batch = 0;
+    } tuned[2];
 };
 
 namespace chem_host {
@@ -55,6 +60,7 @@ namespace chem_host {
 // most n), so that a count produced by an earlier kernel needs no host sync.
 int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
                     double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
-                    hipStream_t stream, const int64_t *n_dev);
+                    hipStream_t stream, const int64_t *n_dev, const int32_t *idx = nullptr,
+                    int64_t n_idx = 0);
 
 }  // namespace chem_host

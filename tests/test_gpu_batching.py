@@ -1,0 +1,111 @@
+"""Batching: integration of a listed subset in a given order, the LPT order,
+and the autotuner.  The per-cell result does not depend on which lane or
+wave takes the cell or when, so reordered and subset runs must be bitwise
+equal to the plain run on the same cells."""
+import numpy as np
+import pytest
+
+from test_gpu_integrate import DT_TOL, DY_TOL, _say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _dev(torch, a, dtype=None):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda:0")
+
+
+@pytest.fixture(scope="module")
+def m9(mech_dir, torch):
+    from paper_2312_13513_amd import chem
+    m = chem.Mechanism(str(mech_dir / "M9.mech"), 0)
+    yield m
+    m.close()
+
+
+@pytest.fixture(scope="module")
+def field(mech_dir):
+    from chemgen.fields import cells4096
+    from chemgen.mechanism import read_mechanism
+    return cells4096(read_mechanism(str(mech_dir / "M9.mech")), n=3000, seed=12)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_indexed_subset_is_bitwise_plain(torch, m9, field, schedule):
+    from paper_2312_13513_amd import chem
+    f = field
+    o = chem.chem_default_opts()
+    o.schedule = schedule
+    rng = np.random.default_rng(5)
+    sub = rng.choice(f.n, size=777, replace=False).astype(np.int32)   # random order
+    # plain run of the subset as its own field
+    Ts, Ys = _dev(torch, f.T[sub]), _dev(torch, f.Y[:, sub])
+    cs = torch.zeros(6 * sub.size, dtype=torch.int32, device="cuda:0")
+    m9.integrate(Ts, _dev(torch, f.p[sub]), Ys, f.dt, opts=o, counters=cs)
+    # indexed run on the full arrays, with out-of-range entries mixed in
+    idx = np.concatenate([sub[:400], [-1, f.n, 10 ** 9], sub[400:]]).astype(np.int32)
+    T, Y = _dev(torch, f.T), _dev(torch, f.Y)
+    st = torch.full((f.n,), -5, dtype=torch.int32, device="cuda:0")
+    cnt = torch.full((6 * f.n,), -5, dtype=torch.int32, device="cuda:0")
+    m9.integrate_indexed(T, _dev(torch, f.p), Y, _dev(torch, idx, torch.int32), f.dt, opts=o, status=st,
+                         counters=cnt)
+    torch.cuda.synchronize()
+    T, Y, st, cnt = T.cpu().numpy(), Y.cpu().numpy(), st.cpu().numpy(), cnt.cpu().numpy().reshape(6, f.n)
+    assert np.array_equal(T[sub], Ts.cpu().numpy()) and np.array_equal(Y[:, sub], Ys.cpu().numpy())
+    assert np.array_equal(cnt[:, sub], cs.cpu().numpy().reshape(6, sub.size))
+    rest = np.setdiff1d(np.arange(f.n), sub)
+    assert np.array_equal(T[rest], f.T[rest]) and np.array_equal(Y[:, rest], f.Y[:, rest])
+    assert np.all(st[rest] == -5) and np.all(st[sub] == 0)
+
+
+def test_lpt_order_matches_stable_sort(torch):
+    from paper_2312_13513_amd import chem
+    rng = np.random.default_rng(6)
+    for n in (1, 63, 1000, 70001):
+        cost = rng.integers(0, 50, size=n).astype(np.int32)
+        order = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+        chem.chem_lpt_order(_dev(torch, cost, torch.int32), order)
+        ref = np.argsort(-cost.astype(np.int64), kind="stable")
+        assert np.array_equal(order.cpu().numpy(), ref)
+
+
+def test_lpt_ordered_run_is_bitwise_plain(torch, m9, field):
+    f = field
+    T1, Y1 = _dev(torch, f.T), _dev(torch, f.Y)
+    p = _dev(torch, f.p)
+    cnt = torch.zeros(6 * f.n, dtype=torch.int32, device="cuda:0")
+    m9.integrate(T1, p, Y1, f.dt, counters=cnt)
+    from paper_2312_13513_amd import chem
+    order = torch.zeros(f.n, dtype=torch.int32, device="cuda:0")
+    chem.chem_lpt_order(cnt[:f.n].contiguous(), order)
+    T2, Y2 = _dev(torch, f.T), _dev(torch, f.Y)
+    m9.integrate_indexed(T2, p, Y2, order, f.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(T1, T2) and torch.equal(Y1, Y2)
+
+
+def test_autotune_choice_meets_parity(torch, m9, field, om9):
+    from paper_2312_13513_amd import chem
+    f = field
+    T, Y, p = _dev(torch, f.T), _dev(torch, f.Y), _dev(torch, f.p)
+    best, lpt, ms = m9.autotune(T, p, Y, f.dt, max_sample=2048)
+    _say(f"[autotune] schedule {best.schedule} jac_batch {best.jac_batch} lpt {lpt} {ms:.3f} ms on 2048 cells")
+    assert best.schedule in (0, 1) and ms > 0
+    # the states passed in are not modified
+    assert np.array_equal(T.cpu().numpy(), f.T) and np.array_equal(Y.cpu().numpy(), f.Y)
+    o = chem.chem_default_opts()
+    o.schedule = -2
+    m9.integrate(T, p, Y, f.dt, opts=o)
+    torch.cuda.synchronize()
+    To, Yo, _, _, _ = om9.integrate(f.T, f.p, f.Y, f.dt)
+    dT = np.abs(T.cpu().numpy() - To).max()
+    dY = np.abs(Y.cpu().numpy() - Yo).max()
+    _say(f"[autotune] tuned run vs oracle: max|dT| {dT:.3e} K max|dY| {dY:.3e}")
+    assert dT < DT_TOL and dY < DY_TOL
