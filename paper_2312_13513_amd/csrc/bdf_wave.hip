@@ -90,9 +90,11 @@ __device__ __forceinline__ int wave_argmax(double v, bool cand)
 template <int NP, typename LT>
 struct WaveLds {
     double C[kWaveLanes + 1], g[kWaveLanes + 1], h[kWaveLanes + 1];
+    double invW[kWaveLanes + 1];   // 1 / W_k, 0 for the sentinel slot (set once)
     LT row[NP][NP + 2];   // Jacobian rows, then the LU factors of I - gamma J;
                           // column NP+1 collects sentinel slots
     int perm[NP];         // pivot row of each elimination step
+    LT lcol[NP];          // multipliers of the current elimination step
 };
 
 // Species data of this lane: its NASA block stays in the (cached) mechanism
@@ -119,7 +121,7 @@ __device__ __forceinline__ void lane_thermo(const SpeciesLane &s, bool two_range
 
 // f(y): each lane passes its component yi and receives fi.
 template <int NP, typename LT>
-__device__ double wave_rhs(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT> &L,
+__device__ __forceinline__ double wave_rhs(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT> &L,
                            const SpeciesLane &sp, int K, double p, double yi, double *qbuf)
 {
     const int lane = lane_id();
@@ -151,6 +153,7 @@ __device__ double wave_rhs(const DevMechView &m, const WaveTables &wt, WaveLds<N
     double wk = 0.0;
     if (lane < K) {
         const int b = wt.inc_off[lane], e = wt.inc_off[lane + 1];
+#pragma unroll 4
         for (int j = b; j < e; j++) {
             const int2 ent = wt.inc[j];
             wk += (double)ent.y * qbuf[ent.x];
@@ -235,7 +238,7 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
             for (int s = 0; s < 4; s++) {
                 const bool sentinel = sl[s] == K;
                 const int c = sentinel ? NP + 1 : sl[s];
-                const double f = sentinel ? 0.0 : nu * sp.W * m.invW[sl[s]];
+                const double f = sentinel ? 0.0 : nu * sp.W * L.invW[sl[s]];
                 L.row[lane][c] += (LT)(f * dq[4 * r + s]);
             }
         }
@@ -251,7 +254,8 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
     double JT = 0.0;
     if (lane < K) {
         double col = 0.0;
-        for (int k = 0; k < K; k++) col += (double)L.row[k][lane] * (L.h[k] * m.invW[k]);
+#pragma unroll 4
+        for (int k = 0; k < K; k++) col += (double)L.row[k][lane] * (L.h[k] * L.invW[k]);
         const double dS = RT * rho * (col - (wbar / rho) * sp.invW * hAC);
         const double drcp = rho * sp.invW * (kRu * cpk - cpm * wbar);
         JT = (-dS + S * drcp * inv_rcp) * inv_rcp;
@@ -263,7 +267,8 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
     const double gq = wbar / rho;
     if (lane < K) {
         const double u = sp.W * gq * (wk - ACk);
-        for (int c = 0; c < K; c++) L.row[lane][c] += (LT)(u * m.invW[c]);
+#pragma unroll 4
+        for (int c = 0; c < K; c++) L.row[lane][c] += (LT)(u * L.invW[c]);
         L.row[lane][K] = (LT)(sp.W / rho * (wTk + (wk - ACk) * invT));
     }
     if (lane < N) L.row[K][lane] = (LT)JT;
@@ -280,10 +285,11 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
 // eliminates its row r > k against the pivot row (read by every lane from
 // the same LDS address).  perm[k] records p.
 template <int NP, typename LT>
-__device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N)
+__device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N, int &pi, LT &dinv)
 {
     const int lane = lane_id();
     bool ok = true;
+    pi = lane;   // lane k ends with the original row that lands at position k
     for (int k = 0; k < N; k++) {
         const bool cand = lane >= k && lane < N;
         int p = wave_argmax(cand ? (double)L.row[lane][k] : 0.0, cand);
@@ -291,11 +297,15 @@ __device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N)
             p = k;
             ok = false;
         }
-        if (lane == 0) L.perm[k] = p;
-        if (p != k && lane < N) {
-            const LT a = L.row[k][lane], b = L.row[p][lane];
-            L.row[k][lane] = b;
-            L.row[p][lane] = a;
+        if (p != k) {
+            const int a = __builtin_amdgcn_readlane(pi, k), b = __builtin_amdgcn_readlane(pi, p);
+            if (lane == k) pi = b;
+            if (lane == p) pi = a;
+            if (lane < N) {
+                const LT ra = L.row[k][lane], rb = L.row[p][lane];
+                L.row[k][lane] = rb;
+                L.row[p][lane] = ra;
+            }
         }
         __syncthreads();
         const LT piv = L.row[k][k];
@@ -303,38 +313,45 @@ __device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N)
         if (lane > k && lane < N) {
             const LT l = L.row[lane][k] / piv;
             L.row[lane][k] = l;
+            L.lcol[lane] = l;
+        }
+        __syncthreads();
+        // lane c updates column c below the pivot row: one multiplier read
+        // (same address for every lane) and one element of its own column
+        // per row, independent from row to row
+        if (lane > k && lane < N) {
+            const LT ukc = L.row[k][lane];
 #pragma unroll 4
-            for (int c = k + 1; c < N; c++) L.row[lane][c] -= l * L.row[k][c];
+            for (int r = k + 1; r < N; r++) L.row[r][lane] -= L.lcol[r] * ukc;
         }
         __syncthreads();
     }
+    dinv = lane < N ? (LT)1 / L.row[lane][lane] : (LT)0;
     return ok;
 }
 
 // Solve M x = b with the factors of wave_lu.  Lane i passes b_i and receives
-// x_i: the recorded row exchanges, then forward (unit lower) and backward
-// substitution, each step broadcasting one component from its lane.
+// x_i: the row exchanges applied at once (each lane reads the component of
+// its original row), then forward (unit lower) and backward substitution,
+// each step broadcasting one component; the diagonal enters through its
+// reciprocal.
 template <int NP, typename LT>
-__device__ __forceinline__ double wave_solve(const WaveLds<NP, LT> &L, int N, double bi)
+__device__ __forceinline__ double wave_solve(const WaveLds<NP, LT> &L, int N, int pi, LT dinv, double bi)
 {
     const int lane = lane_id();
-    LT x = (LT)bi;
+    LT x = (LT)__shfl(bi, pi);
+#pragma unroll 4
     for (int k = 0; k < N; k++) {
-        const int p = uniform(L.perm[k]);
-        if (p != k) {
-            const LT a = lane_value(x, k), b = lane_value(x, p);
-            if (lane == k) x = b;
-            if (lane == p) x = a;
-        }
-    }
-    for (int k = 0; k < N; k++) {
+        const LT a = (lane > k && lane < N) ? L.row[lane][k] : (LT)0;
         const LT xk = lane_value(x, k);
-        if (lane > k && lane < N) x -= L.row[lane][k] * xk;
+        x -= a * xk;
     }
+#pragma unroll 4
     for (int k = N - 1; k >= 0; k--) {
-        if (lane == k) x = x / L.row[k][k];
+        if (lane == k) x = x * dinv;
+        const LT a = (lane < k) ? L.row[lane][k] : (LT)0;
         const LT xk = lane_value(x, k);
-        if (lane < k) x -= L.row[lane][k] * xk;
+        x -= a * xk;
     }
     return lane < N ? (double)x : 0.0;
 }
@@ -355,6 +372,10 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
         sp.W = m.W[k];
         sp.invW = m.invW[k];
     }
+    if (lane <= K) L.invW[lane] = lane < K ? sp.invW : 0.0;
+    __syncthreads();
+    int lu_pi = lane;       // factorisation's row permutation (this lane's entry)
+    LT lu_dinv = (LT)0;     // reciprocal of this lane's diagonal element of U
     for (;;) {
         unsigned long long c = 0;
         if (lane == 0) c = atomicAdd(queue, 1ull);
@@ -481,7 +502,7 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                 if (!have_M || force_M || nst >= nst_M + kMsbp || fabs(gamma / gamma_M - 1.0) > kDgmax) {
                     wave_newton_matrix<NP, LT>(m, wt, L, sp, K, p, z[0], gamma, qbuf);
                     nje++;
-                    lu_ok = wave_lu<NP, LT>(L, N);
+                    lu_ok = wave_lu<NP, LT>(L, N, lu_pi, lu_dinv);
                     gamma_M = gamma;
                     nst_M = nst;
                     crate = 1.0;
@@ -498,7 +519,7 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                         nfe++;
                         if (!all_finite(fy)) break;
                         double d = active ? -(e - gamma * fy + z[1] * inv_l1) : 0.0;
-                        d = wave_solve<NP, LT>(L, N, d);
+                        d = wave_solve<NP, LT>(L, N, lu_pi, lu_dinv, d);
                         if (!active) d = 0.0;
                         if (gamma != gamma_M) d *= 2.0 / (1.0 + gamma / gamma_M);
                         const double dl = wnorm(d);
