@@ -340,18 +340,37 @@ __device__ __forceinline__ double wave_solve(const WaveLds<NP, LT> &L, int N, in
 {
     const int lane = lane_id();
     LT x = (LT)__shfl(bi, pi);
-#pragma unroll 4
-    for (int k = 0; k < N; k++) {
-        const LT a = (lane > k && lane < N) ? L.row[lane][k] : (LT)0;
-        const LT xk = lane_value(x, k);
-        x -= a * xk;
+    // the lane's matrix elements are read eight at a time ahead of the
+    // broadcast chain, which then runs on registers
+    constexpr int B = 8;
+    for (int k0 = 0; k0 < N; k0 += B) {
+        LT a[B];
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            const int k = k0 + j;
+            a[j] = (k < N && lane > k && lane < N) ? L.row[lane][k] : (LT)0;
+        }
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            const int k = k0 + j;
+            if (k < N) x -= a[j] * lane_value(x, k);
+        }
     }
-#pragma unroll 4
-    for (int k = N - 1; k >= 0; k--) {
-        if (lane == k) x = x * dinv;
-        const LT a = (lane < k) ? L.row[lane][k] : (LT)0;
-        const LT xk = lane_value(x, k);
-        x -= a * xk;
+    for (int k1 = N - 1; k1 >= 0; k1 -= B) {
+        LT a[B];
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            const int k = k1 - j;
+            a[j] = (k >= 0 && lane < k) ? L.row[lane][k] : (LT)0;
+        }
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            const int k = k1 - j;
+            if (k >= 0) {
+                if (lane == k) x = x * dinv;
+                x -= a[j] * lane_value(x, k);
+            }
+        }
     }
     return lane < N ? (double)x : 0.0;
 }

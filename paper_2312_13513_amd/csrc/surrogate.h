@@ -95,8 +95,8 @@ hipError_t launch_gather_rows(const int32_t *order, int64_t start, int64_t rows,
 // (FP64, accumulated over calls), dOut = bf16(2 (out - y) / (rows K)).
 hipError_t launch_loss_grad(const float *out, const float *Yb, int rows, int K, int nout_pad,
                             bf16_t *dOut, double *loss_acc, hipStream_t s);
-// db[n] = sum over rows of d[r][n].
-hipError_t launch_bias_grad(const bf16_t *d, int rows, int N, int ld, float *db, hipStream_t s);
+// db[n] = sum over rows of d[r][n]; part: 64 x N floats of workspace.
+hipError_t launch_bias_grad(const bf16_t *d, int rows, int N, int ld, float *part, float *db, hipStream_t s);
 // Adam on FP32 master weights, BF16 copies refreshed from them.
 struct AdamArgs {
     float *p, *m, *v;

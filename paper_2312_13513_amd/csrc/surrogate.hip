@@ -234,24 +234,31 @@ __global__ void __launch_bounds__(256) fit_norm_kernel(const double *__restrict_
 // ---------------------------------------------------------------------------
 constexpr double kRuS = 8.31446261815324;
 
-// mass-specific enthalpy and cp of the mixture Y[k * ys]
-__device__ void mix_h_cp(const ApplyArgs &a, double T, const double *Y, int ys, double &hm, double &cm)
+// mass-specific enthalpy and cp of the mixture Y[0..K) (KM >= K, static loop)
+template <int KM>
+__device__ __forceinline__ void mix_h_cp(const ApplyArgs &a, double T, const double (&Y)[KM], double &hm,
+                                         double &cm)
 {
     double h = 0.0, c = 0.0;
     const double invT = 1.0 / T;
-    for (int k = 0; k < a.K; k++) {
-        const double *s = a.species + k * kSpeciesLen;
-        const double *r = (!a.two_range || T < s[0]) ? s + 1 : s + 1 + kRangeLen;
-        const double cp = r[0] + T * (r[1] + T * (r[2] + T * (r[3] + T * r[4])));
-        const double hrt = r[0] + T * (r[7] + T * (r[8] + T * (r[9] + T * r[10]))) + r[5] * invT;
-        const double y = Y[(int64_t)k * ys];
-        h += y * kRuS * T * hrt / a.W[k];
-        c += y * kRuS * cp / a.W[k];
+#pragma unroll
+    for (int k = 0; k < KM; k++) {
+        if (k < a.K) {
+            const double *s = a.species + k * kSpeciesLen;
+            const double *r = (!a.two_range || T < s[0]) ? s + 1 : s + 1 + kRangeLen;
+            const double cp = r[0] + T * (r[1] + T * (r[2] + T * (r[3] + T * r[4])));
+            const double hrt = r[0] + T * (r[7] + T * (r[8] + T * (r[9] + T * r[10]))) + r[5] * invT;
+            h += Y[k] * kRuS * T * hrt / a.W[k];
+            c += Y[k] * kRuS * cp / a.W[k];
+        }
     }
     hm = h;
     cm = c;
 }
 
+// KM: a compile-time bound on the species count, so that the cell's mass
+// fractions stay in registers.
+template <int KM>
 __global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restrict__ T,
                                                     const double *__restrict__ p,
                                                     double *__restrict__ Y, int64_t ldY, int64_t n,
@@ -267,24 +274,32 @@ __global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restr
         (void)p;
         const int K = a.K;
         const double T0 = T[i];
-        double Y1[kMaxSurrSpecies];
+        double Y0[KM], Y1[KM];
         bool ok = true;
         double sum = 0.0, ymin = 1e300;
-        for (int k = 0; k < K; k++) {
-            const double y = Y[(int64_t)k * ldY + i];
-            const double v = y + a.mu_y[k] + a.sig_y[k] * (double)out[i * nout_pad + k];
-            Y1[k] = v;
-            ok = ok && isfinite(v);
-            sum += v;
-            ymin = fmin(ymin, v);
+#pragma unroll
+        for (int k = 0; k < KM; k++) {
+            Y0[k] = 0.0;
+            Y1[k] = 0.0;
+            if (k < K) {
+                Y0[k] = Y[(int64_t)k * ldY + i];
+                const double v = Y0[k] + a.mu_y[k] + a.sig_y[k] * (double)out[i * nout_pad + k];
+                Y1[k] = v;
+                ok = ok && isfinite(v);
+                sum += v;
+                ymin = fmin(ymin, v);
+            }
         }
         // element residual relative to the element content of the input
         for (int e = 0; ok && e < a.E; e++) {
             double res = 0.0, ref = 0.0;
-            for (int k = 0; k < K; k++) {
-                const double nk = a.counts[e * K + k] / a.W[k];
-                res += nk * (Y1[k] - Y[(int64_t)k * ldY + i]);
-                ref += nk * Y[(int64_t)k * ldY + i];
+#pragma unroll
+            for (int k = 0; k < KM; k++) {
+                if (k < K) {
+                    const double nk = a.counts[e * K + k] / a.W[k];
+                    res += nk * (Y1[k] - Y0[k]);
+                    ref += nk * Y0[k];
+                }
             }
             if (fabs(res) / fmax(ref, 1e-12) > a.elem_tol) ok = false;
         }
@@ -293,31 +308,27 @@ __global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restr
         double Tn = T0;
         if (ok) {
             double s2 = 0.0;
-            for (int k = 0; k < K; k++) {
-                Y1[k] = fmax(Y1[k], 0.0);
-                s2 += Y1[k];
-            }
-            for (int k = 0; k < K; k++) Y1[k] = Y1[k] / s2;
-            double h0;
-            // enthalpy of the input state
-            {
-                double h = 0.0;
-                const double invT = 1.0 / T0;
-                for (int k = 0; k < K; k++) {
-                    const double *s = a.species + k * kSpeciesLen;
-                    const double *r = (!a.two_range || T0 < s[0]) ? s + 1 : s + 1 + kRangeLen;
-                    const double hrt = r[0] + T0 * (r[7] + T0 * (r[8] + T0 * (r[9] + T0 * r[10]))) + r[5] * invT;
-                    h += Y[(int64_t)k * ldY + i] * kRuS * T0 * hrt / a.W[k];
+#pragma unroll
+            for (int k = 0; k < KM; k++) {
+                if (k < K) {
+                    Y1[k] = fmax(Y1[k], 0.0);
+                    s2 += Y1[k];
                 }
-                h0 = h;
             }
+#pragma unroll
+            for (int k = 0; k < KM; k++)
+                if (k < K) Y1[k] = Y1[k] / s2;
+            // enthalpy of the input state
+            double h0, c0;
+            mix_h_cp<KM>(a, T0, Y0, h0, c0);
+            (void)c0;
             // Newton on h(T, Y2) = h0 from T0; |dT| < 1e-10 K, at most 20
             // iterations, T kept in [200, 3500] K
             bool conv = false;
             double Tk = T0;
             for (int it = 0; it < 20; it++) {
                 double hm, cm;
-                mix_h_cp(a, Tk, Y1, 1, hm, cm);
+                mix_h_cp<KM>(a, Tk, Y1, hm, cm);
                 const double dT = -(hm - h0) / cm;
                 Tk += dT;
                 Tk = fmin(fmax(Tk, 200.0), 3500.0);
@@ -333,7 +344,9 @@ __global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restr
         }
         if (ok) {
             T[i] = Tn;
-            for (int k = 0; k < K; k++) Y[(int64_t)k * ldY + i] = Y1[k];
+#pragma unroll
+            for (int k = 0; k < KM; k++)
+                if (k < K) Y[(int64_t)k * ldY + i] = Y1[k];
         }
         if (mask) mask[i] = ok ? 0 : 1;
         if (status) status[i] = 0;
@@ -452,13 +465,31 @@ __global__ void sum_partials_kernel(const double *__restrict__ partial, int np, 
     }
 }
 
-__global__ void __launch_bounds__(256) bias_grad_kernel(const bf16_t *__restrict__ d, int rows, int N,
-                                                        int ld, float *__restrict__ db)
+// Column sums in two passes with a fixed order: block (column tile, row
+// chunk) sums its rows per column into part[chunk][n], then the chunks are
+// added in chunk order.
+constexpr int kBiasChunks = 64;
+
+__global__ void __launch_bounds__(64) bias_grad_part_kernel(const bf16_t *__restrict__ d, int rows, int N,
+                                                            int ld, float *__restrict__ part)
+{
+    const int n = blockIdx.x * 64 + threadIdx.x;
+    const int chunk = blockIdx.y;
+    const int per = (rows + kBiasChunks - 1) / kBiasChunks;
+    const int r0 = chunk * per, r1 = min(rows, r0 + per);
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int r = r0; r < r1; r++) s += __uint_as_float((unsigned)d[(int64_t)r * ld + n] << 16);
+    part[chunk * N + n] = s;
+}
+
+__global__ void __launch_bounds__(256) bias_grad_final_kernel(const float *__restrict__ part, int N,
+                                                              float *__restrict__ db)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float s = 0.0f;
-    for (int r = 0; r < rows; r++) s += __uint_as_float((unsigned)d[(int64_t)r * ld + n] << 16);
+    for (int c = 0; c < kBiasChunks; c++) s += part[c * N + n];
     db[n] = s;
 }
 
@@ -528,8 +559,20 @@ hipError_t launch_apply(const ApplyArgs &a, double *T, const double *p, double *
                         int32_t *status, int32_t *list, int64_t *count, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(apply_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, ldY, n,
-                       base, out, nout_pad, mask, status, list, count);
+#define CHEM_APPLY(KM)                                                                                  \
+    hipLaunchKernelGGL(apply_kernel<KM>, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, ldY, n, base, \
+                       out, nout_pad, mask, status, list, count)
+    if (a.K <= 16)
+        CHEM_APPLY(16);
+    else if (a.K <= 32)
+        CHEM_APPLY(32);
+    else if (a.K <= 48)
+        CHEM_APPLY(48);
+    else if (a.K <= kMaxSurrSpecies)
+        CHEM_APPLY(kMaxSurrSpecies);
+    else
+        return hipErrorInvalidValue;
+#undef CHEM_APPLY
     return hipGetLastError();
 }
 
@@ -580,9 +623,11 @@ hipError_t launch_loss_grad(const float *out, const float *Yb, int rows, int K, 
     return hipGetLastError();
 }
 
-hipError_t launch_bias_grad(const bf16_t *d, int rows, int N, int ld, float *db, hipStream_t s)
+hipError_t launch_bias_grad(const bf16_t *d, int rows, int N, int ld, float *part, float *db, hipStream_t s)
 {
-    hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, d, rows, N, ld, db);
+    hipLaunchKernelGGL(bias_grad_part_kernel, dim3(blocks_for(N, 64), kBiasChunks), dim3(64), 0, s, d, rows, N, ld,
+                       part);
+    hipLaunchKernelGGL(bias_grad_final_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, part, N, db);
     return hipGetLastError();
 }
 

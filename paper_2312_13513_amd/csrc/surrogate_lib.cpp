@@ -109,7 +109,7 @@ int64_t norm_len(const chem_surr_s *s) { return 2 * (int64_t)s->nin + 2 * (int64
 // `train` also U1..U3 (FP32), Yb (FP32), dOut, D1..D3 (BF16).
 struct Acts {
     bf16_t *X, *H[3], *dOut, *D[3];
-    float *OUT, *U[3], *Yb;
+    float *OUT, *U[3], *Yb, *bpart;
 };
 
 size_t acts_bytes(const chem_surr_s *s, int64_t rows, bool train)
@@ -119,6 +119,7 @@ size_t acts_bytes(const chem_surr_s *s, int64_t rows, bool train)
     if (train) {
         for (int l = 0; l < 3; l++) b += carve_size<float>(rows * s->h[l]) + carve_size<bf16_t>(rows * s->h[l]);
         b += carve_size<float>(rows * s->nout_pad) + carve_size<bf16_t>(rows * s->nout_pad);
+        b += carve_size<float>(64 * 4096);
     }
     return b;
 }
@@ -150,6 +151,7 @@ Acts carve_acts(const chem_surr_s *s)
         }
         a.Yb = c.take<float>(rows * s->nout_pad);
         a.dOut = c.take<bf16_t>(rows * s->nout_pad);
+        a.bpart = c.take<float>(64 * 4096);
     }
     return a;
 }
@@ -194,7 +196,8 @@ hipError_t backward(const chem_surr_s *s, const Acts &a, const bf16_t *X, int ro
         // dW[n][k] = sum_r d[r][n] h[r][k]
         e = gemm(d, 1, ldd, hin, 1, Kin, Nout, Kin, rows, chem::kEpiF32, nullptr,
                  s->grad + s->off_W[l], Kin, nullptr, 0, nullptr, 0, st);
-        if (e == hipSuccess) e = chem::launch_bias_grad(d, rows, Nout, (int)ldd, s->grad + s->off_b[l], st);
+        if (e == hipSuccess)
+            e = chem::launch_bias_grad(d, rows, Nout, (int)ldd, a.bpart, s->grad + s->off_b[l], st);
         if (l > 0 && e == hipSuccess) {
             // d_prev[r][k] = (sum_n d[r][n] W[n][k]) * gelu'(u_prev[r][k])
             e = gemm(d, ldd, 1, s->wbf + s->off_W[l], 1, Kin, rows, Kin, Nout, chem::kEpiGeluGradBf16,
