@@ -20,7 +20,9 @@ Other workloads (``--workload``):
              flame field (4,194,304 cells, 35 species, dt = 1e-5): training
              states labelled by the GPU integrator, training on the GPU, then
              timed inference steps against the plain integrator on the same
-             cells and the oracle on a sample.
+             cells and the oracle on a sample.  --field flame256 serves the
+             256^3 field (16,777,216 cells) and --graph replays the captured
+             step; the plain integrator then runs on a seeded sample.
 """
 from __future__ import annotations
 
@@ -103,6 +105,10 @@ def kernel_name(mech, schedule: int, precision: int) -> str:
     if mech.variant.startswith("specialised:"):
         return f"bdf_queue_kernel<GenMech_{mech.variant.split(':')[1]}>"
     return f"bdf_queue_kernel<TableMech<{mech.K}>>"
+
+
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def mech_file(name: str):
@@ -270,6 +276,7 @@ def run_surrogate(args):
     torch.cuda.synchronize()
     n_train = Td.shape[0]
     log["label_s"] = time.perf_counter() - t0
+    progress(f"labelled {n_train} training states in {log['label_s']:.1f} s")
     # ---- training on the GPU
     t0 = time.perf_counter()
     surr = chem.Surrogate(mech, 512, 256, 128)
@@ -278,12 +285,14 @@ def run_surrogate(args):
     order = t(epoch_orders(n_train, args.epochs, 10), torch.int32)
     losses = surr.train(Td, pd, Yd, Yn, epochs=args.epochs, batch=4096, lr0=1e-3, lr1=1e-5, order=order)
     log["train_s"] = time.perf_counter() - t0
+    progress(f"trained {args.epochs} epochs in {log['train_s']:.1f} s")
     del Td, pd, Yd, Yn, Tn, order
     torch.cuda.empty_cache()
     # ---- the served field
     field = F.flame256x128x128(mpy) if args.field == "flame256x128x128" else F.flame256(mpy)
     n = field.n
     T0, p0, Y0 = t(field.T), t(field.p), t(field.Y)
+    progress(f"served field {field.name}: {n} cells")
     T, Y = T0.clone(), Y0.clone()
     mask = torch.zeros(n, dtype=torch.int32, device=dev)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -298,17 +307,36 @@ def run_surrogate(args):
         if ev is not None:
             ev[1].record(stream)
 
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):
         step()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
+    graph = None
+    if args.graph:
+        # the whole flow step (restore + surrogate + fallback) as one HIP graph
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                T.copy_(T0)
+                Y.copy_(Y0)
+                surr.infer(T, p0, Y, dt, mask=mask, fallback_count=cnt, stream=side)
+        torch.cuda.synchronize()
+        graph.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(events[k])
+        if graph is not None:
+            events[k][0].record(stream)
+            graph.replay()
+            events[k][1].record(stream)
+        else:
+            step(events[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    progress(f"{args.steps} timed surrogate steps: {wall / args.steps * 1e3:.2f} ms per step")
     Ts_, Ys_ = T.cpu().numpy(), Y.cpu().numpy()
     nfb = int(cnt.item())
     # forward pass alone: algorithmic MFMA flops over its time
@@ -324,15 +352,21 @@ def run_surrogate(args):
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1) / 10
     fwd_flops = 2.0 * X.shape[0] * ((K + 2) * 512 + 512 * 256 + 256 * 128 + 128 * K)
-    # ---- plain integrator on the same cells (one timed step)
-    Tp, Yp = T0.clone(), Y0.clone()
+    # ---- plain integrator on the same cells (one timed step; a seeded
+    # sample of the cells when the field is larger than --plain-cells)
+    from chemgen.fields import seeded_sample
+    pidx = np.arange(n) if n <= args.plain_cells else seeded_sample(n, args.plain_cells, seed=11)
+    Tp, Yp = t(field.T[pidx]), t(field.Y[:, pidx])
+    pp = t(field.p[pidx])
     opts = chem.chem_default_opts()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mech.integrate(Tp, p0, Yp, dt, opts=opts)
+    mech.integrate(Tp, pp, Yp, dt, opts=opts)
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
+    progress(f"plain integrator on {pidx.size} cells: {plain_s:.2f} s")
     Tp_ = Tp.cpu().numpy()
+    n_plain = pidx.size
     result = {
         "metric": METRIC, "value": n * args.steps / wall, "unit": "cell-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
@@ -348,9 +382,11 @@ def run_surrogate(args):
                      "rows": int(X.shape[0])},
         "fallback_frac": nfb / n,
         "surrogate_step_ms": kern_ms,
-        "plain_gpu": {"value": n / plain_s, "unit": "cell-steps/s", "ms_per_step": plain_s * 1e3},
-        "speedup_vs_plain_gpu": (n * args.steps / wall) / (n / plain_s),
-        "max_dT_vs_plain_gpu": float(np.abs(Ts_ - Tp_).max()),
+        "plain_gpu": {"value": n_plain / plain_s, "unit": "cell-steps/s", "cells": int(n_plain),
+                      "ms": plain_s * 1e3},
+        "speedup_vs_plain_gpu": (n * args.steps / wall) / (n_plain / plain_s),
+        "max_dT_vs_plain_gpu": float(np.abs(Ts_[pidx] - Tp_).max()),
+        "graph": bool(args.graph),
         "train": {"samples": n_train, "epochs": args.epochs, "loss_first": float(losses[0]),
                   "loss_last": float(losses[-1]), "label_s": log["label_s"], "train_s": log["train_s"]},
     }
@@ -382,6 +418,9 @@ def main():
     ap.add_argument("--traj-steps", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--field", default="flame256x128x128", choices=("flame256x128x128", "flame256"))
+    ap.add_argument("--graph", action="store_true", help="surrogate: replay the step as one captured HIP graph")
+    ap.add_argument("--plain-cells", type=int, default=4194304,
+                    help="surrogate: cells of the plain-integrator comparison (a seeded sample when fewer)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB three times (scales the HBM "
                          "byte counters of a profiler run)")

@@ -72,8 +72,10 @@ typedef struct {
                            kernel exists and precision is 0, else one wave per
                            cell), 0 = one thread per cell (K <= 9 table kernel or
                            a compiled-in mechanism), 1 = one 64-lane wave per
-                           cell (any K <= 63).  CHEM_EUNSUP when the chosen
-                           schedule cannot serve the mechanism or precision. */
+                           cell (any K <= 63), 2 = tile: 16 lanes per cell, four
+                           cells per wave (K <= 15; the same operations per
+                           cell as 1).  CHEM_EUNSUP when the chosen schedule
+                           cannot serve the mechanism or precision. */
     int32_t block;      /* threads per block, 0 = library choice */
     int32_t jac_batch;  /* one-thread-per-cell kernels: lanes of a wave that wait for
                            a new Newton matrix before the Jacobian is evaluated
@@ -133,7 +135,8 @@ int chem_lpt_order(const int32_t *cost, int64_t n, int32_t *order, void *hip_str
 
 /* Autotuner: times every schedule that can serve the mechanism at
  * opts->precision (one thread per cell with jac_batch 4, 16, 64; one wave
- * per cell), each in natural and in LPT order, on a strided sample of at
+ * per cell; the 16-lane tile when K <= 15), each in natural and in LPT
+ * order, on a strided sample of at
  * most max_sample cells (0 = 65,536) of the given states (not modified),
  * and returns the fastest as *best (schedule, jac_batch filled in),
  * *use_lpt (1 if the LPT order was faster) and *best_ms.  The choice is also

@@ -141,6 +141,7 @@ int chem_autotune(chem_mech m, const double *T, const double *p, const double *Y
     };
     const bool thread_ok = (m->gen != nullptr || chem::thread_kernel_supports(K)) && o0.precision == 0;
     const bool wave_ok = chem::wave_kernel_rows(K + 1) > 0;
+    const bool tile_ok = K + 1 <= 16;
     struct Cand {
         int schedule, jac_batch, lpt;
     };
@@ -149,6 +150,7 @@ int chem_autotune(chem_mech m, const double *T, const double *p, const double *Y
         if (thread_ok)
             for (int jb : {4, 16, 64}) cands.push_back({0, jb, l});
         if (wave_ok) cands.push_back({1, 0, l});
+        if (tile_ok) cands.push_back({2, 0, l});
     }
     // a first run in natural order gives the per-cell step counts for LPT
     float best_t = 1e30f;

@@ -1,4 +1,5 @@
-// Wave-per-cell integrator (bdf_wave.hip): tables and launcher.
+// Wave-per-cell and tile (16 lanes per cell) integrators (bdf_wave.hip):
+// tables and launcher.
 #pragma once
 
 #include "chem_internal.h"
@@ -16,9 +17,12 @@ struct WaveTables {
 // Padded row count of the wave kernel for N unknowns (0 = unsupported).
 int wave_kernel_rows(int N);
 
+// lanes = 64: one wave per cell (N <= 64); lanes = 16: four cells per wave
+// (N <= 16).  qscratch holds max_groups slices of 7 R doubles, used when the
+// reaction scratch of a wave does not fit in 32 KB of LDS.
 hipError_t launch_bdf_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
                            double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
                            int32_t *status, int32_t *counters, unsigned long long *queue,
-                           double *qscratch, int max_waves, bool fp32_lu, hipStream_t s);
+                           double *qscratch, int max_groups, bool fp32_lu, int lanes, hipStream_t s);
 
 }  // namespace chem

@@ -1,15 +1,17 @@
-// Wave-per-cell BDF integrator for larger mechanisms on gfx950.
+// Lane-group BDF integrators on gfx950: one 64-lane wave per cell (larger
+// mechanisms), or one 16-lane tile per cell with four cells per wave (N <= 16).
 //
-// One 64-lane wave owns one cell at a time and takes the next from a work
-// queue.  Lane i owns component i of every state vector (Nordsieck column,
-// correction, weights) and row i of the Newton matrix, in registers; lanes
-// cooperate on the right-hand side (lane k: thermo of species k; lane j:
-// reactions j, j+64, ...) through LDS.  Sums over reactions are gathered by
-// the owning species lane in a fixed order, so results do not depend on
-// timing.  Control flow is uniform across the wave: every decision of the
-// integrator contract (the same as the one-thread-per-cell driver and the CPU
-// oracle) is taken once per cell, so cells of very different stiffness do not
-// hold each other back.
+// A group of G lanes owns one cell at a time and takes the next from a work
+// queue as soon as that cell is done.  Lane i owns component i of every state
+// vector (Nordsieck column, correction, weights); the Newton matrix and its
+// LU factors live in LDS (lane i: row i); lanes cooperate on the right-hand
+// side (lane k: thermo of species k; lane j: reactions j, j+G, ...) through
+// LDS.  Sums over reactions are gathered by the owning species lane in a
+// fixed order, so results do not depend on timing.  Control flow is uniform
+// within a group: every decision of the integrator contract (the same as the
+// one-thread-per-cell driver and the CPU oracle) is taken once per cell, so
+// cells of very different stiffness do not hold each other back; the groups
+// of one wave diverge like the lanes of any SIMT program.
 //
 // NP is the padded row count (a compile-time bound on N = K+1 <= 64).  LT is
 // the type of the Jacobian, the Newton matrix, its LU factors and the
@@ -23,18 +25,23 @@
 namespace chem {
 namespace {
 
-constexpr int kWaveLanes = 64;
+// Lanes that own one cell: Grp<64> is a whole wave (one cell per wave),
+// Grp<16> one DPP row of 16 lanes (four cells per wave, the tile schedule).
+// Within a group every decision is uniform; groups of one wave follow their
+// own cells and diverge freely.  Every primitive below needs all lanes of
+// the calling group active, and touches no lane outside it.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
 
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-
-// Cross-lane moves of a double through DPP (row-local permutations).  Every
-// lane of the wave must be active.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = dpp_i32<CTRL>((int)(b & 0xffffffffll));
+    const int hi = dpp_i32<CTRL>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -46,54 +53,136 @@ __device__ __forceinline__ double readlane_f64(double v, int src)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Sum over the 64 lanes, the same value in every lane: pairwise within quads
-// (xor 1, xor 2), then the mirrored halves of 8 and of 16 lanes (each a
-// commutative pair, so all lanes of a row agree), then the four row sums in
-// a fixed order.
-__device__ __forceinline__ double wave_sum(double v)
+__device__ __forceinline__ double bpermute_f64(double v, int src_lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 16 lanes of each DPP row, the same value in every lane of the
+// row: pairwise within quads (xor 1, xor 2), then the mirrored halves of 8
+// and of 16 lanes (each a commutative pair, so all lanes of a row agree).
+__device__ __forceinline__ double row_sum(double v)
 {
     v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
     v += dpp_f64<0x141>(v);   // row_half_mirror
     v += dpp_f64<0x140>(v);   // row_mirror
-    return ((readlane_f64(v, 15) + readlane_f64(v, 31)) + readlane_f64(v, 47)) + readlane_f64(v, 63);
+    return v;
 }
 
-__device__ __forceinline__ double wave_max(double v)
+__device__ __forceinline__ double row_max(double v)
 {
     v = fmax(v, dpp_f64<0xB1>(v));
     v = fmax(v, dpp_f64<0x4E>(v));
     v = fmax(v, dpp_f64<0x141>(v));
     v = fmax(v, dpp_f64<0x140>(v));
-    return fmax(fmax(readlane_f64(v, 15), readlane_f64(v, 31)), fmax(readlane_f64(v, 47), readlane_f64(v, 63)));
+    return v;
 }
 
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// lane S of each row, to every lane of the row (row_newbcast)
+template <int S>
+__device__ __forceinline__ double row_bcast(double v) { return dpp_f64<0x150 + S>(v); }
+template <int S>
+__device__ __forceinline__ float row_bcast(float v) { return __int_as_float(dpp_i32<0x150 + S>(__float_as_int(v))); }
 
-// value of lane src (src wave-uniform), for every lane regardless of EXEC
-__device__ __forceinline__ double lane_value(double v, int src) { return readlane_f64(v, src); }
-__device__ __forceinline__ float lane_value(float v, int src)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
-}
+template <int G>
+struct Grp;
 
-// Lowest candidate lane holding the largest |v| (-1 if no candidate has a
-// comparable value).
-__device__ __forceinline__ int wave_argmax(double v, bool cand)
+template <>
+struct Grp<64> {
+    static constexpr int kCells = 1;
+    __device__ static int lane() { return threadIdx.x & 63; }
+    __device__ static int slot() { return 0; }
+    // the four row sums added in a fixed order
+    __device__ static double sum(double v)
+    {
+        v = row_sum(v);
+        return ((readlane_f64(v, 15) + readlane_f64(v, 31)) + readlane_f64(v, 47)) + readlane_f64(v, 63);
+    }
+    __device__ static double max(double v)
+    {
+        v = row_max(v);
+        return fmax(fmax(readlane_f64(v, 15), readlane_f64(v, 31)), fmax(readlane_f64(v, 47), readlane_f64(v, 63)));
+    }
+    // value of lane src (the same src in every lane of the wave)
+    __device__ static double at(double v, int src) { return readlane_f64(v, src); }
+    __device__ static float at(float v, int src) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src)); }
+    __device__ static int at(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+    // value of lane k, k a constant after unrolling
+    template <typename V>
+    __device__ static V at_k(V v, int k) { return at(v, k); }
+    // value of lane src of the group, src chosen per lane
+    __device__ static double gather(double v, int src) { return __shfl(v, src); }
+    __device__ static unsigned long long ballot(bool b) { return __ballot(b); }
+    __device__ static unsigned long long first(unsigned long long v) { return __shfl(v, 0); }
+    __device__ static void sync() { __syncthreads(); }
+};
+
+template <>
+struct Grp<16> {
+    static constexpr int kCells = 4;
+    __device__ static int lane() { return threadIdx.x & 15; }
+    __device__ static int slot() { return (threadIdx.x >> 4) & 3; }
+    __device__ static double sum(double v) { return row_sum(v); }
+    __device__ static double max(double v) { return row_max(v); }
+    __device__ static double at(double v, int src) { return bpermute_f64(v, (threadIdx.x & 48) + src); }
+    __device__ static int at(int v, int src) { return __builtin_amdgcn_ds_bpermute(((threadIdx.x & 48) + src) << 2, v); }
+    // k must fold to a constant (fully unrolled loops): one DPP broadcast
+    template <typename V>
+    __device__ static V at_k(V v, int k)
+    {
+        switch (k) {
+        case 0: return row_bcast<0>(v);
+        case 1: return row_bcast<1>(v);
+        case 2: return row_bcast<2>(v);
+        case 3: return row_bcast<3>(v);
+        case 4: return row_bcast<4>(v);
+        case 5: return row_bcast<5>(v);
+        case 6: return row_bcast<6>(v);
+        case 7: return row_bcast<7>(v);
+        case 8: return row_bcast<8>(v);
+        case 9: return row_bcast<9>(v);
+        case 10: return row_bcast<10>(v);
+        case 11: return row_bcast<11>(v);
+        case 12: return row_bcast<12>(v);
+        case 13: return row_bcast<13>(v);
+        case 14: return row_bcast<14>(v);
+        default: return row_bcast<15>(v);
+        }
+    }
+    __device__ static double gather(double v, int src) { return bpermute_f64(v, (threadIdx.x & 48) + src); }
+    __device__ static unsigned long long ballot(bool b) { return (__ballot(b) >> (threadIdx.x & 48)) & 0xFFFFull; }
+    __device__ static unsigned long long first(unsigned long long v)
+    {
+        const int lo = dpp_i32<0x150>((int)(v & 0xffffffffull)), hi = dpp_i32<0x150>((int)(v >> 32));
+        return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    }
+    // LDS written by some lanes of the group, then read by others: the DS
+    // instructions of one wave execute in order, so ordering them in the
+    // instruction stream (and waiting for completion) is enough
+    __device__ static void sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+};
+
+// Lowest candidate lane of the group holding the largest |v| (-1 if no
+// candidate has a comparable value).
+template <int G>
+__device__ __forceinline__ int group_argmax(double v, bool cand)
 {
     const double a = cand ? fabs(v) : -1.0;
-    const double best = wave_max(a);
-    const unsigned long long hit = __ballot(cand && a == best);
+    const double best = Grp<G>::max(a);
+    const unsigned long long hit = Grp<G>::ballot(cand && a == best);
     return hit ? (int)__ffsll((long long)hit) - 1 : -1;
 }
 
-template <int NP, typename LT>
+template <int NP, typename LT, int G>
 struct WaveLds {
-    double C[kWaveLanes + 1], g[kWaveLanes + 1], h[kWaveLanes + 1];
-    double invW[kWaveLanes + 1];   // 1 / W_k, 0 for the sentinel slot (set once)
+    double C[G + 1], g[G + 1], h[G + 1];
+    double invW[G + 1];   // 1 / W_k, 0 for the sentinel slot (set once)
     LT row[NP][NP + 2];   // Jacobian rows, then the LU factors of I - gamma J;
                           // column NP+1 collects sentinel slots
-    int perm[NP];         // pivot row of each elimination step
     LT lcol[NP];          // multipliers of the current elimination step
 };
 
@@ -120,19 +209,20 @@ __device__ __forceinline__ void lane_thermo(const SpeciesLane &s, bool two_range
 }
 
 // f(y): each lane passes its component yi and receives fi.
-template <int NP, typename LT>
-__device__ __forceinline__ double wave_rhs(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT> &L,
+template <int NP, typename LT, int G>
+__device__ __forceinline__ double wave_rhs(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT, G> &L,
                            const SpeciesLane &sp, int K, double p, double yi, double *qbuf)
 {
-    const int lane = lane_id();
-    const double T = lane_value(yi, K);
+    using Gp = Grp<G>;
+    const int lane = Gp::lane();
+    const double T = Gp::at(yi, K);
     const double invT = 1.0 / T;
     const double lnT = log(T);
     double cpk = 0.0, hk = 0.0, gk = 0.0, dcpk = 0.0;
     if (lane < K) lane_thermo(sp, m.two_range, T, invT, lnT, cpk, hk, gk, dcpk);
-    const double sumYW = wave_sum(lane < K ? yi * sp.invW : 0.0);
+    const double sumYW = Gp::sum(lane < K ? yi * sp.invW : 0.0);
     const double rho = p / (kRu * T * sumYW);
-    const double cpm = kRu * wave_sum(lane < K ? yi * cpk * sp.invW : 0.0);
+    const double cpm = kRu * Gp::sum(lane < K ? yi * cpk * sp.invW : 0.0);
     if (lane < K) {
         L.C[lane] = rho * yi * sp.invW;
         L.g[lane] = gk;
@@ -140,16 +230,16 @@ __device__ __forceinline__ double wave_rhs(const DevMechView &m, const WaveTable
         L.C[K] = 1.0;
         L.g[K] = 0.0;
     }
-    __syncthreads();
+    Gp::sync();
     const double ln_c0 = log(kPstd / kRu) - lnT;
-    for (int r = lane; r < m.R; r += kWaveLanes) {
+    for (int r = lane; r < m.R; r += G) {
         const DevRxn x = m.rxn[r];
         const double lnkf = x.lnA + x.b * lnT - x.Ea_R * invT;
         const double dg = L.g[x.p0] + L.g[x.p1] - L.g[x.r0] - L.g[x.r1];
         const double lnkr = lnkf + dg - x.dnu * ln_c0;
         qbuf[r] = exp(lnkf) * L.C[x.r0] * L.C[x.r1] - exp(lnkr) * L.C[x.p0] * L.C[x.p1];
     }
-    __syncthreads();
+    Gp::sync();
     double wk = 0.0;
     if (lane < K) {
         const int b = wt.inc_off[lane], e = wt.inc_off[lane + 1];
@@ -159,31 +249,32 @@ __device__ __forceinline__ double wave_rhs(const DevMechView &m, const WaveTable
             wk += (double)ent.y * qbuf[ent.x];
         }
     }
-    const double heat = wave_sum(lane < K ? hk * wk : 0.0);
-    __syncthreads();
+    const double heat = Gp::sum(lane < K ? hk * wk : 0.0);
+    Gp::sync();
     if (lane < K) return sp.W * wk / rho;
     if (lane == K) return -(kRu * T) * heat / (rho * cpm);
     return 0.0;
 }
 
 // Row `lane` of M = I - gamma J at the state yi.
-template <int NP, typename LT>
-__device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT> &L,
+template <int NP, typename LT, int G>
+__device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const WaveTables &wt, WaveLds<NP, LT, G> &L,
                                    const SpeciesLane &sp, int K, double p, double yi, double gamma,
                                    double *qbuf)
 {
-    const int lane = lane_id();
+    using Gp = Grp<G>;
+    const int lane = Gp::lane();
     const int N = K + 1;
-    const double T = lane_value(yi, K);
+    const double T = Gp::at(yi, K);
     const double invT = 1.0 / T;
     const double lnT = log(T);
     double cpk = 0.0, hk = 0.0, gk = 0.0, dcpk = 0.0;
     if (lane < K) lane_thermo(sp, m.two_range, T, invT, lnT, cpk, hk, gk, dcpk);
-    const double sumYW = wave_sum(lane < K ? yi * sp.invW : 0.0);
+    const double sumYW = Gp::sum(lane < K ? yi * sp.invW : 0.0);
     const double wbar = 1.0 / sumYW;
     const double rho = p * wbar / (kRu * T);
-    const double cpm = kRu * wave_sum(lane < K ? yi * cpk * sp.invW : 0.0);
-    const double dcpm = kRu * wave_sum(lane < K ? yi * dcpk * sp.invW : 0.0);
+    const double cpm = kRu * Gp::sum(lane < K ? yi * cpk * sp.invW : 0.0);
+    const double dcpm = kRu * Gp::sum(lane < K ? yi * dcpk * sp.invW : 0.0);
     if (lane < K) {
         L.C[lane] = rho * yi * sp.invW;
         L.g[lane] = gk;
@@ -196,11 +287,11 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
     if (lane < N)
 #pragma unroll
         for (int c = 0; c < NP + 2; c++) L.row[lane][c] = (LT)0;
-    __syncthreads();
+    Gp::sync();
     const int R = m.R;
     double *qh = qbuf + R, *dqT = qbuf + 2 * R, *dq = qbuf + 3 * R;
     const double ln_c0 = log(kPstd / kRu) - lnT;
-    for (int r = lane; r < R; r += kWaveLanes) {
+    for (int r = lane; r < R; r += G) {
         const DevRxn x = m.rxn[r];
         const double lnkf = x.lnA + x.b * lnT - x.Ea_R * invT;
         const double dg = L.g[x.p0] + L.g[x.p1] - L.g[x.r0] - L.g[x.r1];
@@ -220,7 +311,7 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
         dq[4 * r + 2] = -kr * cp1;
         dq[4 * r + 3] = -kr * cp0;
     }
-    __syncthreads();
+    Gp::sync();
     // species rows: owner lane k walks the reactions it takes part in
     double wk = 0.0, wTk = 0.0, ACk = 0.0;
     if (lane < K) {
@@ -246,10 +337,10 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
     const double RT = kRu * T;
     const double rcp = rho * cpm;
     const double inv_rcp = 1.0 / rcp;
-    const double S = RT * wave_sum(lane < K ? hk * wk : 0.0);
-    const double hAC = wave_sum(lane < K ? hk * ACk : 0.0);
-    const double dST = wave_sum(lane < K ? kRu * cpk * wk + RT * hk * (wTk - ACk * invT) : 0.0);
-    __syncthreads();
+    const double S = RT * Gp::sum(lane < K ? hk * wk : 0.0);
+    const double hAC = Gp::sum(lane < K ? hk * ACk : 0.0);
+    const double dST = Gp::sum(lane < K ? kRu * cpk * wk + RT * hk * (wTk - ACk * invT) : 0.0);
+    Gp::sync();
     // temperature row: lane j sums column j over the species rows
     double JT = 0.0;
     if (lane < K) {
@@ -263,7 +354,7 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
         const double drcpT = rho * dcpm - cpm * rho * invT;
         JT = (-dST + S * drcpT * inv_rcp) * inv_rcp;
     }
-    __syncthreads();
+    Gp::sync();
     const double gq = wbar / rho;
     if (lane < K) {
         const double u = sp.W * gq * (wk - ACk);
@@ -272,33 +363,34 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
         L.row[lane][K] = (LT)(sp.W / rho * (wTk + (wk - ACk) * invT));
     }
     if (lane < N) L.row[K][lane] = (LT)JT;
-    __syncthreads();
+    Gp::sync();
     if (lane < N)
         for (int c = 0; c < N; c++)
             L.row[lane][c] = (LT)((c == lane ? 1.0 : 0.0) - gamma * (double)L.row[lane][c]);
-    __syncthreads();
+    Gp::sync();
 }
 
 // LU with row partial pivoting of the Newton matrix in LDS, in place: at
 // step k the pivot is the largest magnitude in column k at or below the
 // diagonal (ties to the lowest row), rows k and p are exchanged, and lane r
 // eliminates its row r > k against the pivot row (read by every lane from
-// the same LDS address).  perm[k] records p.
-template <int NP, typename LT>
-__device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N, int &pi, LT &dinv)
+// the same LDS address).
+template <int NP, typename LT, int G>
+__device__ __forceinline__ bool wave_lu(WaveLds<NP, LT, G> &L, int N, int &pi, LT &dinv)
 {
-    const int lane = lane_id();
+    using Gp = Grp<G>;
+    const int lane = Gp::lane();
     bool ok = true;
     pi = lane;   // lane k ends with the original row that lands at position k
     for (int k = 0; k < N; k++) {
         const bool cand = lane >= k && lane < N;
-        int p = wave_argmax(cand ? (double)L.row[lane][k] : 0.0, cand);
+        int p = group_argmax<G>(cand ? (double)L.row[lane][k] : 0.0, cand);
         if (p < 0) {   // no comparable value (NaN column): keep the row, fail below
             p = k;
             ok = false;
         }
         if (p != k) {
-            const int a = __builtin_amdgcn_readlane(pi, k), b = __builtin_amdgcn_readlane(pi, p);
+            const int a = Gp::at(pi, k), b = Gp::at(pi, p);
             if (lane == k) pi = b;
             if (lane == p) pi = a;
             if (lane < N) {
@@ -307,7 +399,7 @@ __device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N, int &pi, LT &
                 L.row[p][lane] = ra;
             }
         }
-        __syncthreads();
+        Gp::sync();
         const LT piv = L.row[k][k];
         ok = ok && (piv != (LT)0);
         if (lane > k && lane < N) {
@@ -315,7 +407,7 @@ __device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N, int &pi, LT &
             L.row[lane][k] = l;
             L.lcol[lane] = l;
         }
-        __syncthreads();
+        Gp::sync();
         // lane c updates column c below the pivot row: one multiplier read
         // (same address for every lane) and one element of its own column
         // per row, independent from row to row
@@ -324,7 +416,7 @@ __device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N, int &pi, LT &
 #pragma unroll 4
             for (int r = k + 1; r < N; r++) L.row[r][lane] -= L.lcol[r] * ukc;
         }
-        __syncthreads();
+        Gp::sync();
     }
     dinv = lane < N ? (LT)1 / L.row[lane][lane] : (LT)0;
     return ok;
@@ -334,16 +426,19 @@ __device__ __forceinline__ bool wave_lu(WaveLds<NP, LT> &L, int N, int &pi, LT &
 // x_i: the row exchanges applied at once (each lane reads the component of
 // its original row), then forward (unit lower) and backward substitution,
 // each step broadcasting one component; the diagonal enters through its
-// reciprocal.
-template <int NP, typename LT>
-__device__ __forceinline__ double wave_solve(const WaveLds<NP, LT> &L, int N, int pi, LT dinv, double bi)
+// reciprocal.  The lane's matrix elements are read eight at a time ahead of
+// the broadcast chain, which then runs on registers; with 16-lane groups the
+// loops unroll completely and every broadcast is one DPP row broadcast.
+template <int NP, typename LT, int G>
+__device__ __forceinline__ double wave_solve(const WaveLds<NP, LT, G> &L, int N, int pi, LT dinv, double bi)
 {
-    const int lane = lane_id();
-    LT x = (LT)__shfl(bi, pi);
-    // the lane's matrix elements are read eight at a time ahead of the
-    // broadcast chain, which then runs on registers
+    using Gp = Grp<G>;
+    const int lane = Gp::lane();
+    LT x = (LT)Gp::gather(bi, pi);
     constexpr int B = 8;
-    for (int k0 = 0; k0 < N; k0 += B) {
+#pragma unroll(G == 16 ? NP / B : 1)
+    for (int k0 = 0; k0 < NP; k0 += B) {
+        if (k0 >= N) break;
         LT a[B];
 #pragma unroll
         for (int j = 0; j < B; j++) {
@@ -353,35 +448,41 @@ __device__ __forceinline__ double wave_solve(const WaveLds<NP, LT> &L, int N, in
 #pragma unroll
         for (int j = 0; j < B; j++) {
             const int k = k0 + j;
-            if (k < N) x -= a[j] * lane_value(x, k);
+            if (k < N) x -= a[j] * Gp::at_k(x, k);
         }
     }
-    for (int k1 = N - 1; k1 >= 0; k1 -= B) {
+#pragma unroll(G == 16 ? NP / B : 1)
+    for (int k1 = (G == 16 ? NP - 1 : N - 1); k1 >= 0; k1 -= B) {
         LT a[B];
 #pragma unroll
         for (int j = 0; j < B; j++) {
             const int k = k1 - j;
-            a[j] = (k >= 0 && lane < k) ? L.row[lane][k] : (LT)0;
+            a[j] = (k >= 0 && k < N && lane < k) ? L.row[lane][k] : (LT)0;
         }
 #pragma unroll
         for (int j = 0; j < B; j++) {
             const int k = k1 - j;
-            if (k >= 0) {
+            if (k >= 0 && k < N) {
                 if (lane == k) x = x * dinv;
-                x -= a[j] * lane_value(x, k);
+                x -= a[j] * Gp::at_k(x, k);
             }
         }
     }
     return lane < N ? (double)x : 0.0;
 }
 
-template <int NP, typename LT>
-__device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellIO &io,
-                         double t_end, unsigned long long *queue, double *qbuf,
-                         WaveLds<NP, LT> &L)
+// One group of G lanes integrates one cell at a time and takes the next from
+// the work queue as soon as its cell is done, whatever the other groups of
+// the wave are doing: each pass of the loop is one step of the group's cell
+// (preceded by taking and starting a new cell when the group has none).
+template <int NP, typename LT, int G>
+__device__ void run_cells(const DevMechView &m, const WaveTables &wt, const CellIO &io,
+                          double t_end, unsigned long long *queue, double *qbuf,
+                          WaveLds<NP, LT, G> &L)
 {
     using namespace bdf;
-    const int lane = lane_id();
+    using Gp = Grp<G>;
+    const int lane = Gp::lane();
     const int K = m.K, N = K + 1;
     const double rtol = io.prm->rtol, atol = io.prm->atol;
     SpeciesLane sp;
@@ -392,75 +493,93 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
         sp.invW = m.invW[k];
     }
     if (lane <= K) L.invW[lane] = lane < K ? sp.invW : 0.0;
-    __syncthreads();
+    Gp::sync();
+    const bool active = lane < N;
     int lu_pi = lane;       // factorisation's row permutation (this lane's entry)
     LT lu_dinv = (LT)0;     // reciprocal of this lane's diagonal element of U
+    // the group's cell and its integration state
+    bool busy = false;
+    int64_t cell = 0;
+    double p = 0.0, w = 0.0, h = 0.0, t = 0.0;
+    double z[kQmax + 1], tau[kQmax + 2];
+    int nst = 0, nfe = 0, nje = 0, nni = 0, netf = 0, ncfn = 0, status = 0;
+    int q = 1, qwait = 2, nst_M = 0;
+    bool have_M = false, ehat_ok = false;
+    double gamma_M = 0.0, crate = 1.0, ehat_h = 0.0, ehat = 0.0;
+    auto wnorm = [&](double v) { const double u = active ? v * w : 0.0; return sqrt(Gp::sum(u * u) * (1.0 / N)); };
+    auto all_finite = [&](double v) { return Gp::ballot(active && !isfinite(v)) == 0ull; };
     for (;;) {
-        unsigned long long c = 0;
-        if (lane == 0) c = atomicAdd(queue, 1ull);
-        c = __shfl(c, 0);
-        if (c >= (unsigned long long)io.nq) break;
-        const int64_t cell = io.idx ? (int64_t)io.idx[c] : (int64_t)c;
-        if (cell < 0 || cell >= io.n) continue;   // an index outside the arrays is skipped
-        const double p = io.p[cell];
-        double y0 = 0.0;
-        if (lane < K) y0 = io.Y[lane * io.ldY + cell];
-        else if (lane == K) y0 = io.T[cell];
-        int nst = 0, nfe = 0, nje = 0, nni = 0, netf = 0, ncfn = 0;
-        int status = 0;
-        bool active = lane < N;
-        // ---------------- initial derivative and step ----------------
-        double f0 = wave_rhs<NP, LT>(m, wt, L, sp, K, p, y0, qbuf);
-        nfe++;
-        double z[kQmax + 1];
+        if (!busy) {
+            unsigned long long c = 0;
+            if (lane == 0) c = atomicAdd(queue, 1ull);
+            c = Gp::first(c);
+            if (c >= (unsigned long long)io.nq) break;
+            const int64_t cc = io.idx ? (int64_t)io.idx[c] : (int64_t)c;
+            if (cc < 0 || cc >= io.n) continue;   // an index outside the arrays is skipped
+            cell = cc;
+            busy = true;
+            p = io.p[cell];
+            double y0 = 0.0;
+            if (lane < K) y0 = io.Y[lane * io.ldY + cell];
+            else if (lane == K) y0 = io.T[cell];
+            nst = nfe = nje = nni = netf = ncfn = 0;
+            status = 0;
+            // ---------------- initial derivative and step ----------------
+            const double f0 = wave_rhs<NP, LT, G>(m, wt, L, sp, K, p, y0, qbuf);
+            nfe++;
 #pragma unroll
-        for (int j = 0; j <= kQmax; j++) z[j] = 0.0;
-        z[0] = y0;
-        double w = active ? 1.0 / (rtol * fabs(y0) + atol) : 0.0;
-        auto wnorm = [&](double v) { const double t = active ? v * w : 0.0; return sqrt(wave_sum(t * t) * (1.0 / N)); };
-        auto all_finite = [&](double v) { return __ballot(active && !isfinite(v)) == 0ull; };
-        if (!all_finite(f0)) {
-            status = 4;
-        }
-        double h = t_end;
-        if (status == 0 && wnorm(f0) != 0.0) {
-            double hub = t_end;
-            {
-                // hub = min over components of (0.1|y0| + 1/w)/|f0| where it binds
-                double lim = active ? 0.1 * fabs(y0) + 1.0 / w : 0.0;
-                // sequential in component order, like the definition
-                for (int i = 0; i < N; i++) {
-                    const double fi = lane_value(f0, i), li = lane_value(lim, i);
-                    if (fabs(fi) * hub > li) hub = li / fabs(fi);
-                }
+            for (int j = 0; j <= kQmax; j++) z[j] = 0.0;
+            z[0] = y0;
+            w = active ? 1.0 / (rtol * fabs(y0) + atol) : 0.0;
+            if (!all_finite(f0)) {
+                status = 4;
             }
-            double hg = hub;
-            for (int it = 0; it < kH0Iters; it++) {
-                const double f1 = wave_rhs<NP, LT>(m, wt, L, sp, K, p, y0 + hg * f0, qbuf);
-                nfe++;
-                if (!all_finite(f1)) {
-                    hg *= 0.1;
-                    continue;
+            h = t_end;
+            if (status == 0 && wnorm(f0) != 0.0) {
+                double hub = t_end;
+                {
+                    // hub = min over components of (0.1|y0| + 1/w)/|f0| where it binds
+                    double lim = active ? 0.1 * fabs(y0) + 1.0 / w : 0.0;
+                    // sequential in component order, like the definition
+                    for (int i = 0; i < N; i++) {
+                        const double fi = Gp::at(f0, i), li = Gp::at(lim, i);
+                        if (fabs(fi) * hub > li) hub = li / fabs(fi);
+                    }
                 }
-                const double ydd = wnorm((f1 - f0) / hg);
-                double hnew = ydd > 0.0 ? sqrt(2.0 / ydd) : hub;
-                if (hnew > hub) hnew = hub;
-                const double ratio = hnew / hg;
-                hg = hnew;
-                if (ratio >= 0.5 && ratio <= 2.0) break;
+                double hg = hub;
+                for (int it = 0; it < kH0Iters; it++) {
+                    const double f1 = wave_rhs<NP, LT, G>(m, wt, L, sp, K, p, y0 + hg * f0, qbuf);
+                    nfe++;
+                    if (!all_finite(f1)) {
+                        hg *= 0.1;
+                        continue;
+                    }
+                    const double ydd = wnorm((f1 - f0) / hg);
+                    double hnew = ydd > 0.0 ? sqrt(2.0 / ydd) : hub;
+                    if (hnew > hub) hnew = hub;
+                    const double ratio = hnew / hg;
+                    hg = hnew;
+                    if (ratio >= 0.5 && ratio <= 2.0) break;
+                }
+                h = 0.5 * hg;
+                if (h > t_end) h = t_end;
             }
-            h = 0.5 * hg;
-            if (h > t_end) h = t_end;
-        }
-        z[1] = h * f0;
-        int q = 1, qwait = 2, nst_M = 0;
-        bool have_M = false, ehat_ok = false;
-        double gamma_M = 0.0, crate = 1.0, ehat_h = 0.0, ehat = 0.0, t = 0.0;
-        double tau[kQmax + 2];
+            z[1] = h * f0;
+            q = 1;
+            qwait = 2;
+            nst_M = 0;
+            have_M = false;
+            ehat_ok = false;
+            gamma_M = 0.0;
+            crate = 1.0;
+            ehat_h = 0.0;
+            ehat = 0.0;
+            t = 0.0;
 #pragma unroll
-        for (int j = 0; j < kQmax + 2; j++) tau[j] = 0.0;
-        // ---------------- step loop ----------------
-        while (status == 0 && t < t_end) {
+            for (int j = 0; j < kQmax + 2; j++) tau[j] = 0.0;
+        }
+        do {   // one step of the cell; break ends the step early
+            if (status != 0 || t >= t_end) break;
             if (nst >= io.prm->max_steps) {
                 status = 1;
                 break;
@@ -519,9 +638,9 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                 const double Cq = 1.0 / (1.0 + l[1] * xq1);
                 bool jcur = false, conv = false, lu_ok = true;
                 if (!have_M || force_M || nst >= nst_M + kMsbp || fabs(gamma / gamma_M - 1.0) > kDgmax) {
-                    wave_newton_matrix<NP, LT>(m, wt, L, sp, K, p, z[0], gamma, qbuf);
+                    wave_newton_matrix<NP, LT, G>(m, wt, L, sp, K, p, z[0], gamma, qbuf);
                     nje++;
-                    lu_ok = wave_lu<NP, LT>(L, N, lu_pi, lu_dinv);
+                    lu_ok = wave_lu<NP, LT, G>(L, N, lu_pi, lu_dinv);
                     gamma_M = gamma;
                     nst_M = nst;
                     crate = 1.0;
@@ -534,11 +653,11 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                     e = 0.0;
                     const double inv_l1 = 1.0 / l[1];
                     for (int it = 0; it < kMaxCor; it++) {
-                        const double fy = wave_rhs<NP, LT>(m, wt, L, sp, K, p, z[0] + e, qbuf);
+                        const double fy = wave_rhs<NP, LT, G>(m, wt, L, sp, K, p, z[0] + e, qbuf);
                         nfe++;
                         if (!all_finite(fy)) break;
                         double d = active ? -(e - gamma * fy + z[1] * inv_l1) : 0.0;
-                        d = wave_solve<NP, LT>(L, N, lu_pi, lu_dinv, d);
+                        d = wave_solve<NP, LT, G>(L, N, lu_pi, lu_dinv, d);
                         if (!active) d = 0.0;
                         if (gamma != gamma_M) d *= 2.0 / (1.0 + gamma / gamma_M);
                         const double dl = wnorm(d);
@@ -595,7 +714,7 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                     if (nef >= kNefRestart) {
                         h *= kEtaMinEf;
                         q = 1;
-                        const double fr = wave_rhs<NP, LT>(m, wt, L, sp, K, p, z[0], qbuf);
+                        const double fr = wave_rhs<NP, LT, G>(m, wt, L, sp, K, p, z[0], qbuf);
                         nfe++;
                         if (!all_finite(fr)) {
                             status = 4;
@@ -747,7 +866,9 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                 }
                 h *= eta;
             }
-        }
+        } while (false);
+        if (status == 0 && t < t_end) continue;
+        // ---------------- the cell is done ----------------
         if (status == 0 && !all_finite(z[0])) status = 4;
         if (status == 0) {
             if (lane < K) io.Y[lane * io.ldY + cell] = z[0];
@@ -764,71 +885,106 @@ __device__ void run_wave(const DevMechView &m, const WaveTables &wt, const CellI
                 io.counters[5 * io.n + cell] = ncfn;
             }
         }
+        busy = false;
     }
 }
 
+// Reaction scratch of the right-hand side and the Jacobian (7 R doubles per
+// cell in flight): LDS (dynamic shared memory) when it fits, else a global
+// slice per group.
+template <int NP, typename LT, int G>
+__device__ __forceinline__ void run_block(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
+                                          double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
+                                          int32_t *status, int32_t *counters, unsigned long long *queue,
+                                          double *qscratch, WaveLds<NP, LT, G> *Ls)
+{
+    const CellIO io = make_cell_io(T, p, Y, ldY, n, status, counters, prm);
+    extern __shared__ double qlds[];
+    const int slot = Grp<G>::slot();
+    const size_t q7 = (size_t)7 * (m.R > 0 ? m.R : 1);
+    double *qbuf = qscratch ? qscratch + ((size_t)blockIdx.x * Grp<G>::kCells + slot) * q7 : qlds + slot * q7;
+    run_cells<NP, LT, G>(m, wt, io, dt, queue, qbuf, Ls[slot]);
+}
+
+// One 64-lane wave per cell.
 template <int NP, typename LT>
-__global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables wt,
-                                                      double *__restrict__ T,
-                                                      const double *__restrict__ p,
-                                                      double *__restrict__ Y, int64_t ldY,
-                                                      int64_t n, double dt, BdfParams prm,
-                                                      int32_t *__restrict__ status,
-                                                      int32_t *__restrict__ counters,
+__global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables wt, double *__restrict__ T,
+                                                      const double *__restrict__ p, double *__restrict__ Y,
+                                                      int64_t ldY, int64_t n, double dt, BdfParams prm,
+                                                      int32_t *__restrict__ status, int32_t *__restrict__ counters,
                                                       unsigned long long *__restrict__ queue,
                                                       double *__restrict__ qscratch)
 {
-    __shared__ WaveLds<NP, LT> L;
-    const CellIO io = make_cell_io(T, p, Y, ldY, n, status, counters, prm);
-    // reaction scratch of the right-hand side and the Jacobian (7 R doubles):
-    // LDS (dynamic shared memory) when it fits, else a global slice per wave
-    extern __shared__ double qlds[];
-    double *qbuf = qscratch ? qscratch + (size_t)blockIdx.x * 7 * m.R : qlds;
-    run_wave<NP, LT>(m, wt, io, dt, queue, qbuf, L);
+    __shared__ WaveLds<NP, LT, 64> Ls[1];
+    run_block<NP, LT, 64>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, Ls);
+}
+
+// Tile schedule: 16 lanes per cell, four cells per wave (N <= 16).
+template <typename LT>
+__global__ void __launch_bounds__(64) bdf_tile_kernel(DevMechView m, WaveTables wt, double *__restrict__ T,
+                                                      const double *__restrict__ p, double *__restrict__ Y,
+                                                      int64_t ldY, int64_t n, double dt, BdfParams prm,
+                                                      int32_t *__restrict__ status, int32_t *__restrict__ counters,
+                                                      unsigned long long *__restrict__ queue,
+                                                      double *__restrict__ qscratch)
+{
+    __shared__ WaveLds<16, LT, 16> Ls[4];
+    run_block<16, LT, 16>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, Ls);
 }
 
 }  // namespace
 
 int wave_kernel_rows(int N) { return N <= 16 ? 16 : (N <= 40 ? 40 : (N <= 64 ? 64 : 0)); }
 
-template <int NP, typename LT>
-static hipError_t launch_np(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
-                            double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
-                            int32_t *status, int32_t *counters, unsigned long long *queue,
-                            double *qscratch, int max_waves, hipStream_t s)
+template <typename Kern>
+static hipError_t launch_groups(Kern kern, int cells_per_wave, const DevMechView &m, const WaveTables &wt, double *T,
+                                const double *p, double *Y, int64_t ldY, int64_t n, double dt,
+                                const BdfParams &prm, int32_t *status, int32_t *counters,
+                                unsigned long long *queue, double *qscratch, int max_groups, hipStream_t s)
 {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, queue);
-    const size_t qbytes = (size_t)7 * (m.R > 0 ? m.R : 1) * sizeof(double);
+    const size_t qbytes = (size_t)cells_per_wave * 7 * (m.R > 0 ? m.R : 1) * sizeof(double);
     const bool in_lds = qbytes <= 32768;
     int blocks = 0;
     {
         int dev = 0, cus = 0, per_cu = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)bdf_wave_kernel<NP, LT>, 64,
-                                                          in_lds ? qbytes : 0) != hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 64, in_lds ? qbytes : 0) !=
+                hipSuccess ||
+            per_cu < 1)
             per_cu = 1;
         blocks = cus * per_cu;
     }
-    if (blocks > max_waves) blocks = max_waves;
-    if (blocks > n) blocks = (int)n;
-    hipLaunchKernelGGL((bdf_wave_kernel<NP, LT>), dim3(blocks), dim3(64), in_lds ? qbytes : 0, s, m, wt, T,
-                       p, Y, ldY, n, dt, prm, status, counters, queue, in_lds ? nullptr : qscratch);
+    // a global scratch slice per group when the LDS cannot hold it
+    if (!in_lds && blocks > max_groups / cells_per_wave) blocks = max_groups / cells_per_wave;
+    const int64_t need = (n + cells_per_wave - 1) / cells_per_wave;
+    if (blocks > need) blocks = (int)need;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), in_lds ? qbytes : 0, s, m, wt, T, p, Y, ldY, n, dt, prm, status,
+                       counters, queue, in_lds ? nullptr : qscratch);
     return hipGetLastError();
 }
 
 hipError_t launch_bdf_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
                            double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
                            int32_t *status, int32_t *counters, unsigned long long *queue,
-                           double *qscratch, int max_waves, bool fp32_lu, hipStream_t s)
+                           double *qscratch, int max_groups, bool fp32_lu, int lanes, hipStream_t s)
 {
+    if (lanes == 16) {
+        if (m.K + 1 > 16) return hipErrorInvalidValue;
+        return fp32_lu ? launch_groups(bdf_tile_kernel<float>, 4, m, wt, T, p, Y, ldY, n, dt, prm, status, counters,
+                                       queue, qscratch, max_groups, s)
+                       : launch_groups(bdf_tile_kernel<double>, 4, m, wt, T, p, Y, ldY, n, dt, prm, status, counters,
+                                       queue, qscratch, max_groups, s);
+    }
     const int NP = wave_kernel_rows(m.K + 1);
-#define CHEM_WAVE_CASE(NPV)                                                                          \
-    if (NP == NPV)                                                                                   \
-        return fp32_lu ? launch_np<NPV, float>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters,   \
-                                              queue, qscratch, max_waves, s)                       \
-                       : launch_np<NPV, double>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters,  \
-                                               queue, qscratch, max_waves, s);
+#define CHEM_WAVE_CASE(NPV)                                                                                      \
+    if (NP == NPV)                                                                                               \
+        return fp32_lu ? launch_groups(bdf_wave_kernel<NPV, float>, 1, m, wt, T, p, Y, ldY, n, dt, prm, status,   \
+                                       counters, queue, qscratch, max_groups, s)                                 \
+                       : launch_groups(bdf_wave_kernel<NPV, double>, 1, m, wt, T, p, Y, ldY, n, dt, prm, status,  \
+                                       counters, queue, qscratch, max_groups, s);
     CHEM_WAVE_CASE(16)
     CHEM_WAVE_CASE(40)
     CHEM_WAVE_CASE(64)

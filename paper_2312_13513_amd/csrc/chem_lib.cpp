@@ -204,7 +204,7 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
         return fail(CHEM_EINVAL, "rtol and atol must be finite and > 0");
     if (o.max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
     if (o.precision != 0 && o.precision != 1) return fail(CHEM_EINVAL, "precision must be 0 or 1");
-    if (o.schedule < -2 || o.schedule > 1) return fail(CHEM_EINVAL, "unknown schedule");
+    if (o.schedule < -2 || o.schedule > 2) return fail(CHEM_EINVAL, "unknown schedule");
     if (o.schedule == -2) {
         const auto &tu = m->tuned[o.precision == 1 ? 1 : 0];
         o.schedule = tu.valid ? tu.schedule : -1;
@@ -226,15 +226,17 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
         return fail(CHEM_EUNSUP, "the one-thread-per-cell schedule computes in FP64 only");
     if (sched == 1 && !wave_ok)
         return fail(CHEM_EUNSUP, "the wave schedule supports at most 63 species");
+    if (sched == 2 && K + 1 > 16)
+        return fail(CHEM_EUNSUP, "the tile schedule supports at most 15 species");
     if (o.jac_batch < 0 || o.jac_batch > 64) return fail(CHEM_EINVAL, "jac_batch must be in 0..64");
     chem::BdfParams prm{o.rtol, o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16, n_dev, idx, n_idx};
     // each call takes its own queue counter (64 rotate), so that calls in
     // flight on different streams do not share one
     unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);
     hipError_t e;
-    if (sched == 1)
+    if (sched == 1 || sched == 2)
         e = chem::launch_bdf_wave(m->view, m->wave, T, p, Y, ldY, n, dt, prm, status, counters, queue,
-                                  m->wave_scratch, m->wave_slots, o.precision == 1, stream);
+                                  m->wave_scratch, m->wave_slots, o.precision == 1, sched == 2 ? 16 : 64, stream);
     else if (m->gen)
         e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, stream);
     else
@@ -353,7 +355,7 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     const size_t off_io = off_q + kQueues * 256;
     const size_t off_inc = (off_io + (K + 1) * sizeof(int) + 255) & ~size_t(255);
     const size_t off_ws = (off_inc + inc_flat.size() * sizeof(int) + 255) & ~size_t(255);
-    const int wave_slots = 4096;   // concurrent waves of the wave kernel
+    const int wave_slots = 4096;   // cells in flight of the wave / tile kernels (global reaction scratch)
     const size_t total = off_ws + (size_t)wave_slots * 7 * (R > 0 ? R : 1) * sizeof(double);
     int prev = 0;
     if ((rc = check_hip(hipGetDevice(&prev), "hipGetDevice")) != CHEM_OK) {

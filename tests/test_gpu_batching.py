@@ -37,7 +37,7 @@ def field(mech_dir):
     return cells4096(read_mechanism(str(mech_dir / "M9.mech")), n=3000, seed=12)
 
 
-@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_indexed_subset_is_bitwise_plain(torch, m9, field, schedule):
     from paper_2312_13513_amd import chem
     f = field
@@ -97,7 +97,7 @@ def test_autotune_choice_meets_parity(torch, m9, field, om9):
     T, Y, p = _dev(torch, f.T), _dev(torch, f.Y), _dev(torch, f.p)
     best, lpt, ms = m9.autotune(T, p, Y, f.dt, max_sample=2048)
     _say(f"[autotune] schedule {best.schedule} jac_batch {best.jac_batch} lpt {lpt} {ms:.3f} ms on 2048 cells")
-    assert best.schedule in (0, 1) and ms > 0
+    assert best.schedule in (0, 1, 2) and ms > 0
     # the states passed in are not modified
     assert np.array_equal(T.cpu().numpy(), f.T) and np.array_equal(Y.cpu().numpy(), f.Y)
     o = chem.chem_default_opts()

@@ -1,0 +1,141 @@
+"""GPU parity of the tile schedule (16 lanes per cell, four cells per wave,
+mechanisms with N = K + 1 <= 16): against the CPU oracle on the 9-species
+mechanism, and against the wave schedule, which takes the same decisions with
+the same operations per cell (the compiler may fuse multiply-adds differently
+in the two kernels, so agreement is at round-off, not bitwise).  Ragged cell
+counts (not a multiple of four) and index lists with entries outside the
+arrays must reproduce the full tile run bit for bit; failure statuses and the
+FP32 Jacobian/LU mode are covered."""
+import numpy as np
+import pytest
+
+from test_gpu_integrate import compare, run_gpu, _say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def g9(mech_dir, torch):
+    from paper_2312_13513_amd import chem
+    m = chem.Mechanism(str(mech_dir / "M9.mech"), 0)
+    yield m
+    m.close()
+
+
+@pytest.fixture(scope="module")
+def field(mech_dir):
+    from chemgen.fields import cells4096
+    from chemgen.mechanism import read_mechanism
+    return cells4096(read_mechanism(str(mech_dir / "M9.mech")), n=3001, seed=21)
+
+
+def _opts(schedule, precision=0, max_steps=None):
+    from paper_2312_13513_amd import chem
+    o = chem.chem_default_opts()
+    o.schedule = schedule
+    o.precision = precision
+    if max_steps is not None:
+        o.max_steps = max_steps
+    return o
+
+
+@pytest.fixture(scope="module")
+def tile_and_wave(torch, g9, field):
+    f = field
+    tile = run_gpu(torch, g9, f.T, f.p, f.Y, f.dt, opts=_opts(2))
+    wave = run_gpu(torch, g9, f.T, f.p, f.Y, f.dt, opts=_opts(1))
+    return tile, wave
+
+
+def _bitwise(a, b):
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_tile_matches_oracle(tile_and_wave, field, om9):
+    f = field
+    Tg, Yg, sg, cg = tile_and_wave[0]
+    To, Yo, so, co, _ = om9.integrate(f.T, f.p, f.Y, f.dt)
+    flips = compare("tile-M9", Tg, Yg, sg, cg, To, Yo, so, co)
+    assert flips.size <= 3
+
+
+def test_tile_agrees_with_wave(tile_and_wave):
+    tile, wave = tile_and_wave
+    compare("tile-vs-wave", *tile, *wave)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 67])
+def test_tile_ragged_sizes(torch, g9, field, tile_and_wave, n):
+    f = field
+    out = run_gpu(torch, g9, f.T[:n], f.p[:n], f.Y[:, :n], f.dt, opts=_opts(2))
+    full = tile_and_wave[0]
+    _bitwise(out, (full[0][:n], full[1][:, :n], full[2][:n], full[3][:n]))
+
+
+def test_tile_index_list(torch, g9, field, tile_and_wave):
+    f = field
+    dev = "cuda:0"
+    rng = np.random.default_rng(3)
+    sub = rng.choice(f.n, size=501, replace=False).astype(np.int32)
+    idx = np.concatenate([sub[:200], [-1, f.n, 1 << 30], sub[200:]]).astype(np.int32)
+    T = torch.tensor(f.T, dtype=torch.float64, device=dev)
+    Y = torch.tensor(f.Y, dtype=torch.float64, device=dev)
+    st = torch.full((f.n,), -5, dtype=torch.int32, device=dev)
+    g9.integrate_indexed(T, torch.tensor(f.p, dtype=torch.float64, device=dev), Y,
+                         torch.tensor(idx, dtype=torch.int32, device=dev), f.dt, opts=_opts(2), status=st)
+    torch.cuda.synchronize()
+    T, Y, st = T.cpu().numpy(), Y.cpu().numpy(), st.cpu().numpy()
+    full = tile_and_wave[0]
+    assert np.array_equal(T[sub], full[0][sub]) and np.array_equal(Y[:, sub], full[1][:, sub])
+    rest = np.setdiff1d(np.arange(f.n), sub)
+    assert np.array_equal(T[rest], f.T[rest]) and np.all(st[rest] == -5) and np.all(st[sub] == 0)
+
+
+def test_tile_failure_statuses(torch, g9, field, tile_and_wave):
+    f = field
+    sel = np.arange(0, 130)
+    T = f.T[sel].copy()
+    T[7] = float("nan")
+    for opts in (_opts(2, max_steps=1), _opts(2)):
+        tile = run_gpu(torch, g9, T, f.p[sel], f.Y[:, sel], f.dt, opts=opts)
+        opts.schedule = 1
+        wave = run_gpu(torch, g9, T, f.p[sel], f.Y[:, sel], f.dt, opts=opts)
+        assert np.array_equal(tile[2], wave[2])
+        assert tile[2][7] == 4 and np.isnan(tile[0][7])
+    many = tile_and_wave[0][3][sel, 0] > 1
+    capped = run_gpu(torch, g9, T, f.p[sel], f.Y[:, sel], f.dt, opts=_opts(2, max_steps=1))
+    assert np.all(capped[2][many & (sel != 7)] == 1)
+
+
+def test_tile_fp32_lu_error(torch, g9, field, om9):
+    """FP32 Jacobian and LU, FP64 residual and state: the same error scale as
+    the wave schedule's mixed mode against the FP64 oracle."""
+    f = field
+    n = 1024
+    tile = run_gpu(torch, g9, f.T[:n], f.p[:n], f.Y[:, :n], f.dt, opts=_opts(2, precision=1))
+    wave = run_gpu(torch, g9, f.T[:n], f.p[:n], f.Y[:, :n], f.dt, opts=_opts(1, precision=1))
+    To, Yo = om9.integrate(f.T[:n], f.p[:n], f.Y[:, :n], f.dt)[:2]
+    assert np.all(tile[2] == 0) and np.all(wave[2] == 0)
+    dT, dY = np.abs(tile[0] - To).max(), np.abs(tile[1] - Yo).max()
+    dTw = np.abs(wave[0] - To).max()
+    _say(f"[tile] FP32 J/LU: max|dT| vs FP64 oracle {dT:.3e} K (wave schedule {dTw:.3e} K), max|dY| {dY:.3e}")
+    assert dT < 1e-3 and dY < 1e-6
+
+
+def test_tile_rejects_large_mechanism(torch, mech_dir):
+    from paper_2312_13513_amd import chem
+    g = chem.Mechanism(str(mech_dir / "M35.mech"), 0)
+    T = torch.full((4,), 1500.0, dtype=torch.float64, device="cuda:0")
+    Y = torch.full((35, 4), 1.0 / 35, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(chem.ChemError, match="tile"):
+        g.integrate(T, T, Y, 1e-6, opts=_opts(2))
+    g.close()
