@@ -2,7 +2,8 @@
 
 Default workload (``--workload flame64``): the plain FP64 GPU integrator on
 the 64^3 flame field (262,144 cells, 9-species / 21-reaction synthetic
-mechanism, dt = 1e-6 s, rtol 1e-8, atol 1e-12).  One step = one call of
+mechanism, dt = 1e-6 s, rtol 1e-8, atol 1e-12), in the library's choice of
+schedule (the 16-lane tile for this mechanism; --schedule picks another).  One step = one call of
 chem_integrate over all cells, starting from the same pristine field
 (restored by a device-to-device copy inside the step, so the copy is timed
 too).  Prints ONE JSON line: the metric, the roofline of the integrator
@@ -99,9 +100,14 @@ def traffic_for(workload: str, kernel: str):
 
 
 def kernel_name(mech, schedule: int, precision: int) -> str:
+    lt = "float" if precision == 1 else "double"
+    if schedule < 0:   # the library's own choice
+        schedule = 2 if mech.N <= 16 else 1
+    if schedule == 2:
+        return f"bdf_tile_kernel<{12 if mech.N <= 12 else 16},{lt},true>"
     if schedule == 1 or precision == 1 or (mech.variant == "table" and mech.K > 9):
         np_rows = 16 if mech.N <= 16 else (40 if mech.N <= 40 else 64)
-        return f"bdf_wave_kernel<{np_rows},{'float' if precision == 1 else 'double'}>"
+        return f"bdf_wave_kernel<{np_rows},{lt},true>"
     if mech.variant.startswith("specialised:"):
         return f"bdf_queue_kernel<GenMech_{mech.variant.split(':')[1]}>"
     return f"bdf_queue_kernel<TableMech<{mech.K}>>"
@@ -158,6 +164,8 @@ def run_integrator(args, workload: str):
     mech = chem.Mechanism(path, 0)
     n, K, R = field.n, mpy.K, mpy.R
     opts = chem.chem_default_opts()
+    if args.schedule is not None:
+        schedule = args.schedule
     opts.precision = precision
     opts.schedule = schedule
     T0 = torch.tensor(field.T, dtype=torch.float64, device=dev)
@@ -211,7 +219,8 @@ def run_integrator(args, workload: str):
         "data": "synthetic",
         "config": {"workload": f"{desc}, dt={field.dt:g} s, rtol 1e-8, atol 1e-12",
                    "ncells": n, "species": K, "reactions": R, "dt": field.dt,
-                   "schedule": "wave per cell" if kname.startswith("bdf_wave") else "thread per cell"},
+                   "schedule": ("tile: 16 lanes per cell, 4 cells per wave" if kname.startswith("bdf_tile") else
+                                "wave per cell" if kname.startswith("bdf_wave") else "thread per cell")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kname,
                      "kernel_ms": avg_kern_s * 1e3, "flops_per_launch": fl["total"],
@@ -412,6 +421,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="flame64", choices=("flame64", "cells4096", "zones128", "surrogate"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", type=int, default=None, choices=(-1, 0, 1, 2),
+                    help="integrator workloads: -1 library choice, 0 thread, 1 wave, 2 tile per cell")
     ap.add_argument("--cpu-sample", type=int, default=0, help="cells for the oracle timing (0 = workload default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="repeat the oracle sample until this long")
     ap.add_argument("--train-samples", type=int, default=2 * 1024 * 1024)

@@ -65,12 +65,13 @@ typedef struct {
     int32_t precision;  /* 0 = FP64 throughout; 1 = Jacobian, Newton matrix, LU
                            factors and triangular solves in FP32, while residuals,
                            state, norms, error control and equilibrium constants
-                           stay FP64 (wave schedule only; results then differ
-                           from FP64 at the level of the integration tolerance) */
+                           stay FP64 (wave and tile schedules; results then
+                           differ from FP64 at the level of the integration
+                           tolerance) */
     int32_t schedule;   /* -2 = the autotuned choice (chem_autotune), else as -1;
-                           -1 = library choice (one thread per cell when such a
-                           kernel exists and precision is 0, else one wave per
-                           cell), 0 = one thread per cell (K <= 9 table kernel or
+                           -1 = library choice (the tile schedule when K <= 15,
+                           else one wave per cell), 0 = one thread per cell
+                           (FP64 only; K <= 9 table kernel or
                            a compiled-in mechanism), 1 = one 64-lane wave per
                            cell (any K <= 63), 2 = tile: 16 lanes per cell, four
                            cells per wave (K <= 15; the same operations per

@@ -436,7 +436,7 @@ __device__ __forceinline__ double wave_solve(const WaveLds<NP, LT, G> &L, int N,
     const int lane = Gp::lane();
     LT x = (LT)Gp::gather(bi, pi);
     constexpr int B = 8;
-#pragma unroll(G == 16 ? NP / B : 1)
+#pragma unroll(G == 16 ? (NP + B - 1) / B : 1)
     for (int k0 = 0; k0 < NP; k0 += B) {
         if (k0 >= N) break;
         LT a[B];
@@ -451,7 +451,7 @@ __device__ __forceinline__ double wave_solve(const WaveLds<NP, LT, G> &L, int N,
             if (k < N) x -= a[j] * Gp::at_k(x, k);
         }
     }
-#pragma unroll(G == 16 ? NP / B : 1)
+#pragma unroll(G == 16 ? (NP + B - 1) / B : 1)
     for (int k1 = (G == 16 ? NP - 1 : N - 1); k1 >= 0; k1 -= B) {
         LT a[B];
 #pragma unroll
@@ -890,24 +890,28 @@ __device__ void run_cells(const DevMechView &m, const WaveTables &wt, const Cell
 }
 
 // Reaction scratch of the right-hand side and the Jacobian (7 R doubles per
-// cell in flight): LDS (dynamic shared memory) when it fits, else a global
-// slice per group.
-template <int NP, typename LT, int G>
+// cell in flight): in LDS after `qlds` (QLDS), else a global slice per group
+// (qscratch).  Fixing the choice at compile time keeps LDS accesses as LDS
+// instructions.
+template <int NP, typename LT, int G, bool QLDS>
 __device__ __forceinline__ void run_block(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
                                           double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
                                           int32_t *status, int32_t *counters, unsigned long long *queue,
-                                          double *qscratch, WaveLds<NP, LT, G> *Ls)
+                                          double *qscratch, double *qlds, WaveLds<NP, LT, G> *Ls)
 {
     const CellIO io = make_cell_io(T, p, Y, ldY, n, status, counters, prm);
-    extern __shared__ double qlds[];
     const int slot = Grp<G>::slot();
     const size_t q7 = (size_t)7 * (m.R > 0 ? m.R : 1);
-    double *qbuf = qscratch ? qscratch + ((size_t)blockIdx.x * Grp<G>::kCells + slot) * q7 : qlds + slot * q7;
+    double *qbuf;
+    if constexpr (QLDS)
+        qbuf = qlds + slot * q7;
+    else
+        qbuf = qscratch + ((size_t)blockIdx.x * Grp<G>::kCells + slot) * q7;
     run_cells<NP, LT, G>(m, wt, io, dt, queue, qbuf, Ls[slot]);
 }
 
 // One 64-lane wave per cell.
-template <int NP, typename LT>
+template <int NP, typename LT, bool QLDS>
 __global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables wt, double *__restrict__ T,
                                                       const double *__restrict__ p, double *__restrict__ Y,
                                                       int64_t ldY, int64_t n, double dt, BdfParams prm,
@@ -916,11 +920,15 @@ __global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables 
                                                       double *__restrict__ qscratch)
 {
     __shared__ WaveLds<NP, LT, 64> Ls[1];
-    run_block<NP, LT, 64>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, Ls);
+    extern __shared__ double dyn[];
+    run_block<NP, LT, 64, QLDS>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, dyn, Ls);
 }
 
-// Tile schedule: 16 lanes per cell, four cells per wave (N <= 16).
-template <typename LT>
+// Tile schedule: 16 lanes per cell, four cells per wave (N <= NP <= 16).  With
+// STAGE the mechanism tables (species .. incidence entries, one contiguous
+// range) are first copied into LDS, where the four cells share them, and the
+// reaction scratch follows them there; without it both stay in global memory.
+template <int NP, typename LT, bool STAGE>
 __global__ void __launch_bounds__(64) bdf_tile_kernel(DevMechView m, WaveTables wt, double *__restrict__ T,
                                                       const double *__restrict__ p, double *__restrict__ Y,
                                                       int64_t ldY, int64_t n, double dt, BdfParams prm,
@@ -928,42 +936,94 @@ __global__ void __launch_bounds__(64) bdf_tile_kernel(DevMechView m, WaveTables 
                                                       unsigned long long *__restrict__ queue,
                                                       double *__restrict__ qscratch)
 {
-    __shared__ WaveLds<16, LT, 16> Ls[4];
-    run_block<16, LT, 16>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, Ls);
+    __shared__ WaveLds<NP, LT, 16> Ls[4];
+    extern __shared__ double dyn[];
+    if constexpr (STAGE) {
+        const int tb = m.table_bytes;
+        const int4 *src = (const int4 *)m.species;
+        int4 *dst = (int4 *)dyn;
+        for (int i = threadIdx.x; i < tb / 16; i += 64) dst[i] = src[i];
+        __syncthreads();
+        const char *base = (const char *)m.species;
+        const char *lds = (const char *)dyn;
+        DevMechView ml = m;
+        ml.species = (const double *)lds;
+        ml.W = (const double *)(lds + ((const char *)m.W - base));
+        ml.invW = (const double *)(lds + ((const char *)m.invW - base));
+        ml.rxn = (const DevRxn *)(lds + ((const char *)m.rxn - base));
+        WaveTables wl;
+        wl.inc_off = (const int *)(lds + ((const char *)wt.inc_off - base));
+        wl.inc = (const int2 *)(lds + ((const char *)wt.inc - base));
+        run_block<NP, LT, 16, true>(ml, wl, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch,
+                                    dyn + tb / 8, Ls);
+    } else {
+        run_block<NP, LT, 16, false>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, dyn, Ls);
+    }
 }
 
 }  // namespace
 
 int wave_kernel_rows(int N) { return N <= 16 ? 16 : (N <= 40 ? 40 : (N <= 64 ? 64 : 0)); }
 
+// Persistent grid: as many one-wave blocks as fit on the device at once
+// (occupancy with `dyn` bytes of dynamic LDS), at most one per `cells_per_wave`
+// cells, at most max_groups / cells_per_wave when the reaction scratch is in
+// global memory (one slice per group).
 template <typename Kern>
-static hipError_t launch_groups(Kern kern, int cells_per_wave, const DevMechView &m, const WaveTables &wt, double *T,
-                                const double *p, double *Y, int64_t ldY, int64_t n, double dt,
-                                const BdfParams &prm, int32_t *status, int32_t *counters,
+static hipError_t launch_groups(Kern kern, int cells_per_wave, size_t dyn, bool qglobal, const DevMechView &m,
+                                const WaveTables &wt, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
+                                double dt, const BdfParams &prm, int32_t *status, int32_t *counters,
                                 unsigned long long *queue, double *qscratch, int max_groups, hipStream_t s)
 {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, queue);
-    const size_t qbytes = (size_t)cells_per_wave * 7 * (m.R > 0 ? m.R : 1) * sizeof(double);
-    const bool in_lds = qbytes <= 32768;
     int blocks = 0;
     {
         int dev = 0, cus = 0, per_cu = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 64, in_lds ? qbytes : 0) !=
-                hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 64, dyn) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         blocks = cus * per_cu;
     }
-    // a global scratch slice per group when the LDS cannot hold it
-    if (!in_lds && blocks > max_groups / cells_per_wave) blocks = max_groups / cells_per_wave;
+    if (qglobal && blocks > max_groups / cells_per_wave) blocks = max_groups / cells_per_wave;
     const int64_t need = (n + cells_per_wave - 1) / cells_per_wave;
     if (blocks > need) blocks = (int)need;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), in_lds ? qbytes : 0, s, m, wt, T, p, Y, ldY, n, dt, prm, status,
-                       counters, queue, in_lds ? nullptr : qscratch);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), dyn, s, m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue,
+                       qscratch);
     return hipGetLastError();
+}
+
+constexpr size_t kQbufLdsMax = 49152;     // reaction scratch of one wave kept in LDS up to this size
+constexpr size_t kTileStageMax = 24576;   // tables + scratch of a tile block staged in LDS up to this size
+
+template <int NP, typename LT>
+static hipError_t launch_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p, double *Y,
+                              int64_t ldY, int64_t n, double dt, const BdfParams &prm, int32_t *status,
+                              int32_t *counters, unsigned long long *queue, double *qscratch, int max_groups,
+                              hipStream_t s)
+{
+    const size_t qbytes = (size_t)7 * (m.R > 0 ? m.R : 1) * sizeof(double);
+    if (qbytes <= kQbufLdsMax)
+        return launch_groups(bdf_wave_kernel<NP, LT, true>, 1, qbytes, false, m, wt, T, p, Y, ldY, n, dt, prm,
+                             status, counters, queue, qscratch, max_groups, s);
+    return launch_groups(bdf_wave_kernel<64, LT, false>, 1, 0, true, m, wt, T, p, Y, ldY, n, dt, prm, status,
+                         counters, queue, qscratch, max_groups, s);
+}
+
+template <int NP, typename LT>
+static hipError_t launch_tile(const DevMechView &m, const WaveTables &wt, double *T, const double *p, double *Y,
+                              int64_t ldY, int64_t n, double dt, const BdfParams &prm, int32_t *status,
+                              int32_t *counters, unsigned long long *queue, double *qscratch, int max_groups,
+                              hipStream_t s)
+{
+    const size_t lds = (size_t)m.table_bytes + (size_t)4 * 7 * (m.R > 0 ? m.R : 1) * sizeof(double);
+    if (lds <= kTileStageMax)
+        return launch_groups(bdf_tile_kernel<NP, LT, true>, 4, lds, false, m, wt, T, p, Y, ldY, n, dt, prm, status,
+                             counters, queue, qscratch, max_groups, s);
+    return launch_groups(bdf_tile_kernel<16, LT, false>, 4, 0, true, m, wt, T, p, Y, ldY, n, dt, prm, status,
+                         counters, queue, qscratch, max_groups, s);
 }
 
 hipError_t launch_bdf_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
@@ -971,24 +1031,21 @@ hipError_t launch_bdf_wave(const DevMechView &m, const WaveTables &wt, double *T
                            int32_t *status, int32_t *counters, unsigned long long *queue,
                            double *qscratch, int max_groups, bool fp32_lu, int lanes, hipStream_t s)
 {
+#define CHEM_LAUNCH(FN, NPV)                                                                                     \
+    return fp32_lu ? FN<NPV, float>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch,        \
+                                    max_groups, s)                                                             \
+                   : FN<NPV, double>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch,       \
+                                     max_groups, s)
+    const int N = m.K + 1;
     if (lanes == 16) {
-        if (m.K + 1 > 16) return hipErrorInvalidValue;
-        return fp32_lu ? launch_groups(bdf_tile_kernel<float>, 4, m, wt, T, p, Y, ldY, n, dt, prm, status, counters,
-                                       queue, qscratch, max_groups, s)
-                       : launch_groups(bdf_tile_kernel<double>, 4, m, wt, T, p, Y, ldY, n, dt, prm, status, counters,
-                                       queue, qscratch, max_groups, s);
+        if (N <= 12) CHEM_LAUNCH(launch_tile, 12);
+        if (N <= 16) CHEM_LAUNCH(launch_tile, 16);
+        return hipErrorInvalidValue;
     }
-    const int NP = wave_kernel_rows(m.K + 1);
-#define CHEM_WAVE_CASE(NPV)                                                                                      \
-    if (NP == NPV)                                                                                               \
-        return fp32_lu ? launch_groups(bdf_wave_kernel<NPV, float>, 1, m, wt, T, p, Y, ldY, n, dt, prm, status,   \
-                                       counters, queue, qscratch, max_groups, s)                                 \
-                       : launch_groups(bdf_wave_kernel<NPV, double>, 1, m, wt, T, p, Y, ldY, n, dt, prm, status,  \
-                                       counters, queue, qscratch, max_groups, s);
-    CHEM_WAVE_CASE(16)
-    CHEM_WAVE_CASE(40)
-    CHEM_WAVE_CASE(64)
-#undef CHEM_WAVE_CASE
+    if (N <= 16) CHEM_LAUNCH(launch_wave, 16);
+    if (N <= 40) CHEM_LAUNCH(launch_wave, 40);
+    if (N <= 64) CHEM_LAUNCH(launch_wave, 64);
+#undef CHEM_LAUNCH
     return hipErrorInvalidValue;
 }
 

@@ -34,7 +34,8 @@ static_assert(sizeof(DevRxn) == 64, "reaction record is 64 bytes");
 struct DevMechView {
     int32_t K, R;
     int32_t two_range;          // 0 when every species uses one NASA range
-    int32_t pad;
+    int32_t table_bytes;        // species .. incidence entries: one contiguous
+                                // range of bytes starting at `species`
     const double *species;      // K x kSpeciesLen
     const double *W;            // K, kg/mol
     const double *invW;         // K

@@ -217,9 +217,9 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
     const int K = m->host.K;
     const bool thread_ok = m->gen != nullptr || chem::thread_kernel_supports(K);
     const bool wave_ok = chem::wave_kernel_rows(K + 1) > 0;
-    // automatic choice: the wave kernel for mixed precision and for mechanisms
-    // without a one-thread-per-cell kernel
-    const int sched = o.schedule >= 0 ? o.schedule : ((o.precision == 1 || !thread_ok) ? 1 : 0);
+    // automatic choice: the 16-lane tile when a cell fits in it (N <= 16),
+    // else one wave per cell; one thread per cell only when asked for
+    const int sched = o.schedule >= 0 ? o.schedule : (K + 1 <= 16 ? 2 : 1);
     if (sched == 0 && !thread_ok)
         return fail(CHEM_EUNSUP, "no one-thread-per-cell kernel is built for K = " + std::to_string(K));
     if (sched == 0 && o.precision != 0)
@@ -326,13 +326,15 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
         rx[i] = d;
     }
     m->W = W;
-    // one device block: species | W | invW | reactions
+    // one device block: the tables (species | W | invW | reactions | incidence
+    // offsets | incidence entries, contiguous so that a kernel can copy them
+    // into LDS in one pass), then the work-queue counters, then wave scratch
     const size_t n_sp = species.size() * sizeof(double);
     const size_t n_w = (size_t)K * sizeof(double);
-    const size_t off_w = (n_sp + 255) & ~size_t(255);
-    const size_t off_iw = (off_w + n_w + 255) & ~size_t(255);
-    const size_t off_rx = (off_iw + n_w + 255) & ~size_t(255);
-    const size_t off_q = (off_rx + rx.size() * sizeof(chem::DevRxn) + 255) & ~size_t(255);
+    auto a16 = [](size_t x) { return (x + 15) & ~size_t(15); };
+    const size_t off_w = a16(n_sp);
+    const size_t off_iw = a16(off_w + n_w);
+    const size_t off_rx = a16(off_iw + n_w);
     // species -> (reaction, net coefficient) incidence, reactions in order
     std::vector<int> inc_off(K + 1, 0);
     std::vector<std::vector<std::pair<int, int>>> inc_lists(K);
@@ -352,9 +354,11 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
         }
     }
     if (inc_flat.empty()) inc_flat.assign(2, 0);
-    const size_t off_io = off_q + kQueues * 256;
-    const size_t off_inc = (off_io + (K + 1) * sizeof(int) + 255) & ~size_t(255);
-    const size_t off_ws = (off_inc + inc_flat.size() * sizeof(int) + 255) & ~size_t(255);
+    const size_t off_io = a16(off_rx + rx.size() * sizeof(chem::DevRxn));
+    const size_t off_inc = a16(off_io + (K + 1) * sizeof(int));
+    const size_t table_bytes = a16(off_inc + inc_flat.size() * sizeof(int));
+    const size_t off_q = (table_bytes + 255) & ~size_t(255);
+    const size_t off_ws = off_q + kQueues * 256;
     const int wave_slots = 4096;   // cells in flight of the wave / tile kernels (global reaction scratch)
     const size_t total = off_ws + (size_t)wave_slots * 7 * (R > 0 ? R : 1) * sizeof(double);
     int prev = 0;
@@ -395,6 +399,7 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     m->view.W = (const double *)(blk + off_w);
     m->view.invW = (const double *)(blk + off_iw);
     m->view.rxn = (const chem::DevRxn *)(blk + off_rx);
+    m->view.table_bytes = (int32_t)table_bytes;
     m->queues = (unsigned long long *)(blk + off_q);
     m->wave.inc_off = (const int *)(blk + off_io);
     m->wave.inc = (const int2 *)(blk + off_inc);
