@@ -387,7 +387,7 @@ def run_surrogate(args):
                    "ncells": n, "species": K, "dt": dt},
         "roofline": {"bound": "mfma", "achieved": fwd_flops / (fwd_ms * 1e-3) / 1e12, "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": fwd_flops / (fwd_ms * 1e-3) / 1e12 / 2500.0, "traffic": None,
-                     "kernel": "gemm_bf16_kernel (forward, 4 layers)", "kernel_ms": fwd_ms,
+                     "kernel": "mlp_forward_kernel (fused forward, 4 layers)", "kernel_ms": fwd_ms,
                      "rows": int(X.shape[0])},
         "fallback_frac": nfb / n,
         "surrogate_step_ms": kern_ms,

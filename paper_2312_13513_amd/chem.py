@@ -73,6 +73,7 @@ def _load():
     L.chem_surrogate_fit_norm.argtypes = [vp, dp, dp, dp, i64, dp, i64, i64, C.c_double, vp]
     L.chem_surrogate_encode.argtypes = [vp, dp, dp, dp, i64, i64, dp, vp]
     L.chem_surrogate_forward.argtypes = [vp, dp, i64, dp, i64, vp]
+    L.chem_surrogate_forward_path.argtypes = [vp, dp, i64, dp, i64, C.c_int32, vp]
     L.chem_surrogate_apply.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, ckp, dp, vp]
     L.chem_surrogate_infer.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), ckp,
                                        dp, dp, dp, vp]
@@ -96,7 +97,7 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_default_checks", "chem_surrogate_create",
             "chem_free_surrogate", "chem_surrogate_info", "chem_surrogate_set_params",
             "chem_surrogate_get_params", "chem_surrogate_set_norm", "chem_surrogate_get_norm",
-            "chem_surrogate_fit_norm", "chem_surrogate_encode", "chem_surrogate_forward",
+            "chem_surrogate_fit_norm", "chem_surrogate_encode", "chem_surrogate_forward", "chem_surrogate_forward_path",
             "chem_surrogate_apply", "chem_surrogate_infer", "chem_surrogate_grad",
             "chem_surrogate_get_grads", "chem_surrogate_set_grads", "chem_surrogate_adam",
             "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load")
@@ -312,9 +313,10 @@ class Surrogate:
         _check(_lib.chem_surrogate_encode(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
                                           T.shape[0], _ptr(X), _stream(stream)))
 
-    def forward(self, X, out, stream=None):
-        _check(_lib.chem_surrogate_forward(C.c_void_p(self.handle), _ptr(X), X.shape[0], _ptr(out),
-                                           out.shape[1], _stream(stream)))
+    def forward(self, X, out, path=0, stream=None):
+        """path: 0 library choice, 1 one GEMM per layer, 2 fused kernel."""
+        _check(_lib.chem_surrogate_forward_path(C.c_void_p(self.handle), _ptr(X), X.shape[0], _ptr(out),
+                                                out.shape[1], int(path), _stream(stream)))
 
     def apply(self, T, p, Y, out, checks=None, mask=None, stream=None):
         _check(_lib.chem_surrogate_apply(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],

@@ -42,6 +42,26 @@ struct GemmArgs {
 
 hipError_t launch_gemm_bf16(const GemmArgs &g, hipStream_t s);
 
+// Fused inference forward pass: out = W4 h3 + b4 with h_l = GELU(W_l h_(l-1) + b_l),
+// h_0 = the 64-wide input rows.  W[l] holds the [out_l][in_l] BF16 weights in
+// fragment order (launch_swizzle_frag; in_l of layer 0 is 64), b[l] FP32.
+// One block takes 64 rows through all four layers with the activations in
+// LDS; the result equals the layer-by-layer GEMMs bit for bit.
+struct MlpArgs {
+    const bf16_t *X;        // rows x 64
+    int64_t rows;
+    const bf16_t *W[4];
+    const float *b[4];
+    int in_l[4], out_l[4];
+    float *out;
+    int64_t ldo;
+};
+// false when the hidden widths do not fit the fused kernel (each <= 512).
+bool mlp_fused_supported(const int out_l[4]);
+// W [N][K] row-major -> Wf in the fused kernel's fragment order (N % 16 == 0, K % 32 == 0).
+hipError_t launch_swizzle_frag(const bf16_t *W, int N, int K, bf16_t *Wf, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpArgs &a, hipStream_t s);
+
 // Network input of cells: x = zscore([T, p, BoxCox(max(Y,0); 0.1)]) -> FP32 -> BF16,
 // written as rows of nin_pad values (zero padded).  norm = mu_x[nin], sig_x[nin].
 hipError_t launch_encode(const double *T, const double *p, const double *Y, int64_t ldY, int64_t n,

@@ -26,9 +26,27 @@ __device__ __forceinline__ bf16_t to_bf16(float f)
     return (bf16_t)(u >> 16);
 }
 
+// GELU(u) = u Phi(u) without branches: Phi(-|u|) = erfc(z)/2, z = |u|/sqrt(2),
+// with erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2), P of degree 9 fitted in
+// FP64 to ln(erfcx(z)/t) (gelu_fit.py).  The FP32 evaluation stays within a
+// relative 3e-5 of the exact GELU for all u; the activations are then rounded
+// to BF16 (unit roundoff 2^-8).
 __device__ __forceinline__ float gelu(float u)
 {
-    return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f));
+    const float z = fabsf(u) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);
+    float p = 1.708727777e-01f;
+    p = fmaf(p, t, -8.221522344e-01f);
+    p = fmaf(p, t, 1.488515889e+00f);
+    p = fmaf(p, t, -1.135204000e+00f);
+    p = fmaf(p, t, 2.788680844e-01f);
+    p = fmaf(p, t, -1.862880617e-01f);
+    p = fmaf(p, t, 9.678418949e-02f);
+    p = fmaf(p, t, 3.740919597e-01f);
+    p = fmaf(p, t, 1.000023680e+00f);
+    p = fmaf(p, t, -1.265512225e+00f);
+    const float half = 0.5f * t * __expf(p - z * z);
+    return u * (u >= 0.0f ? 1.0f - half : half);
 }
 
 __device__ __forceinline__ float gelu_grad(float u)
@@ -126,6 +144,144 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
                     break;
                 }
             }
+}
+
+// ---------------------------------------------------------------------------
+// Fused forward pass (inference): 64 rows per block, eight waves; each layer
+// is a 64 x N x K product with A (the activations) from LDS and B (the
+// weights, L2-resident) loaded by each lane straight into its MFMA operand
+// registers.  Wave w owns the 16-column blocks w + 8 j of the layer's output
+// for all four 16-row blocks, so every weight fragment is loaded once per
+// block.  The weights come in fragment order (swizzle_frag_kernel): the
+// 16 x 32 operand of column block jb and K step ks is 1 KB at
+// ((jb * K/32 + ks) * 512 + 8 lane), so a wave reads it as one contiguous
+// 16-byte-per-lane load.  The accumulation over K runs in steps of 32 in
+// increasing order, as in gemm_bf16_kernel, and the epilogues are the same,
+// so the result is bitwise that of the GEMMs.
+// ---------------------------------------------------------------------------
+constexpr int kMlpRows = 64, kMlpWaves = 8, kMlpMaxN = 512, kMlpJ = kMlpMaxN / 16 / kMlpWaves;
+constexpr int kMlpPad = 8;   // bf16 pad per LDS row: spreads the 16 rows of an A fragment over banks
+constexpr int kMlpDepth = 4; // K steps of weight fragments loaded ahead
+
+template <int J>
+__device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, const bf16_t *__restrict__ Wf, int N,
+                                          const float *__restrict__ bias, bf16_t *outs, int lds_out,
+                                          float *outg, int64_t ldg, int64_t r0, int64_t rows)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kk = (lane >> 4) * 8;
+    const int nblk = N >> 4, ksteps = K >> 5;
+    floatx4 acc[J][4];
+#pragma unroll
+    for (int j = 0; j < J; j++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc[j][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bf16_t *wfr[J];
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const int jb = w + kMlpWaves * j;
+        wfr[j] = Wf + (int64_t)(jb < nblk ? jb : 0) * ksteps * 512 + lane * 8;
+    }
+    const bf16_t *arow = in + (lane & 15) * ldi + kk;
+    // weight fragments of the next kMlpDepth K steps are in flight while the
+    // current step's products run (one register slot per step, the loop
+    // unrolled by the depth so that every slot index is static)
+    bf16x8 bq[kMlpDepth][J];
+#pragma unroll
+    for (int d = 0; d < kMlpDepth; d++)
+#pragma unroll
+        for (int j = 0; j < J; j++)
+            if (d < ksteps && w + kMlpWaves * j < nblk) __builtin_memcpy(&bq[d][j], wfr[j] + d * 512, 16);
+    for (int s0 = 0; s0 < ksteps; s0 += kMlpDepth) {
+#pragma unroll
+        for (int d = 0; d < kMlpDepth; d++) {
+            const int ks = s0 + d;
+            if (ks >= ksteps) break;
+            bf16x8 a[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) __builtin_memcpy(&a[i], arow + i * 16 * ldi + ks * 32, 16);
+#pragma unroll
+            for (int j = 0; j < J; j++)
+                if (w + kMlpWaves * j < nblk)
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bq[d][j], acc[j][i], 0, 0, 0);
+            const int kn = ks + kMlpDepth;
+#pragma unroll
+            for (int j = 0; j < J; j++)
+                if (kn < ksteps && w + kMlpWaves * j < nblk) __builtin_memcpy(&bq[d][j], wfr[j] + kn * 512, 16);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const int jb = w + kMlpWaves * j;
+        if (jb >= nblk) continue;
+        const int n = jb * 16 + (lane & 15);
+        const float bn = bias[n];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int m = i * 16 + (lane >> 4) * 4 + r;
+                const float u = acc[j][i][r] + bn;
+                if (outs) {
+                    outs[m * lds_out + n] = to_bf16(gelu(u));
+                } else if (r0 + m < rows) {
+                    outg[(r0 + m) * ldg + n] = u;
+                }
+            }
+    }
+}
+
+// one layer with the register budget of its width
+__device__ __forceinline__ void mlp_layer_any(const bf16_t *in, int ldi, int K, const bf16_t *Wf, int N,
+                                              const float *bias, bf16_t *outs, int lds_out, float *outg,
+                                              int64_t ldg, int64_t r0, int64_t rows)
+{
+    if (N <= 128)
+        mlp_layer<1>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
+    else if (N <= 256)
+        mlp_layer<2>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
+    else
+        mlp_layer<kMlpJ>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
+}
+
+// Weights [N][K] -> fragment order (see above), 8 values per thread.
+__global__ void __launch_bounds__(256) swizzle_frag_kernel(const bf16_t *__restrict__ W, int N, int K,
+                                                           bf16_t *__restrict__ Wf)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 8-value chunk of Wf
+    if (c >= (int64_t)N * K / 8) return;
+    const int64_t blk = c >> 6;
+    const int L = (int)(c & 63);
+    const int ksteps = K >> 5;
+    const int jb = (int)(blk / ksteps), ks = (int)(blk % ksteps);
+    const int n = jb * 16 + (L & 15), k = ks * 32 + (L >> 4) * 8;
+    *(uint4 *)(Wf + c * 8) = *(const uint4 *)(W + (int64_t)n * K + k);
+}
+
+__global__ void __launch_bounds__(kMlpRows * kMlpWaves) mlp_forward_kernel(MlpArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) bf16_t mlp_lds[];
+    const int ld0 = (a.out_l[1] > 64 ? a.out_l[1] : 64) + kMlpPad;
+    const int ld1 = (a.out_l[0] > a.out_l[2] ? a.out_l[0] : a.out_l[2]) + kMlpPad;
+    bf16_t *buf0 = mlp_lds, *buf1 = mlp_lds + kMlpRows * ld0;
+    const int64_t r0 = (int64_t)blockIdx.x * kMlpRows;
+    // the block's input rows, zero past the end
+    for (int c = threadIdx.x; c < kMlpRows * 8; c += kMlpRows * kMlpWaves) {
+        const int r = c >> 3, kc = (c & 7) * 8;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (r0 + r < a.rows) v = *(const uint4 *)(a.X + (r0 + r) * 64 + kc);
+        *(uint4 *)(buf0 + r * ld0 + kc) = v;
+    }
+    __syncthreads();
+    mlp_layer_any(buf0, ld0, a.in_l[0], a.W[0], a.out_l[0], a.b[0], buf1, ld1, nullptr, 0, r0, a.rows);
+    __syncthreads();
+    mlp_layer_any(buf1, ld1, a.in_l[1], a.W[1], a.out_l[1], a.b[1], buf0, ld0, nullptr, 0, r0, a.rows);
+    __syncthreads();
+    mlp_layer_any(buf0, ld0, a.in_l[2], a.W[2], a.out_l[2], a.b[2], buf1, ld1, nullptr, 0, r0, a.rows);
+    __syncthreads();
+    mlp_layer_any(buf1, ld1, a.in_l[3], a.W[3], a.out_l[3], a.b[3], nullptr, 0, a.out, a.ldo, r0, a.rows);
 }
 
 // ---------------------------------------------------------------------------
@@ -522,6 +678,47 @@ hipError_t launch_gemm_bf16(const GemmArgs &g, hipStream_t s)
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM));
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+static size_t mlp_lds_bytes(const int out_l[4])
+{
+    const int ld0 = (out_l[1] > 64 ? out_l[1] : 64) + kMlpPad;
+    const int ld1 = (out_l[0] > out_l[2] ? out_l[0] : out_l[2]) + kMlpPad;
+    return (size_t)kMlpRows * (ld0 + ld1) * sizeof(bf16_t);
+}
+
+bool mlp_fused_supported(const int out_l[4])
+{
+    for (int l = 0; l < 4; l++)
+        if (out_l[l] > kMlpMaxN || out_l[l] % 16 != 0) return false;
+    int dev = 0, max_lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return false;
+    return mlp_lds_bytes(out_l) <= (size_t)max_lds;
+}
+
+hipError_t launch_swizzle_frag(const bf16_t *W, int N, int K, bf16_t *Wf, hipStream_t s)
+{
+    if (N % 16 != 0 || K % 32 != 0) return hipErrorInvalidValue;
+    const int64_t chunks = (int64_t)N * K / 8;
+    hipLaunchKernelGGL(swizzle_frag_kernel, dim3(blocks_for(chunks, 256)), dim3(256), 0, s, W, N, K, Wf);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const MlpArgs &a, hipStream_t s)
+{
+    if (a.rows <= 0) return hipSuccess;
+    if (!mlp_fused_supported(a.out_l) || a.in_l[0] != 64) return hipErrorInvalidValue;
+    const size_t lds = mlp_lds_bytes(a.out_l);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)mlp_forward_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((a.rows + kMlpRows - 1) / kMlpRows)),
+                       dim3(kMlpRows * kMlpWaves), lds, s, a);
     return hipGetLastError();
 }
 

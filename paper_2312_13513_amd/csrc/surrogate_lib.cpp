@@ -77,6 +77,8 @@ struct chem_surr_s {
     int64_t off_W[4], off_b[4], n_pad = 0, n_logical = 0;
     float *master = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
     bf16_t *wbf = nullptr;
+    bf16_t *wfrag = nullptr;          // the BF16 weights in the fused kernel's fragment order
+    bool frag_valid = false;          // wfrag matches wbf
     double *norm_dev = nullptr;       // mu_x, sig_x, mu_y, sig_y
     double *counts_dev = nullptr;     // [E][K]
     int64_t *scalars = nullptr;       // [0] fallback count
@@ -164,10 +166,42 @@ hipError_t gemm(const bf16_t *A, int64_t sam, int64_t sak, const bf16_t *B, int6
     return chem::launch_gemm_bf16(g, st);
 }
 
-// Forward pass of `rows` rows of X; saves pre-activations when U[0] != NULL.
-hipError_t forward(const chem_surr_s *s, const bf16_t *X, int rows, bf16_t *const H[3],
-                   float *const U[3], float *OUT, int64_t ldo, hipStream_t st)
+bool fused_ok(const chem_surr_s *s) { return s->in_l[0] == kInPad && chem::mlp_fused_supported(s->out_l); }
+
+// Inference forward pass of all four layers in one kernel (activations in
+// LDS); the fragment-order copy of the weights is made when they changed.
+hipError_t forward_fused(chem_surr_s *s, const bf16_t *X, int64_t rows, float *OUT, int64_t ldo,
+                         hipStream_t st)
 {
+    if (!s->frag_valid) {
+        for (int l = 0; l < 4; l++) {
+            hipError_t e = chem::launch_swizzle_frag(s->wbf + s->off_W[l], s->out_l[l], s->in_l[l],
+                                                     s->wfrag + s->off_W[l], st);
+            if (e != hipSuccess) return e;
+        }
+        s->frag_valid = true;
+    }
+    chem::MlpArgs a{};
+    a.X = X;
+    a.rows = rows;
+    for (int l = 0; l < 4; l++) {
+        a.W[l] = s->wfrag + s->off_W[l];
+        a.b[l] = s->master + s->off_b[l];
+        a.in_l[l] = s->in_l[l];
+        a.out_l[l] = s->out_l[l];
+    }
+    a.out = OUT;
+    a.ldo = ldo;
+    return chem::launch_mlp_forward(a, st);
+}
+
+// Forward pass of `rows` rows of X; saves pre-activations when U[0] != NULL.
+// Without saved pre-activations the fused kernel runs when the widths allow
+// it (the same result bit for bit), unless `layered` asks for the GEMMs.
+hipError_t forward(chem_surr_s *s, const bf16_t *X, int rows, bf16_t *const H[3],
+                   float *const U[3], float *OUT, int64_t ldo, hipStream_t st, bool layered = false)
+{
+    if (!U[0] && !layered && fused_ok(s)) return forward_fused(s, X, rows, OUT, ldo, st);
     const bf16_t *in = X;
     int64_t ld_in = kInPad;
     hipError_t e = hipSuccess;
@@ -256,6 +290,7 @@ int download_logical(chem_surr_s *s, const float *dev, float *host, int64_t coun
 
 int refresh_bf16(chem_surr_s *s, hipStream_t st)
 {
+    s->frag_valid = false;
     return check_hip(chem::launch_to_bf16(s->master, s->wbf, s->n_pad, st), "bf16 weights");
 }
 
@@ -384,7 +419,7 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
     }
     s->n_pad = off;
     const int64_t nn = 2 * (int64_t)s->nin + 2 * K;
-    const size_t bytes = 4 * carve_size<float>(s->n_pad) + carve_size<bf16_t>(s->n_pad) +
+    const size_t bytes = 4 * carve_size<float>(s->n_pad) + 2 * carve_size<bf16_t>(s->n_pad) +
                          carve_size<double>(nn) + carve_size<double>((int64_t)E * K) +
                          carve_size<int64_t>(8) + carve_size<double>(80);
     if (hipMalloc(&s->block, bytes) != hipSuccess) {
@@ -399,6 +434,7 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
     s->am = c.take<float>(s->n_pad);
     s->av = c.take<float>(s->n_pad);
     s->wbf = c.take<bf16_t>(s->n_pad);
+    s->wfrag = c.take<bf16_t>(s->n_pad);
     s->norm_dev = c.take<double>(nn);
     s->counts_dev = c.take<double>((int64_t)E * K);
     s->scalars = c.take<int64_t>(8);
@@ -531,10 +567,21 @@ int chem_surrogate_encode(chem_surr s, const double *T, const double *p, const d
 
 int chem_surrogate_forward(chem_surr s, const uint16_t *X, int64_t n, float *out, int64_t ldo, void *stream)
 {
+    return chem_surrogate_forward_path(s, X, n, out, ldo, 0, stream);
+}
+
+int chem_surrogate_forward_path(chem_surr s, const uint16_t *X, int64_t n, float *out, int64_t ldo, int32_t path,
+                                void *stream)
+{
     int rc = check_surr(s);
-    if (rc != CHEM_OK || n == 0) return rc;
+    if (rc != CHEM_OK) return rc;
+    if (path < 0 || path > 2) return fail(CHEM_EINVAL, "path must be 0, 1 or 2");
+    if (path == 2 && !fused_ok(s)) return fail(CHEM_EUNSUP, "the fused forward kernel takes widths up to 512");
+    if (n == 0) return CHEM_OK;
     if (n < 0 || ldo < s->nout_pad) return fail(CHEM_EINVAL, "need ncells >= 0 and ldo >= K rounded up to 16");
     if (!is_device_ptr(X) || !is_device_ptr(out)) return fail(CHEM_EINVAL, "X and out must be device pointers");
+    if (path != 1 && fused_ok(s)) return check_hip(forward_fused(s, (const bf16_t *)X, n, out, ldo, (hipStream_t)stream),
+                                                   "fused forward");
     const int64_t rows = n < kChunk ? n : kChunk;
     rc = ensure_acts(s, rows, false);
     if (rc != CHEM_OK) return rc;
@@ -543,7 +590,7 @@ int chem_surrogate_forward(chem_surr s, const uint16_t *X, int64_t n, float *out
     hipStream_t st = (hipStream_t)stream;
     for (int64_t r0 = 0; r0 < n; r0 += kChunk) {
         const int rr = (int)(n - r0 < kChunk ? n - r0 : kChunk);
-        hipError_t e = forward(s, X + r0 * kInPad, rr, a.H, noU, out + r0 * ldo, ldo, st);
+        hipError_t e = forward(s, X + r0 * kInPad, rr, a.H, noU, out + r0 * ldo, ldo, st, true);
         if (e != hipSuccess) return check_hip(e, "forward");
     }
     return CHEM_OK;
@@ -740,6 +787,7 @@ int chem_surrogate_train(chem_surr s, const double *T, const double *p, const do
                 s->adam_t++;
                 e = chem::launch_adam(adam_args(s, lr), st);
                 if (e == hipSuccess) e = chem::launch_to_bf16(s->master, s->wbf, s->n_pad, st);
+                s->frag_valid = false;
             }
         }
         if (e == hipSuccess && loss_per_epoch) {

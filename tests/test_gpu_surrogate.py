@@ -119,8 +119,9 @@ def _forward_bound(params_bf, x):
             return u, eu
 
 
-@pytest.mark.parametrize("rows", [1, 63, 2050])
-def test_forward_parity(torch, mechs, rows):
+@pytest.mark.parametrize("rows,path", [(1, 1), (63, 1), (2050, 1), (1, 2), (63, 2), (2050, 2)])
+def test_forward_parity(torch, mechs, rows, path):
+    """path 1: one GEMM per layer; path 2: the fused kernel."""
     from chemgen.surrogate_data import split_params
     from oracle import surrogate as S
     from paper_2312_13513_amd import chem
@@ -132,7 +133,7 @@ def test_forward_parity(torch, mechs, rows):
     Xb[:, :K + 2] = S.bf16_bits(x)
     X = torch.tensor(Xb.view(np.int16), device="cuda:0")
     out = torch.zeros((rows, s.nout_pad), dtype=torch.float32, device="cuda:0")
-    s.forward(X, out)
+    s.forward(X, out, path=path)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     params_bf = [(S.to_bf16(W.astype(np.float32)), b) for W, b in split_params(flat, dims)]
@@ -144,6 +145,45 @@ def test_forward_parity(torch, mechs, rows):
     assert np.all(err <= 2.0 * bound + 1e-6)
     assert np.all(got[:, K:] == 0.0)          # padded outputs: zero rows of W4, zero bias
     assert rel < 1e-2
+    s.close()
+
+
+@pytest.mark.parametrize("h", [(512, 256, 128), (64, 64, 64), (128, 512, 64)])
+def test_fused_forward_bitwise_layered(torch, mechs, h):
+    """The fused kernel against the layer-by-layer GEMMs: the same MFMA
+    accumulation order and epilogues, so the outputs are equal bit for bit;
+    row counts that leave a partial 64-row tile, several tiles, and one
+    larger than the GEMM path's 262,144-row chunk."""
+    from oracle import surrogate as S
+    from paper_2312_13513_amd import chem
+    K = 35
+    s, dims, flat = _surr(chem, mechs["M35"], K, h=h)
+    for rows in (1, 65, 4097, 300000):
+        rng = np.random.default_rng(rows)
+        x = S.to_bf16(rng.normal(0, 1, (rows, K + 2)).astype(np.float32))
+        Xb = np.zeros((rows, 64), dtype=np.uint16)
+        Xb[:, :K + 2] = S.bf16_bits(x)
+        X = torch.tensor(Xb.view(np.int16), device="cuda:0")
+        o1 = torch.full((rows, s.nout_pad + 3), -9.0, dtype=torch.float32, device="cuda:0")
+        o2 = torch.full((rows, s.nout_pad + 3), -9.0, dtype=torch.float32, device="cuda:0")
+        s.forward(X, o1, path=1)
+        s.forward(X, o2, path=2)
+        torch.cuda.synchronize()
+        assert torch.equal(o1, o2), f"rows {rows}: fused and layered outputs differ"
+        assert torch.all(o2[:, s.nout_pad:] == -9.0)          # columns past the outputs untouched
+    _say(f"[fused forward {h}] equal to the layered GEMMs bit for bit at 1, 65, 4097 and 300000 rows")
+    s.close()
+
+
+def test_fused_forward_rejects_wide_layers(torch, mechs):
+    from paper_2312_13513_amd import chem
+    s, dims, flat = _surr(chem, mechs["M9"], 9, h=(1024, 64, 64))
+    X = torch.zeros((4, 64), dtype=torch.int16, device="cuda:0")
+    out = torch.zeros((4, s.nout_pad), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(chem.ChemError) as e:
+        s.forward(X, out, path=2)
+    assert e.value.code == -5
+    s.forward(X, out, path=0)       # the library falls back to the GEMMs
     s.close()
 
 
