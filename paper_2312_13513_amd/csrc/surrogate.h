@@ -81,8 +81,8 @@ hipError_t launch_fit_norm(const double *T, const double *p, const double *Y, in
 
 struct ApplyArgs {
     const double *species;   // NASA blocks of the mechanism (device)
-    const double *W;         // molar masses (device)
-    const double *counts;    // n_ke as double, [E][K] (device)
+    const double *rw;        // R / W_k, J/(kg K) (device)
+    const double *ncoef;     // n_ke / W_k, [E][K] (device), E <= 8
     int K, E;
     bool two_range;
     const double *mu_y, *sig_y;

@@ -27,7 +27,7 @@ __device__ __forceinline__ bf16_t to_bf16(float f)
 }
 
 // GELU(u) = u Phi(u) without branches: Phi(-|u|) = erfc(z)/2, z = |u|/sqrt(2),
-// with erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2), P of degree 9 fitted in
+// with erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2), P of degree 7 fitted in
 // FP64 to ln(erfcx(z)/t) (gelu_fit.py).  The FP32 evaluation stays within a
 // relative 3e-5 of the exact GELU for all u; the activations are then rounded
 // to BF16 (unit roundoff 2^-8).
@@ -35,19 +35,20 @@ __device__ __forceinline__ float gelu(float u)
 {
     const float z = fabsf(u) * 0.70710678118654752f;
     const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);
-    float p = 1.708727777e-01f;
-    p = fmaf(p, t, -8.221522344e-01f);
-    p = fmaf(p, t, 1.488515889e+00f);
-    p = fmaf(p, t, -1.135204000e+00f);
-    p = fmaf(p, t, 2.788680844e-01f);
-    p = fmaf(p, t, -1.862880617e-01f);
-    p = fmaf(p, t, 9.678418949e-02f);
-    p = fmaf(p, t, 3.740919597e-01f);
-    p = fmaf(p, t, 1.000023680e+00f);
-    p = fmaf(p, t, -1.265512225e+00f);
+    float p = -1.661221119e-01f;
+    p = fmaf(p, t, 6.685151608e-01f);
+    p = fmaf(p, t, -8.729041482e-01f);
+    p = fmaf(p, t, 2.482906394e-01f);
+    p = fmaf(p, t, 4.035713614e-03f);
+    p = fmaf(p, t, 3.840898445e-01f);
+    p = fmaf(p, t, 9.996045788e-01f);
+    p = fmaf(p, t, -1.265509297e+00f);
     const float half = 0.5f * t * __expf(p - z * z);
     return u * (u >= 0.0f ? 1.0f - half : half);
 }
+
+// Activation FP32 -> BF16 with the hardware conversion (round to nearest even).
+__device__ __forceinline__ bf16_t act_bf16(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
 
 __device__ __forceinline__ float gelu_grad(float u)
 {
@@ -133,11 +134,11 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
                 case kEpiBiasGeluBf16: {
                     const float u = v + (g.bias ? g.bias[n] : 0.0f);
                     if (g.outf) g.outf[(int64_t)m * g.ldf + n] = u;
-                    g.outh[(int64_t)m * g.ldh + n] = to_bf16(gelu(u));
+                    g.outh[(int64_t)m * g.ldh + n] = act_bf16(gelu(u));
                     break;
                 }
                 case kEpiGeluGradBf16:
-                    g.outh[(int64_t)m * g.ldh + n] = to_bf16(v * gelu_grad(g.u[(int64_t)m * g.ldu + n]));
+                    g.outh[(int64_t)m * g.ldh + n] = act_bf16(v * gelu_grad(g.u[(int64_t)m * g.ldu + n]));
                     break;
                 default:
                     g.outf[(int64_t)m * g.ldf + n] = v;
@@ -225,7 +226,7 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
                 const int m = i * 16 + (lane >> 4) * 4 + r;
                 const float u = acc[j][i][r] + bn;
                 if (outs) {
-                    outs[m * lds_out + n] = to_bf16(gelu(u));
+                    outs[m * lds_out + n] = act_bf16(gelu(u));
                 } else if (r0 + m < rows) {
                     outg[(r0 + m) * ldg + n] = u;
                 }
@@ -388,9 +389,26 @@ __global__ void __launch_bounds__(256) fit_norm_kernel(const double *__restrict_
 // ---------------------------------------------------------------------------
 // decode, temperature recovery, checks
 // ---------------------------------------------------------------------------
-constexpr double kRuS = 8.31446261815324;
+constexpr int kApplyMaxE = 8;   // elements the decode kernel handles
 
 // mass-specific enthalpy and cp of the mixture Y[0..K) (KM >= K, static loop)
+// Thermo of species k at T (the NASA range of the lane's T): cp/R and H/(R T).
+__device__ __forceinline__ void species_cp_hrt(const ApplyArgs &a, int k, double T, double invT, double &cp,
+                                               double &hrt)
+{
+    const double *s = a.species + k * kSpeciesLen;
+    const bool low = !a.two_range || T < s[0];
+    double r[11];
+    const double *c = s + 1 + (low ? 0 : kRangeLen);
+#pragma unroll
+    for (int j = 0; j < 11; j++)
+        if (j != 6) r[j] = c[j];
+    cp = r[0] + T * (r[1] + T * (r[2] + T * (r[3] + T * r[4])));
+    hrt = r[0] + T * (r[7] + T * (r[8] + T * (r[9] + T * r[10]))) + r[5] * invT;
+}
+
+// Mixture enthalpy (J/kg) and cp (J/(kg K)) at T: sums over species in order,
+// each term Y_k (R/W_k) times T H_k/(R T), resp. cp_k/R.
 template <int KM>
 __device__ __forceinline__ void mix_h_cp(const ApplyArgs &a, double T, const double (&Y)[KM], double &hm,
                                          double &cm)
@@ -400,21 +418,22 @@ __device__ __forceinline__ void mix_h_cp(const ApplyArgs &a, double T, const dou
 #pragma unroll
     for (int k = 0; k < KM; k++) {
         if (k < a.K) {
-            const double *s = a.species + k * kSpeciesLen;
-            const double *r = (!a.two_range || T < s[0]) ? s + 1 : s + 1 + kRangeLen;
-            const double cp = r[0] + T * (r[1] + T * (r[2] + T * (r[3] + T * r[4])));
-            const double hrt = r[0] + T * (r[7] + T * (r[8] + T * (r[9] + T * r[10]))) + r[5] * invT;
-            h += Y[k] * kRuS * T * hrt / a.W[k];
-            c += Y[k] * kRuS * cp / a.W[k];
+            double cp, hrt;
+            species_cp_hrt(a, k, T, invT, cp, hrt);
+            const double yr = Y[k] * a.rw[k];
+            h += yr * (T * hrt);
+            c += yr * cp;
         }
     }
     hm = h;
     cm = c;
 }
 
-// KM: a compile-time bound on the species count, so that the cell's mass
-// fractions stay in registers.
-template <int KM>
+// Decode, checks and temperature recovery, one thread per cell.  The input
+// state is read once: its element content, the element residual of the
+// prediction and the input enthalpy are accumulated in the same pass, so
+// only the predicted mass fractions stay in registers.
+template <int KM, int KE>
 __global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restrict__ T,
                                                     const double *__restrict__ p,
                                                     double *__restrict__ Y, int64_t ldY, int64_t n,
@@ -430,35 +449,39 @@ __global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restr
         (void)p;
         const int K = a.K;
         const double T0 = T[i];
-        double Y0[KM], Y1[KM];
+        const double invT0 = 1.0 / T0;
+        double Y1[KM];
         bool ok = true;
-        double sum = 0.0, ymin = 1e300;
+        double sum = 0.0, ymin = 1e300, h0 = 0.0;
+        double res[KE], ref[KE];
+#pragma unroll
+        for (int e = 0; e < KE; e++) res[e] = ref[e] = 0.0;
 #pragma unroll
         for (int k = 0; k < KM; k++) {
-            Y0[k] = 0.0;
             Y1[k] = 0.0;
             if (k < K) {
-                Y0[k] = Y[(int64_t)k * ldY + i];
-                const double v = Y0[k] + a.mu_y[k] + a.sig_y[k] * (double)out[i * nout_pad + k];
+                const double y0 = Y[(int64_t)k * ldY + i];
+                const double v = y0 + a.mu_y[k] + a.sig_y[k] * (double)out[i * nout_pad + k];
                 Y1[k] = v;
                 ok = ok && isfinite(v);
                 sum += v;
                 ymin = fmin(ymin, v);
+#pragma unroll
+                for (int e = 0; e < KE; e++)
+                    if (e < a.E) {
+                        const double nk = a.ncoef[e * K + k];
+                        res[e] += nk * (v - y0);
+                        ref[e] += nk * y0;
+                    }
+                double cp, hrt;
+                species_cp_hrt(a, k, T0, invT0, cp, hrt);
+                h0 += (y0 * a.rw[k]) * (T0 * hrt);
             }
         }
         // element residual relative to the element content of the input
-        for (int e = 0; ok && e < a.E; e++) {
-            double res = 0.0, ref = 0.0;
 #pragma unroll
-            for (int k = 0; k < KM; k++) {
-                if (k < K) {
-                    const double nk = a.counts[e * K + k] / a.W[k];
-                    res += nk * (Y1[k] - Y0[k]);
-                    ref += nk * Y0[k];
-                }
-            }
-            if (fabs(res) / fmax(ref, 1e-12) > a.elem_tol) ok = false;
-        }
+        for (int e = 0; e < KE; e++)
+            if (ok && e < a.E && fabs(res[e]) / fmax(ref[e], 1e-12) > a.elem_tol) ok = false;
         if (ok && fabs(sum - 1.0) > a.sum_tol) ok = false;
         if (ok && ymin < -a.neg_tol) ok = false;
         double Tn = T0;
@@ -471,13 +494,10 @@ __global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restr
                     s2 += Y1[k];
                 }
             }
+            const double inv_s2 = 1.0 / s2;
 #pragma unroll
             for (int k = 0; k < KM; k++)
-                if (k < K) Y1[k] = Y1[k] / s2;
-            // enthalpy of the input state
-            double h0, c0;
-            mix_h_cp<KM>(a, T0, Y0, h0, c0);
-            (void)c0;
+                if (k < K) Y1[k] = Y1[k] * inv_s2;
             // Newton on h(T, Y2) = h0 from T0; |dT| < 1e-10 K, at most 20
             // iterations, T kept in [200, 3500] K
             bool conv = false;
@@ -756,9 +776,14 @@ hipError_t launch_apply(const ApplyArgs &a, double *T, const double *p, double *
                         int32_t *status, int32_t *list, int64_t *count, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-#define CHEM_APPLY(KM)                                                                                  \
-    hipLaunchKernelGGL(apply_kernel<KM>, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, ldY, n, base, \
-                       out, nout_pad, mask, status, list, count)
+    if (a.E > kApplyMaxE) return hipErrorInvalidValue;
+#define CHEM_APPLY(KM)                                                                                        \
+    if (a.E <= 4)                                                                                             \
+        hipLaunchKernelGGL((apply_kernel<KM, 4>), dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, ldY, n, \
+                           base, out, nout_pad, mask, status, list, count);                                   \
+    else                                                                                                      \
+        hipLaunchKernelGGL((apply_kernel<KM, kApplyMaxE>), dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, \
+                           ldY, n, base, out, nout_pad, mask, status, list, count)
     if (a.K <= 16)
         CHEM_APPLY(16);
     else if (a.K <= 32)

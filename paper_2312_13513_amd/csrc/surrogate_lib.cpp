@@ -80,7 +80,7 @@ struct chem_surr_s {
     bf16_t *wfrag = nullptr;          // the BF16 weights in the fused kernel's fragment order
     bool frag_valid = false;          // wfrag matches wbf
     double *norm_dev = nullptr;       // mu_x, sig_x, mu_y, sig_y
-    double *counts_dev = nullptr;     // [E][K]
+    double *coef_dev = nullptr;       // [E][K] n_ke / W_k, then [K] R / W_k
     int64_t *scalars = nullptr;       // [0] fallback count
     double *loss_dev = nullptr;       // [0] accumulated loss, [1..64] partials
     void *block = nullptr;
@@ -327,8 +327,8 @@ chem::ApplyArgs apply_args(const chem_surr_s *s, const chem_surr_checks &c)
 {
     chem::ApplyArgs a{};
     a.species = s->mech->view.species;
-    a.W = s->mech->view.W;
-    a.counts = s->counts_dev;
+    a.ncoef = s->coef_dev;
+    a.rw = s->coef_dev + (int64_t)s->E * s->K;
     a.K = s->K;
     a.E = s->E;
     a.two_range = s->mech->view.two_range;
@@ -388,6 +388,7 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
     *out = nullptr;
     const int K = mech->host.K, E = mech->host.E;
     if (K + 2 > kInPad) return fail(CHEM_EUNSUP, "the surrogate takes at most 62 species");
+    if (E > 8) return fail(CHEM_EUNSUP, "the surrogate takes at most 8 elements");
     for (int v : {h1, h2, h3})
         if (v < 64 || v % 64 != 0 || v > 4096)
             return fail(CHEM_EINVAL, "hidden widths must be multiples of 64 in [64, 4096]");
@@ -420,7 +421,7 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
     s->n_pad = off;
     const int64_t nn = 2 * (int64_t)s->nin + 2 * K;
     const size_t bytes = 4 * carve_size<float>(s->n_pad) + 2 * carve_size<bf16_t>(s->n_pad) +
-                         carve_size<double>(nn) + carve_size<double>((int64_t)E * K) +
+                         carve_size<double>(nn) + carve_size<double>((int64_t)(E + 1) * K) +
                          carve_size<int64_t>(8) + carve_size<double>(80);
     if (hipMalloc(&s->block, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -436,16 +437,18 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
     s->wbf = c.take<bf16_t>(s->n_pad);
     s->wfrag = c.take<bf16_t>(s->n_pad);
     s->norm_dev = c.take<double>(nn);
-    s->counts_dev = c.take<double>((int64_t)E * K);
+    s->coef_dev = c.take<double>((int64_t)(E + 1) * K);
     s->scalars = c.take<int64_t>(8);
     s->loss_dev = c.take<double>(80);
     int rc = check_hip(hipMemset(s->block, 0, bytes), "surrogate init");
-    std::vector<double> cnt((size_t)E * K);
+    // decode constants: n_ke / W_k and R / W_k, each one FP64 division here
+    std::vector<double> cnt((size_t)(E + 1) * K);
     for (int e = 0; e < E; e++)
-        for (int k = 0; k < K; k++) cnt[(size_t)e * K + k] = mech->host.counts[k][e];
+        for (int k = 0; k < K; k++) cnt[(size_t)e * K + k] = mech->host.counts[k][e] / mech->W[k];
+    for (int k = 0; k < K; k++) cnt[(size_t)E * K + k] = 8.31446261815324 / mech->W[k];
     if (rc == CHEM_OK)
-        rc = check_hip(hipMemcpy(s->counts_dev, cnt.data(), cnt.size() * sizeof(double), hipMemcpyHostToDevice),
-                       "element table upload");
+        rc = check_hip(hipMemcpy(s->coef_dev, cnt.data(), cnt.size() * sizeof(double), hipMemcpyHostToDevice),
+                       "decode constants upload");
     s->norm.assign((size_t)norm_len(s), 0.0);
     hipSetDevice(prev);
     if (rc != CHEM_OK) {

@@ -2,14 +2,14 @@
 
 GELU(u) = u Phi(u) with Phi(-|u|) = erfc(z) / 2, z = |u| / sqrt(2).  The
 kernels evaluate erfc(z) = t exp(-z^2 + P(t)), t = 1 / (1 + z/2), where P is
-a degree-9 polynomial in t.  P is fitted here in FP64 by least squares on
+a degree-7 polynomial in t.  P is fitted here in FP64 by least squares on
 Chebyshev nodes of t in (0, 1] to ln(erfcx(z) / t) (erfcx(z) = exp(z^2)
 erfc(z), so the target stays finite for large z).  Run to print the
 coefficients and the relative error of an FP32 evaluation of GELU."""
 import numpy as np
 from scipy.special import erfc, erfcx
 
-DEGREE = 9
+DEGREE = 7
 
 
 def fit(deg: int = DEGREE) -> np.ndarray:
