@@ -386,7 +386,8 @@ def run_surrogate(args):
                                f"{n_train} integrator-labelled states for {args.epochs} epochs",
                    "ncells": n, "species": K, "dt": dt},
         "roofline": {"bound": "mfma", "achieved": fwd_flops / (fwd_ms * 1e-3) / 1e12, "peak": 2500.0,
-                     "unit": "TFLOP/s", "frac": fwd_flops / (fwd_ms * 1e-3) / 1e12 / 2500.0, "traffic": None,
+                     "unit": "TFLOP/s", "frac": fwd_flops / (fwd_ms * 1e-3) / 1e12 / 2500.0,
+                     "traffic": traffic_for("surrogate", "mlp_forward_kernel"),
                      "kernel": "mlp_forward_kernel (fused forward, 4 layers)", "kernel_ms": fwd_ms,
                      "rows": int(X.shape[0])},
         "fallback_frac": nfb / n,
