@@ -45,7 +45,7 @@ hipError_t launch_gemm_bf16(const GemmArgs &g, hipStream_t s);
 // Fused inference forward pass: out = W4 h3 + b4 with h_l = GELU(W_l h_(l-1) + b_l),
 // h_0 = the 64-wide input rows.  W[l] holds the [out_l][in_l] BF16 weights in
 // fragment order (launch_swizzle_frag; in_l of layer 0 is 64), b[l] FP32.
-// One block takes 64 rows through all four layers with the activations in
+// One block takes 32 rows through all four layers with the activations in
 // LDS; the result equals the layer-by-layer GEMMs bit for bit.
 struct MlpArgs {
     const bf16_t *X;        // rows x 64

@@ -148,21 +148,23 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
 }
 
 // ---------------------------------------------------------------------------
-// Fused forward pass (inference): 64 rows per block, eight waves; each layer
-// is a 64 x N x K product with A (the activations) from LDS and B (the
-// weights, L2-resident) loaded by each lane straight into its MFMA operand
-// registers.  Wave w owns the 16-column blocks w + 8 j of the layer's output
-// for all four 16-row blocks, so every weight fragment is loaded once per
-// block.  The weights come in fragment order (swizzle_frag_kernel): the
+// Fused forward pass (inference): 32 rows per block, four waves, 50 KB of
+// LDS, so that three blocks share a CU and one block's GELU epilogues overlap
+// another's matrix products; each layer is a 32 x N x K product with A (the
+// activations) from LDS and B (the weights, L2-resident) loaded by each lane
+// straight into its MFMA operand registers.  Wave w owns the 16-column blocks
+// w + 4 j of the layer's output for both 16-row blocks, so every weight
+// fragment is loaded once per block.  The weights come in fragment order (swizzle_frag_kernel): the
 // 16 x 32 operand of column block jb and K step ks is 1 KB at
 // ((jb * K/32 + ks) * 512 + 8 lane), so a wave reads it as one contiguous
 // 16-byte-per-lane load.  The accumulation over K runs in steps of 32 in
 // increasing order, as in gemm_bf16_kernel, and the epilogues are the same,
 // so the result is bitwise that of the GEMMs.
 // ---------------------------------------------------------------------------
-constexpr int kMlpRows = 64, kMlpWaves = 8, kMlpMaxN = 512, kMlpJ = kMlpMaxN / 16 / kMlpWaves;
+constexpr int kMlpRows = 32, kMlpWaves = 4, kMlpMaxN = 512, kMlpJ = kMlpMaxN / 16 / kMlpWaves;
+constexpr int kMlpRB = kMlpRows / 16;
 constexpr int kMlpPad = 8;   // bf16 pad per LDS row: spreads the 16 rows of an A fragment over banks
-constexpr int kMlpDepth = 4; // K steps of weight fragments loaded ahead
+constexpr int kMlpDepth = 2; // K steps of weight fragments loaded ahead
 
 template <int J>
 __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, const bf16_t *__restrict__ Wf, int N,
@@ -172,11 +174,11 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int kk = (lane >> 4) * 8;
     const int nblk = N >> 4, ksteps = K >> 5;
-    floatx4 acc[J][4];
+    floatx4 acc[J][kMlpRB];
 #pragma unroll
     for (int j = 0; j < J; j++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) acc[j][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < kMlpRB; i++) acc[j][i] = floatx4{0.f, 0.f, 0.f, 0.f};
     const bf16_t *wfr[J];
 #pragma unroll
     for (int j = 0; j < J; j++) {
@@ -198,14 +200,14 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
         for (int d = 0; d < kMlpDepth; d++) {
             const int ks = s0 + d;
             if (ks >= ksteps) break;
-            bf16x8 a[4];
+            bf16x8 a[kMlpRB];
 #pragma unroll
-            for (int i = 0; i < 4; i++) __builtin_memcpy(&a[i], arow + i * 16 * ldi + ks * 32, 16);
+            for (int i = 0; i < kMlpRB; i++) __builtin_memcpy(&a[i], arow + i * 16 * ldi + ks * 32, 16);
 #pragma unroll
             for (int j = 0; j < J; j++)
                 if (w + kMlpWaves * j < nblk)
 #pragma unroll
-                    for (int i = 0; i < 4; i++)
+                    for (int i = 0; i < kMlpRB; i++)
                         acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bq[d][j], acc[j][i], 0, 0, 0);
             const int kn = ks + kMlpDepth;
 #pragma unroll
@@ -220,7 +222,7 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
         const int n = jb * 16 + (lane & 15);
         const float bn = bias[n];
 #pragma unroll
-        for (int i = 0; i < 4; i++)
+        for (int i = 0; i < kMlpRB; i++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int m = i * 16 + (lane >> 4) * 4 + r;
@@ -239,10 +241,12 @@ __device__ __forceinline__ void mlp_layer_any(const bf16_t *in, int ldi, int K, 
                                               const float *bias, bf16_t *outs, int lds_out, float *outg,
                                               int64_t ldg, int64_t r0, int64_t rows)
 {
-    if (N <= 128)
+    if (N <= 64)
         mlp_layer<1>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
-    else if (N <= 256)
+    else if (N <= 128)
         mlp_layer<2>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
+    else if (N <= 256)
+        mlp_layer<4>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
     else
         mlp_layer<kMlpJ>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
 }
@@ -261,7 +265,7 @@ __global__ void __launch_bounds__(256) swizzle_frag_kernel(const bf16_t *__restr
     *(uint4 *)(Wf + c * 8) = *(const uint4 *)(W + (int64_t)n * K + k);
 }
 
-__global__ void __launch_bounds__(kMlpRows * kMlpWaves) mlp_forward_kernel(MlpArgs a)
+__global__ void __launch_bounds__(64 * kMlpWaves, 3) mlp_forward_kernel(MlpArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) bf16_t mlp_lds[];
     const int ld0 = (a.out_l[1] > 64 ? a.out_l[1] : 64) + kMlpPad;
@@ -269,7 +273,7 @@ __global__ void __launch_bounds__(kMlpRows * kMlpWaves) mlp_forward_kernel(MlpAr
     bf16_t *buf0 = mlp_lds, *buf1 = mlp_lds + kMlpRows * ld0;
     const int64_t r0 = (int64_t)blockIdx.x * kMlpRows;
     // the block's input rows, zero past the end
-    for (int c = threadIdx.x; c < kMlpRows * 8; c += kMlpRows * kMlpWaves) {
+    for (int c = threadIdx.x; c < kMlpRows * 8; c += 64 * kMlpWaves) {
         const int r = c >> 3, kc = (c & 7) * 8;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (r0 + r < a.rows) v = *(const uint4 *)(a.X + (r0 + r) * 64 + kc);
@@ -738,7 +742,7 @@ hipError_t launch_mlp_forward(const MlpArgs &a, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((a.rows + kMlpRows - 1) / kMlpRows)),
-                       dim3(kMlpRows * kMlpWaves), lds, s, a);
+                       dim3(64 * kMlpWaves), lds, s, a);
     return hipGetLastError();
 }
 

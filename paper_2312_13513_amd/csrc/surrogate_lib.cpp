@@ -22,6 +22,7 @@ namespace {
 
 constexpr int kInPad = 64;            // network input padded for the MFMA K steps
 constexpr int64_t kChunk = 262144;    // rows per inference pass (bounds the activations)
+constexpr int64_t kFusedChunk = 2097152;   // rows per pass of the fused forward (input + output only)
 constexpr double kBeta1 = 0.9, kBeta2 = 0.999, kEps = 1e-8;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -92,6 +93,8 @@ struct chem_surr_s {
     bool act_train = false;
     DevBuf fb;                        // fallback compaction
     int64_t fb_cap = 0;
+    DevBuf io;                        // encoded rows and outputs of the fused inference pass
+    int64_t io_rows = 0;
 };
 
 namespace {
@@ -468,6 +471,7 @@ void chem_free_surrogate(chem_surr s)
     hipSetDevice(s->device);
     s->act.release();
     s->fb.release();
+    s->io.release();
     if (s->block) hipFree(s->block);
     hipSetDevice(prev);
     delete s;
@@ -645,25 +649,47 @@ int chem_surrogate_infer(chem_surr s, double *T, const double *p, double *Y, int
     chem_surrogate_default_checks(&c);
     if (checks) c = *checks;
     const int K = s->K;
-    const int64_t rows = n < kChunk ? n : kChunk;
-    rc = ensure_acts(s, rows, false);
-    if (rc != CHEM_OK) return rc;
+    // the fused forward needs only the encoded rows and the outputs, so it
+    // takes larger passes; the layered GEMMs keep every activation
+    const bool fused = fused_ok(s);
+    const int64_t chunk = fused ? kFusedChunk : kChunk;
+    const int64_t rows = n < chunk ? n : chunk;
+    bf16_t *Xc = nullptr;
+    float *OUTc = nullptr;
+    Acts a{};
+    if (fused) {
+        if (rows > s->io_rows) {
+            rc = s->io.grow(carve_size<bf16_t>(rows * kInPad) + carve_size<float>(rows * s->nout_pad));
+            if (rc != CHEM_OK) return rc;
+            s->io_rows = rows;
+        }
+        Carver ic{(char *)s->io.p};
+        Xc = ic.take<bf16_t>(s->io_rows * kInPad);
+        OUTc = ic.take<float>(s->io_rows * s->nout_pad);
+    } else {
+        rc = ensure_acts(s, rows, false);
+        if (rc != CHEM_OK) return rc;
+        a = carve_acts(s);
+        Xc = a.X;
+        OUTc = a.OUT;
+    }
     Fallback fb;
     rc = ensure_fb(s, n, fb);
     if (rc != CHEM_OK) return rc;
-    Acts a = carve_acts(s);
     float *noU[3] = {nullptr, nullptr, nullptr};
     hipStream_t st = (hipStream_t)stream;
     int64_t *count = fallback_count ? fallback_count : s->scalars;
     rc = check_hip(chem::launch_zero_i64(count, 1, st), "zero");
     if (rc != CHEM_OK) return rc;
     const chem::ApplyArgs aa = apply_args(s, c);
-    for (int64_t r0 = 0; r0 < n; r0 += kChunk) {
-        const int rr = (int)(n - r0 < kChunk ? n - r0 : kChunk);
-        hipError_t e = chem::launch_encode(T + r0, p + r0, Y + r0, ldY, rr, K, kInPad, s->norm_dev, a.X, st);
-        if (e == hipSuccess) e = forward(s, a.X, rr, a.H, noU, a.OUT, s->nout_pad, st);
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+        const int rr = (int)(n - r0 < chunk ? n - r0 : chunk);
+        hipError_t e = chem::launch_encode(T + r0, p + r0, Y + r0, ldY, rr, K, kInPad, s->norm_dev, Xc, st);
         if (e == hipSuccess)
-            e = chem::launch_apply(aa, T + r0, p + r0, Y + r0, ldY, rr, r0, a.OUT, s->nout_pad,
+            e = fused ? forward_fused(s, Xc, rr, OUTc, s->nout_pad, st)
+                      : forward(s, Xc, rr, a.H, noU, OUTc, s->nout_pad, st, true);
+        if (e == hipSuccess)
+            e = chem::launch_apply(aa, T + r0, p + r0, Y + r0, ldY, rr, r0, OUTc, s->nout_pad,
                                    mask ? mask + r0 : nullptr, status ? status + r0 : nullptr, fb.list,
                                    count, st);
         if (e != hipSuccess) return check_hip(e, "surrogate pass");
