@@ -292,7 +292,10 @@ __global__ void __launch_bounds__(64 * kMlpWaves, 3) mlp_forward_kernel(MlpArgs 
 // ---------------------------------------------------------------------------
 // encoding
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double boxcox(double y) { return (pow(fmax(y, 0.0), 0.1) - 1.0) / 0.1; }
+// Box-Cox with lambda 0.1; y^0.1 as exp2(0.1 log2 y) (y = 0 gives exp2(-inf) =
+// 0, as the power), a few ulp of FP64 from the correctly rounded power, far
+// below the BF16 rounding of the feature
+__device__ __forceinline__ double boxcox(double y) { return (exp2(0.1 * log2(fmax(y, 0.0))) - 1.0) / 0.1; }
 
 __global__ void __launch_bounds__(256) encode_kernel(const double *__restrict__ T,
                                                      const double *__restrict__ p,
@@ -438,7 +441,7 @@ __device__ __forceinline__ void mix_h_cp(const ApplyArgs &a, double T, const dou
 // prediction and the input enthalpy are accumulated in the same pass, so
 // only the predicted mass fractions stay in registers.
 template <int KM, int KE>
-__global__ void __launch_bounds__(256) apply_kernel(ApplyArgs a, double *__restrict__ T,
+__global__ void __launch_bounds__(256, 3) apply_kernel(ApplyArgs a, double *__restrict__ T,
                                                     const double *__restrict__ p,
                                                     double *__restrict__ Y, int64_t ldY, int64_t n,
                                                     int64_t base, const float *__restrict__ out,
@@ -792,6 +795,8 @@ hipError_t launch_apply(const ApplyArgs &a, double *T, const double *p, double *
         CHEM_APPLY(16);
     else if (a.K <= 32)
         CHEM_APPLY(32);
+    else if (a.K <= 40)
+        CHEM_APPLY(40);
     else if (a.K <= 48)
         CHEM_APPLY(48);
     else if (a.K <= kMaxSurrSpecies)
