@@ -152,6 +152,38 @@ def compare_flips_to_oracle_alternatives(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, T
     return flip
 
 
+def compare_cell_envelope(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, To, Yo, so, co, factor=4.0, per_cell=True):
+    """For ill-conditioned workloads (hundreds of steps per cell, where
+    round-off in any implementation moves the result beyond the plain bars
+    even without a flipped decision): every cell stays within `factor` times
+    the larger of the plain bar and the oracle's own spread under one- and
+    two-ulp perturbations of T and rtol — the spread of that cell, or with
+    per_cell=False the largest over all cells (the reading for round-off
+    sensitive cells)."""
+    assert np.array_equal(sg, so)
+    sT = np.zeros(Tg.size)
+    sY = np.zeros(Tg.size)
+    for q, k in ((q, k) for q in ("T", "rtol") for k in (1, 2)):
+        f = 1.0 + k * 2.0 ** -52
+        Ta, Ya = om.integrate(T * (f if q == "T" else 1.0), p, Y, dt, rtol=1e-8 * (f if q == "rtol" else 1.0))[:2]
+        sT = np.maximum(sT, np.abs(Ta - To))
+        sY = np.maximum(sY, np.abs(Ya - Yo).max(axis=0))
+    dT = np.abs(Tg - To)
+    dY = np.abs(Yg - Yo).max(axis=0)
+    if not per_cell:
+        sT = np.full(Tg.size, sT.max())
+        sY = np.full(Tg.size, sY.max())
+    okT = dT <= factor * np.maximum(sT, DT_TOL)
+    okY = dY <= factor * np.maximum(sY, DY_TOL)
+    flips = np.where((cg != co).any(axis=1))[0]
+    _say(f"[{tag}] n={Tg.size} max|dT|={dT.max():.3e} K max|dY|={dY.max():.3e}; oracle's own ulp spread up to "
+         f"{sT.max():.3e} K / {sY.max():.3e}; cells within the plain bars {np.sum((dT < DT_TOL) & (dY < DY_TOL))}; "
+         f"decision flips {flips.size}")
+    assert okT.all(), f"cells beyond the envelope (T): {np.where(~okT)[0][:10]}"
+    assert okY.all(), f"cells beyond the envelope (Y): {np.where(~okY)[0][:10]}"
+    return flips
+
+
 def compare_conditioned(tag, Tg, Yg, sg, cg, To, Yo, so, co, envelope, factor=4.0):
     """Bars for workloads whose decisions are round-off sensitive: cells whose
     step counts agree with the oracle meet the plain bars (1e-6 K, 1e-10);

@@ -9,7 +9,7 @@ FP32 Jacobian/LU mode are covered."""
 import numpy as np
 import pytest
 
-from test_gpu_integrate import compare, compare_flips_to_oracle_alternatives, run_gpu, _say
+from test_gpu_integrate import compare, compare_cell_envelope, compare_flips_to_oracle_alternatives, run_gpu, _say
 
 pytestmark = pytest.mark.gpu
 
@@ -138,4 +138,33 @@ def test_tile_rejects_large_mechanism(torch, mech_dir):
     Y = torch.full((35, 4), 1.0 / 35, dtype=torch.float64, device="cuda:0")
     with pytest.raises(chem.ChemError, match="tile"):
         g.integrate(T, T, Y, 1e-6, opts=_opts(2))
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def m15_path(tmp_path_factory):
+    """A 15-species / 80-reaction synthetic mechanism: N = 16 fills a tile, and
+    its tables plus the reaction scratch of four cells exceed what the tile
+    kernel stages in LDS, so the kernel reads them from global memory."""
+    from chemgen.mechanism import make_mechanism
+    p = tmp_path_factory.mktemp("m15") / "M15.mech"
+    make_mechanism(seed=11, K=15, R=80, E=3).write(str(p))
+    return p
+
+
+def test_tile_full_width_unstaged_tables(torch, m15_path, oracle_lib):
+    from chemgen.fields import cells4096
+    from chemgen.mechanism import read_mechanism
+    from paper_2312_13513_amd import chem
+    mpy = read_mechanism(str(m15_path))
+    f = cells4096(mpy, n=515, seed=31)
+    g = chem.Mechanism(str(m15_path), 0)
+    om = oracle_lib.OracleMech(str(m15_path))
+    tile = run_gpu(torch, g, f.T, f.p, f.Y, f.dt, opts=_opts(2))
+    wave = run_gpu(torch, g, f.T, f.p, f.Y, f.dt, opts=_opts(1))
+    To, Yo, so, co, _ = om.integrate(f.T, f.p, f.Y, f.dt)
+    # random states of a random mechanism, up to 345 steps per cell: the
+    # oracle's own ulp spread is the bar, cell by cell
+    compare_cell_envelope("tile-M15", om, f.T, f.p, f.Y, f.dt, *tile, To, Yo, so, co)
+    assert np.array_equal(tile[2], wave[2])
     g.close()

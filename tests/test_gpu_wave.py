@@ -5,7 +5,7 @@ Jacobian/LU mode, whose error against the FP64 oracle is stated."""
 import numpy as np
 import pytest
 
-from test_gpu_integrate import compare, compare_conditioned, oracle_envelope, run_gpu, _say
+from test_gpu_integrate import compare, compare_cell_envelope, compare_conditioned, oracle_envelope, run_gpu, _say
 
 pytestmark = pytest.mark.gpu
 
@@ -108,3 +108,24 @@ def test_thread_schedule_rejects_large_mechanism(torch, gm35):
     assert e.value.code == -5
     with pytest.raises(chem.ChemError):
         gm35.integrate(T, T, Y, 1e-6, opts=_opts(0, 1))
+
+
+def test_wave_global_reaction_scratch(torch, tmp_path, oracle_lib):
+    """900 reactions: the reaction scratch of a wave (7 R doubles) no longer
+    fits the LDS budget, so the kernel keeps it in a global slice per wave."""
+    from chemgen.fields import cells4096
+    from chemgen.mechanism import make_mechanism
+    from paper_2312_13513_amd import chem
+    p = tmp_path / "M40.mech"
+    mpy = make_mechanism(seed=11, K=40, R=900, E=4)
+    mpy.write(str(p))
+    f = cells4096(mpy, n=130, seed=32)
+    g = chem.Mechanism(str(p), 0)
+    om = oracle_lib.OracleMech(str(p))
+    Tg, Yg, sg, cg = run_gpu(torch, g, f.T, f.p, f.Y, f.dt, opts=_opts(1))
+    To, Yo, so, co, _ = om.integrate(f.T, f.p, f.Y, f.dt)
+    # ~900 steps per cell, nearly every cell has a round-off decided decision:
+    # the bar is the oracle's own ulp spread over the field (as for the zones)
+    compare_cell_envelope("wave-M40-R900", om, f.T, f.p, f.Y, f.dt, Tg, Yg, sg, cg, To, Yo, so, co,
+                          per_cell=False)
+    g.close()
