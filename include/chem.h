@@ -128,6 +128,31 @@ int chem_integrate_indexed(chem_mech mech, double *T, const double *p, double *Y
                            const chem_opts *opts, int32_t *status, int32_t *counters,
                            void *hip_stream);
 
+/* Totals of one integration (or inference) call, reduced on the device from
+ * its per-cell outputs. */
+typedef struct {
+    int64_t cells;            /* cells reduced (n) */
+    int64_t steps_total;      /* accepted steps, summed over cells */
+    int64_t rejects;          /* error-test plus Newton convergence failures */
+    int64_t newton_iters;     /* Newton iterations */
+    int64_t jac_evals;        /* Jacobian evaluations (= LU factorisations) */
+    int64_t rhs_evals;        /* right-hand-side evaluations */
+    int64_t fallback_cells;   /* *fallback_count when given, else 0 */
+    int32_t steps_max;        /* largest per-cell step count */
+    int32_t reserved;
+    int64_t status_count[8];  /* cells per status code 0..7 (CHEM_CELL_*) */
+} chem_stats;
+
+/* Reduce the per-cell outputs of a call: status[n] (device, may be NULL)
+ * and counters[6][n] (device, layout of chem_integrate; may be NULL) into
+ * *out (host), plus the fallback count of chem_surrogate_infer (device, may
+ * be NULL).  A diagnostics call: allocates a small device buffer, enqueues
+ * the reduction on the stream, synchronises the stream and copies the
+ * totals back.  Integer sums, so the result does not depend on the order of
+ * the reduction.  A status outside 0..7 is counted in status_count[7]. */
+int chem_get_stats(const int32_t *status, const int32_t *counters, int64_t n, const int64_t *fallback_count,
+                   chem_stats *out, void *hip_stream);
+
 /* Longest-processing-time-first order: order[0..n) (device) receives the
  * indices 0..n-1 sorted by descending cost[i] (device int32, e.g. the step
  * counts of the previous flow step), ties in index order.  A planning call:

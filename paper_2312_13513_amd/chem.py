@@ -31,6 +31,13 @@ class chem_opts(C.Structure):
                 ("jac_batch", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
+class chem_stats(C.Structure):
+    _fields_ = [("cells", C.c_int64), ("steps_total", C.c_int64), ("rejects", C.c_int64),
+                ("newton_iters", C.c_int64), ("jac_evals", C.c_int64), ("rhs_evals", C.c_int64),
+                ("fallback_cells", C.c_int64), ("steps_max", C.c_int32), ("reserved", C.c_int32),
+                ("status_count", C.c_int64 * 8)]
+
+
 class chem_surr_checks(C.Structure):
     _fields_ = [("elem_tol", C.c_double), ("sum_tol", C.c_double), ("neg_tol", C.c_double),
                 ("T_out_min", C.c_double), ("T_out_max", C.c_double), ("T_in_min", C.c_double),
@@ -57,6 +64,7 @@ def _load():
     L.chem_integrate_indexed.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, C.c_double, C.POINTER(chem_opts),
                                          vp, vp, vp]
     L.chem_lpt_order.argtypes = [dp, i64, dp, vp]
+    L.chem_get_stats.argtypes = [vp, vp, i64, vp, C.POINTER(chem_stats), vp]
     L.chem_autotune.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), C.c_int32,
                                 C.POINTER(chem_opts), i32p, C.POINTER(C.c_double), vp]
     fp, dblp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int64)
@@ -93,7 +101,7 @@ _lib = _load()
 #: Symbols that include/chem.h declares (checked by the ABI test).
 EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_mechanism_info", "chem_mechanism_variant", "chem_integrate", "chem_eval_rhs", "chem_eval_jacobian",
-            "chem_last_error", "chem_integrate_indexed", "chem_lpt_order", "chem_autotune",
+            "chem_last_error", "chem_integrate_indexed", "chem_lpt_order", "chem_autotune", "chem_get_stats",
             "chem_surrogate_default_checks", "chem_surrogate_create",
             "chem_free_surrogate", "chem_surrogate_info", "chem_surrogate_set_params",
             "chem_surrogate_get_params", "chem_surrogate_set_norm", "chem_surrogate_get_norm",
@@ -226,6 +234,19 @@ class Mechanism:
 def chem_lpt_order(cost, order, stream=None) -> None:
     """order (int32 GPU tensor) <- indices sorted by descending cost (int32 GPU tensor)."""
     _check(_lib.chem_lpt_order(_ptr(cost), cost.shape[0], _ptr(order), _stream(stream)))
+
+
+def chem_get_stats(status=None, counters=None, n=None, fallback_count=None, stream=None) -> dict:
+    """Totals of one call's per-cell outputs (status: int32 (n,), counters:
+    int32 (6*n,) GPU tensors, either may be None; fallback_count: int64 (1,))."""
+    if n is None:
+        n = status.shape[0] if status is not None else (counters.shape[0] // 6 if counters is not None else 0)
+    out = chem_stats()
+    _check(_lib.chem_get_stats(_ptr(status), _ptr(counters), int(n), _ptr(fallback_count), C.byref(out),
+                               _stream(stream)))
+    d = {k: getattr(out, k) for k, _ in chem_stats._fields_ if k not in ("reserved", "status_count")}
+    d["status_count"] = list(out.status_count)
+    return d
 
 
 # --------------------------------------------------------------------------- surrogate

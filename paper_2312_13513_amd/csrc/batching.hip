@@ -3,6 +3,7 @@
 // autotuner that times the candidate schedules on a sample of the cells.
 
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include <hipcub/hipcub.hpp>
@@ -50,9 +51,96 @@ int lpt_order(const int32_t *cost, int64_t n, int32_t *order, hipStream_t st)
     return check_hip(e, "LPT order");
 }
 
+// Totals of per-cell outputs: a grid-stride pass per thread, a block sum in
+// LDS, one set of 64-bit atomics per block.  acc: 6 counter sums, steps_max,
+// 8 status counts.
+__global__ void __launch_bounds__(256) stats_kernel(const int32_t *__restrict__ status,
+                                                    const int32_t *__restrict__ counters, int64_t n,
+                                                    unsigned long long *__restrict__ acc)
+{
+    __shared__ unsigned long long part[256][15];
+    unsigned long long v[15];
+#pragma unroll
+    for (int j = 0; j < 15; j++) v[j] = 0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (counters) {
+#pragma unroll
+            for (int c = 0; c < 6; c++) v[c] += (unsigned long long)(unsigned)counters[c * n + i];
+            const unsigned long long st = (unsigned)counters[i];
+            v[6] = st > v[6] ? st : v[6];
+        }
+        if (status) {
+            const int s = status[i];
+            v[7 + ((s >= 0 && s < 8) ? s : 7)] += 1ull;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 15; j++) part[threadIdx.x][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x < 15) {
+        const int j = threadIdx.x;
+        unsigned long long t = 0ull;
+        for (int k = 0; k < 256; k++) t = j == 6 ? (part[k][j] > t ? part[k][j] : t) : t + part[k][j];
+        if (j == 6)
+            atomicMax(&acc[j], t);
+        else
+            atomicAdd(&acc[j], t);
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
 }  // namespace
 
 extern "C" {
+
+int chem_get_stats(const int32_t *status, const int32_t *counters, int64_t n, const int64_t *fallback_count,
+                   chem_stats *out, void *stream)
+{
+    if (!out) return fail(CHEM_EINVAL, "out is NULL");
+    if (n < 0) return fail(CHEM_EINVAL, "n must be >= 0");
+    if ((status && !is_device_ptr(status)) || (counters && !is_device_ptr(counters)) ||
+        (fallback_count && !is_device_ptr(fallback_count)))
+        return fail(CHEM_EINVAL, "status, counters and fallback_count must be device pointers or NULL");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long *acc = nullptr;
+    if (hipMalloc((void **)&acc, 16 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CHEM_ENOMEM, "stats buffer allocation failed");
+    }
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, acc, 16);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && n > 0 && (status || counters)) {
+        const int64_t want = (n + 255) / 256;
+        const unsigned blocks = (unsigned)(want < 1024 ? want : 1024);
+        hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(256), 0, st, status, counters, n, acc);
+        e = hipGetLastError();
+    }
+    unsigned long long h[16] = {0};
+    int64_t fb = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(h, acc, 15 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && fallback_count)
+        e = hipMemcpyAsync(&fb, fallback_count, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(acc);
+    if (e != hipSuccess) return check_hip(e, "stats");
+    chem_stats r;
+    std::memset(&r, 0, sizeof(r));
+    r.cells = n;
+    r.steps_total = (int64_t)h[0];
+    r.rhs_evals = (int64_t)h[1];
+    r.jac_evals = (int64_t)h[2];
+    r.newton_iters = (int64_t)h[3];
+    r.rejects = (int64_t)(h[4] + h[5]);
+    r.steps_max = (int32_t)h[6];
+    for (int s = 0; s < 8; s++) r.status_count[s] = (int64_t)h[7 + s];
+    r.fallback_cells = fb;
+    *out = r;
+    return CHEM_OK;
+}
 
 int chem_integrate_indexed(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t ncells,
                            const int32_t *cell_idx, int64_t nidx, double dt, const chem_opts *opts,

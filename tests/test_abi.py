@@ -67,3 +67,13 @@ def test_null_handle_is_rejected():
     rc = chem.lib().chem_integrate(None, None, None, None, 0, 10, 1e-6, None, None, None, None)
     assert rc == -1
     assert b"NULL" in chem.lib().chem_last_error()
+
+
+def test_stats_argument_checks():
+    """chem_get_stats rejects a NULL result and a negative size before any
+    device work."""
+    from paper_2312_13513_amd import chem
+    out = chem.chem_stats()
+    lib = chem.lib()
+    assert lib.chem_get_stats(None, None, 4, None, None, None) == -1
+    assert lib.chem_get_stats(None, None, -1, None, C.byref(out), None) == -1

@@ -109,3 +109,36 @@ def test_autotune_choice_meets_parity(torch, m9, field, om9):
     dY = np.abs(Y.cpu().numpy() - Yo).max()
     _say(f"[autotune] tuned run vs oracle: max|dT| {dT:.3e} K max|dY| {dY:.3e}")
     assert dT < DT_TOL and dY < DY_TOL
+
+
+def test_stats_totals_match_the_per_cell_outputs(torch, m9, field):
+    """chem_get_stats against numpy sums of the same per-cell arrays, with
+    failed cells (a NaN state, a step cap) among them."""
+    from paper_2312_13513_amd import chem
+    f = field
+    n = 1500
+    T = f.T[:n].copy()
+    T[3] = float("nan")
+    o = chem.chem_default_opts()
+    o.max_steps = 3
+    Tg, Yg, p = _dev(torch, T), _dev(torch, f.Y[:, :n]), _dev(torch, f.p[:n])
+    st = torch.full((n,), -1, dtype=torch.int32, device="cuda:0")
+    cn = torch.zeros(6 * n, dtype=torch.int32, device="cuda:0")
+    m9.integrate(Tg, p, Yg, f.dt, opts=o, status=st, counters=cn)
+    fb = torch.tensor([17], dtype=torch.int64, device="cuda:0")
+    s = chem.chem_get_stats(st, cn, n, fallback_count=fb)
+    sn, c = st.cpu().numpy(), cn.cpu().numpy().reshape(6, n)
+    _say(f"[stats] {s}")
+    assert s["cells"] == n and s["fallback_cells"] == 17
+    assert s["steps_total"] == c[0].sum() and s["rhs_evals"] == c[1].sum()
+    assert s["jac_evals"] == c[2].sum() and s["newton_iters"] == c[3].sum()
+    assert s["rejects"] == c[4].sum() + c[5].sum() and s["steps_max"] == c[0].max()
+    assert s["status_count"] == [int(np.sum(sn == k)) for k in range(8)]
+    assert s["status_count"][4] >= 1 and s["status_count"][1] >= 1
+    # status only, counters only, and no cells
+    s2 = chem.chem_get_stats(st, None, n)
+    assert s2["status_count"] == s["status_count"] and s2["steps_total"] == 0
+    s3 = chem.chem_get_stats(None, cn, n)
+    assert s3["steps_total"] == s["steps_total"] and sum(s3["status_count"]) == 0
+    s4 = chem.chem_get_stats(st, cn, 0)
+    assert s4["cells"] == 0 and s4["steps_total"] == 0 and sum(s4["status_count"]) == 0
