@@ -23,7 +23,10 @@ Other workloads (``--workload``):
              timed inference steps against the plain integrator on the same
              cells and the oracle on a sample.  --field flame256 serves the
              256^3 field (16,777,216 cells) and --graph replays the captured
-             step; the plain integrator then runs on a seeded sample.
+             step; the plain integrator then runs on a seeded sample.  With
+             --evolve the timed steps advance the field (no restore inside the
+             step) and the drift against the plain integrator over the same
+             steps is reported on a seeded sample of cells.
 """
 from __future__ import annotations
 
@@ -160,6 +163,16 @@ def run_integrator(args, workload: str):
                 "35-species/200-reaction mechanism, FP32 Jacobian/LU with FP64 residuals and state")
     mpy, path = mech_file(mname)
     field = make(mpy)
+    if args.shuffle:
+        # the same cells in a seeded random order: no spatial clustering of
+        # the stiff zone (the load-balance contrast to the clustered field)
+        perm = np.random.default_rng(17).permutation(field.n)
+        field.T, field.p, field.Y = field.T[perm], field.p[perm], np.ascontiguousarray(field.Y[:, perm])
+        if field.zone is not None:
+            field.zone = field.zone[perm]
+        if field.c is not None:
+            field.c = field.c[perm]
+        desc += "; cells in a seeded random order"
     dev = torch.device("cuda:0")
     mech = chem.Mechanism(path, 0)
     n, K, R = field.n, mpy.K, mpy.R
@@ -307,9 +320,12 @@ def run_surrogate(args):
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
+    evolve = args.evolve
+
     def step(ev=None):
-        T.copy_(T0)
-        Y.copy_(Y0)
+        if not evolve:
+            T.copy_(T0)
+            Y.copy_(Y0)
         if ev is not None:
             ev[0].record(stream)
         surr.infer(T, p0, Y, dt, mask=mask, fallback_count=cnt, stream=stream)
@@ -328,13 +344,17 @@ def run_surrogate(args):
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.stream(side):
             with torch.cuda.graph(graph, stream=side):
-                T.copy_(T0)
-                Y.copy_(Y0)
+                if not evolve:
+                    T.copy_(T0)
+                    Y.copy_(Y0)
                 surr.infer(T, p0, Y, dt, mask=mask, fallback_count=cnt, stream=side)
         torch.cuda.synchronize()
         graph.replay()
     torch.cuda.synchronize()
+    if evolve:
+        T_start, Y_start = T.clone(), Y.clone()
     t0 = time.perf_counter()
+    fb_trace = []
     for k in range(args.steps):
         if graph is not None:
             events[k][0].record(stream)
@@ -342,10 +362,35 @@ def run_surrogate(args):
             events[k][1].record(stream)
         else:
             step(events[k])
+        if evolve and (k % 10 == 9 or k == args.steps - 1):
+            # an evolving field changes its fallback set: report it as it goes
+            fb_trace.append(int(cnt.item()))
+            progress(f"step {k + 1}: {fb_trace[-1]} fallback cells, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     progress(f"{args.steps} timed surrogate steps: {wall / args.steps * 1e3:.2f} ms per step")
+    drift = None
+    if evolve:
+        # the plain integrator over the same flow steps from the same start,
+        # on a seeded sample of the cells (cells are independent)
+        from chemgen.fields import seeded_sample
+        didx = seeded_sample(n, min(args.drift_cells, n), seed=13)
+        di = torch.tensor(didx, dtype=torch.int64, device=dev)
+        Td, Yd, pd = T_start[di].clone(), Y_start[:, di].contiguous(), p0[di].contiguous()
+        for _ in range(args.steps):
+            mech.integrate(Td, pd, Yd, dt)
+        torch.cuda.synchronize()
+        drift = {"steps": args.steps, "cells": int(didx.size), "fallback_cells_every_10_steps": fb_trace,
+                 "max_dT": float((T[di] - Td).abs().max().item()),
+                 "max_dY": float((Y[:, di] - Yd).abs().max().item()),
+                 "mean_abs_dT": float((T[di] - Td).abs().mean().item())}
+        progress(f"drift after {args.steps} steps on {didx.size} cells: max|dT| {drift['max_dT']:.3f} K")
+        # one step from the pristine field for the single-step accuracy below
+        T.copy_(T0)
+        Y.copy_(Y0)
+        surr.infer(T, p0, Y, dt, mask=mask, fallback_count=cnt, stream=stream)
+        torch.cuda.synchronize()
     Ts_, Ys_ = T.cpu().numpy(), Y.cpu().numpy()
     nfb = int(cnt.item())
     # forward pass alone: algorithmic MFMA flops over its time
@@ -397,6 +442,8 @@ def run_surrogate(args):
         "speedup_vs_plain_gpu": (n * args.steps / wall) / (n_plain / plain_s),
         "max_dT_vs_plain_gpu": float(np.abs(Ts_[pidx] - Tp_).max()),
         "graph": bool(args.graph),
+        "evolving_state": bool(evolve),
+        "drift": drift,
         "train": {"samples": n_train, "epochs": args.epochs, "loss_first": float(losses[0]),
                   "loss_last": float(losses[-1]), "label_s": log["label_s"], "train_s": log["train_s"]},
     }
@@ -431,6 +478,12 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--field", default="flame256x128x128", choices=("flame256x128x128", "flame256"))
     ap.add_argument("--graph", action="store_true", help="surrogate: replay the step as one captured HIP graph")
+    ap.add_argument("--evolve", action="store_true",
+                    help="surrogate: timed steps advance the field (no restore); the drift against the plain "
+                         "integrator over the same steps is reported on a seeded sample")
+    ap.add_argument("--drift-cells", type=int, default=16384, help="surrogate --evolve: cells of the drift check")
+    ap.add_argument("--shuffle", action="store_true",
+                    help="integrator workloads: the field's cells in a seeded random order")
     ap.add_argument("--plain-cells", type=int, default=4194304,
                     help="surrogate: cells of the plain-integrator comparison (a seeded sample when fewer)")
     ap.add_argument("--copy-calibration", action="store_true",
