@@ -145,6 +145,21 @@ def time_oracle(path, field, target_s: float, max_cells: int):
     return idx, out, reps * idx.size / total, used, reps, total
 
 
+def time_oracle_one_thread(path, field, target_s: float, max_cells: int):
+    """The oracle on one host thread (a per-core rate), a seeded sample."""
+    import oracle
+    from chemgen.fields import seeded_sample
+    om = oracle.OracleMech(path)
+    idx = seeded_sample(field.n, min(max_cells, field.n), seed=6)
+    cells, total = 0, 0.0
+    while total < target_s or cells == 0:
+        t1 = time.perf_counter()
+        om.integrate(field.T[idx], field.p[idx], field.Y[:, idx], field.dt, nthreads=1)
+        total += time.perf_counter() - t1
+        cells += idx.size
+    return cells / total, int(idx.size), total
+
+
 def run_integrator(args, workload: str):
     import torch
 
@@ -255,6 +270,9 @@ def run_integrator(args, workload: str):
         result["max_dT_vs_oracle"] = float(np.abs(Tg[idx] - To).max())
         result["max_dY_vs_oracle"] = float(np.abs(Yg[:, idx] - Yo).max())
         result["steps_equal_frac"] = float(np.mean(cnt[0][idx] == co[:, 0]))
+        r1, m1, t1 = time_oracle_one_thread(path, field, min(3.0, args.cpu_seconds), 4096 if mname == "M9" else 256)
+        result["cpu_baseline"]["one_thread"] = {"value": r1, "unit": "cell-steps/s",
+                                                "sample": f"{m1} cells (seeded sample), {t1:.2f} s on 1 thread"}
     mech.close()
     return result
 
