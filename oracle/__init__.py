@@ -63,9 +63,9 @@ def lib():
         L.om_bdf_coeffs.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp]
         L.om_integrate.restype = C.c_int
         L.om_integrate.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, C.c_int64, C.c_double,
-                                   C.c_double, C.c_double, C.c_int, C.c_int, _ip_opt, _ip_opt]
+                                   C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _ip_opt, _ip_opt]
         L.om_bdf_user.argtypes = [C.c_int, USER_F, USER_F, C.c_void_p, _dp, C.c_double, C.c_double,
-                                  C.c_double, C.c_int, _ip]
+                                  C.c_double, C.c_int, C.c_int, _ip]
         L.om_bdf_prescribed.argtypes = [C.c_int, USER_F, USER_F, C.c_void_p, C.c_int, C.c_double,
                                         _dp, _dp, C.c_int, _dp]
         L.om_rk4.argtypes = [C.c_void_p, C.c_double, _dp, C.c_double, C.c_int64]
@@ -137,8 +137,9 @@ class OracleMech:
 
     # -- batch integration -------------------------------------------------
     def integrate(self, T, p, Y, dt: float, rtol: float = 1e-8, atol: float = 1e-12,
-                  max_steps: int = 20000, nthreads: int = 0):
-        """Integrate cells over [0, dt].  Returns (T, Y, status, counters, threads)."""
+                  max_steps: int = 20000, nthreads: int = 0, qmax: int = 5):
+        """Integrate cells over [0, dt] with orders up to qmax.  Returns (T, Y,
+        status, counters, threads)."""
         T = np.array(T, dtype=np.float64)
         p = np.ascontiguousarray(p, dtype=np.float64)
         Y = np.array(Y, dtype=np.float64, order="C")
@@ -146,7 +147,8 @@ class OracleMech:
         status = np.zeros(n, dtype=np.int32)
         counters = np.zeros((n, 6), dtype=np.int32)
         used = lib().om_integrate(self.h, n, T, p, Y, Y.shape[1], float(dt), float(rtol), float(atol),
-                                  int(max_steps), int(nthreads), status.ctypes.data, counters.ctypes.data)
+                                  int(max_steps), int(qmax), int(nthreads), status.ctypes.data,
+                                  counters.ctypes.data)
         return T, Y, status, counters, used
 
 
@@ -181,8 +183,8 @@ def _wrap_user(N, fn):
     return USER_F(cb)
 
 
-def bdf_user(f, jac, y0, t_end: float, rtol=1e-8, atol=1e-12, max_steps=100000):
-    """Controlled BDF integration of a user ODE (pins of the integrator)."""
+def bdf_user(f, jac, y0, t_end: float, rtol=1e-8, atol=1e-12, max_steps=100000, qmax=5):
+    """Controlled BDF integration of a user ODE, orders up to qmax (pins of the integrator)."""
     y = np.array(y0, dtype=np.float64)
     N = y.size
     f.__out_size__ = N
@@ -192,7 +194,8 @@ def bdf_user(f, jac, y0, t_end: float, rtol=1e-8, atol=1e-12, max_steps=100000):
     cj_fn.__out_size__ = N * N
     cj = _wrap_user(N, cj_fn)
     counters = np.zeros(6, dtype=np.int32)
-    st = lib().om_bdf_user(N, cf, cj, None, y, float(t_end), float(rtol), float(atol), int(max_steps), counters)
+    st = lib().om_bdf_user(N, cf, cj, None, y, float(t_end), float(rtol), float(atol), int(max_steps), int(qmax),
+                           counters)
     return y, st, counters
 
 

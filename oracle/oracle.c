@@ -557,6 +557,7 @@ typedef struct {
     om_f_fn f;
     om_j_fn jac;
     void *ctx;
+    int qmax;            /* highest order the step selection may raise to (1..BDF_QMAX) */
 } om_problem;
 
 /* Controlled integration of y from t = 0 to t_end.  On failure y is restored
@@ -783,7 +784,7 @@ static int bdf_integrate(const om_problem *P, double *y, double t_end, double rt
                     double Em = wrms(N, z[q], w) * prod / l1;
                     eta_m = 1.0 / (pow(BDF_BIAS_QM1 * Em, 1.0 / q) + BDF_ADDON);
                 }
-                if (q < BDF_QMAX && ehat_valid) {
+                if (q < P->qmax && ehat_valid) {
                     double rr = pow(h_done / ehat_h, q + 1);
                     for (int i = 0; i < N; i++) del[i] = ehat_new[i] - ehat[i] * rr;
                     double prod = 1.0, l1 = 0.0;
@@ -878,10 +879,11 @@ static int chem_j(void *ctx, double t, const double *y, double *J)
 
 /* Integrate n cells over [0, dt].  T (n), p (n), Y (K rows of stride ldY) are
  * updated in place.  status (n) and counters (n x 6: nst nfe nje nni netf ncfn)
- * may be NULL.  nthreads <= 0 uses every available thread.  Returns the number
- * of threads used. */
+ * may be NULL.  qmax caps the order (1..5, anything else means 5: the
+ * maximum-order option of the BDF family, Section 2's CVODE).  nthreads <= 0
+ * uses every available thread.  Returns the number of threads used. */
 int om_integrate(void *h, int64_t n, double *T, const double *p, double *Y, int64_t ldY, double dt,
-                 double rtol, double atol, int max_steps, int nthreads, int32_t *status,
+                 double rtol, double atol, int max_steps, int qmax, int nthreads, int32_t *status,
                  int32_t *counters)
 {
     const om_mech *m = h;
@@ -897,7 +899,7 @@ int om_integrate(void *h, int64_t n, double *T, const double *p, double *Y, int6
         for (int k = 0; k < K; k++) y[k] = Y[k * ldY + i];
         y[K] = T[i];
         chem_ctx c = {m, p[i]};
-        om_problem P = {K + 1, chem_f, chem_j, &c};
+        om_problem P = {K + 1, chem_f, chem_j, &c, (qmax >= 1 && qmax <= BDF_QMAX) ? qmax : BDF_QMAX};
         om_counts cnt;
         int st = bdf_integrate(&P, y, dt, rtol, atol, max_steps, &cnt);
         for (int k = 0; k < K; k++) Y[k * ldY + i] = y[k];
@@ -943,12 +945,13 @@ static int user_j(void *ctx, double t, const double *y, double *J)
     return 0;
 }
 
-/* Controlled integration of a user ODE y' = f(t, y) over [0, t_end]. */
+/* Controlled integration of a user ODE y' = f(t, y) over [0, t_end], orders
+ * up to qmax (1..5, anything else means 5). */
 int om_bdf_user(int N, om_user_f f, om_user_j j, void *ud, double *y, double t_end, double rtol,
-                double atol, int max_steps, int32_t *counters)
+                double atol, int max_steps, int qmax, int32_t *counters)
 {
     user_ctx u = {f, j, ud};
-    om_problem P = {N, user_f, user_j, &u};
+    om_problem P = {N, user_f, user_j, &u, (qmax >= 1 && qmax <= BDF_QMAX) ? qmax : BDF_QMAX};
     om_counts cnt;
     int st = bdf_integrate(&P, y, t_end, rtol, atol, max_steps, &cnt);
     if (counters) {

@@ -293,3 +293,37 @@ def test_equilibrium_cells_take_one_step(om9, mech_dir):
     ends = np.where((g.c < 1e-12) | (g.c > 1 - 1e-12))[0]
     T1, Y1, st, cnt, _ = om9.integrate(g.T[ends], g.p[ends], g.Y[:, ends], 1e-6)
     assert np.all(st == 0) and np.all(cnt[:, 0] <= 2)
+
+
+def test_maximum_order_option(oracle_lib):
+    """qmax caps the order the step selection may raise to: on y' = -y the
+    accepted steps fall strictly with the cap (the step size grows with the
+    order of the local error), every cap meets the tolerance-scaled error of
+    the exact solution, and qmax = 5 is the default method bit for bit."""
+    f = lambda t, y: -y
+    j = lambda t, y: np.array([[-1.0]])
+    exact = math.exp(-2.0)
+    steps = []
+    for q in (1, 2, 3, 4, 5):
+        y, st, c = oracle_lib.bdf_user(f, j, [1.0], 2.0, rtol=1e-6, atol=1e-14, qmax=q)
+        assert st == 0
+        assert abs(y[0] - exact) <= 1e3 * 1e-6 * exact
+        steps.append(int(c[0]))
+    assert all(a > b for a, b in zip(steps, steps[1:])), steps
+    y5, _, c5 = oracle_lib.bdf_user(f, j, [1.0], 2.0, rtol=1e-6, atol=1e-14)
+    y5q, _, c5q = oracle_lib.bdf_user(f, j, [1.0], 2.0, rtol=1e-6, atol=1e-14, qmax=5)
+    assert y5[0] == y5q[0] and np.array_equal(c5, c5q)
+
+
+def test_maximum_order_option_on_cells(om9, mech_dir):
+    """The same option through the cell integrator: a lower cap never takes
+    fewer steps, and the results stay within the tolerance-scaled distance of
+    the default method's."""
+    from chemgen.fields import cells4096
+    from chemgen.mechanism import read_mechanism
+    f = cells4096(read_mechanism(str(mech_dir / "M9.mech")), n=64, seed=7)
+    T5, Y5, s5, c5, _ = om9.integrate(f.T, f.p, f.Y, f.dt)
+    T2, Y2, s2, c2, _ = om9.integrate(f.T, f.p, f.Y, f.dt, qmax=2)
+    assert np.all(s5 == 0) and np.all(s2 == 0)
+    assert np.all(c2[:, 0] >= c5[:, 0]) and c2[:, 0].sum() > c5[:, 0].sum()
+    assert np.max(np.abs(T2 - T5)) < 1e-3
