@@ -82,7 +82,9 @@ typedef struct {
                            a new Newton matrix before the Jacobian is evaluated
                            (1..64; 0 = library choice).  Scheduling only: results
                            do not depend on it. */
-    int32_t reserved[7];
+    int32_t qmax;       /* highest BDF order the step selection may raise to,
+                           1..5 (0 = 5, the default method) */
+    int32_t reserved[6];
 } chem_opts;
 
 /* Fill opts with the defaults above. */

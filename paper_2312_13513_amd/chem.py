@@ -28,7 +28,7 @@ class ChemError(RuntimeError):
 class chem_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
                 ("precision", C.c_int32), ("schedule", C.c_int32), ("block", C.c_int32),
-                ("jac_batch", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("jac_batch", C.c_int32), ("qmax", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class chem_stats(C.Structure):

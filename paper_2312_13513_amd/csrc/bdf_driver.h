@@ -417,9 +417,9 @@ __device__ __forceinline__ void conv_fail(LaneState<N> &S, const CellIO &io)
     begin_attempt(S, io);
 }
 
-// Step size and order for the step after an accepted one.
+// Step size and order for the step after an accepted one (orders up to qmax).
 template <int N>
-__device__ __forceinline__ void select_next(LaneState<N> &S)
+__device__ __forceinline__ void select_next(LaneState<N> &S, int qmax)
 {
     using namespace bdf;
     const int q = S.q;
@@ -461,7 +461,7 @@ __device__ __forceinline__ void select_next(LaneState<N> &S)
                 const double Em = wrms_norm<N>(zq, S.z) * prod / l1;
                 eta_m = 1.0 / (pow(kBiasQm1 * Em, 1.0 / q) + kAddon);
             }
-            if (q < kQmax && S.ehat_ok) {
+            if (q < qmax && S.ehat_ok) {
                 const double rr = pow(h_done / S.ehat_h, q + 1);
                 double dv[N];
 #pragma unroll
@@ -594,7 +594,7 @@ __device__ __forceinline__ void error_test(LaneState<N> &S, const CellIO &io)
         finish_cell(S, io, 0);
         return;
     }
-    select_next(S);
+    select_next(S, io.prm->qmax);
     begin_step(S, io);
 }
 

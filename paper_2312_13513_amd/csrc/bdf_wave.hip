@@ -788,7 +788,7 @@ __device__ void run_cells(const DevMechView &m, const WaveTables &wt, const Cell
                         const double Em = wnorm(zq) * prod / l1;
                         eta_m = 1.0 / (pow(kBiasQm1 * Em, 1.0 / q) + kAddon);
                     }
-                    if (q < kQmax && ehat_ok) {
+                    if (q < io.prm->qmax && ehat_ok) {
                         const double rr = pow(h_done / ehat_h, q + 1);
                         const double dv = ehat_new - ehat * rr;
                         double prod = 1.0, l1 = 0.0;

@@ -49,6 +49,7 @@ struct BdfParams {
     const int64_t *n_dev;   // if not NULL: at most *n_dev cells (read on the device)
     const int32_t *idx;     // if not NULL: integrate cells idx[0 .. n_idx) in this order
     int64_t n_idx;
+    int32_t qmax;           // highest order the step selection may raise to (1..kQmax)
 };
 
 // Launchers of the table-driven kernels.  Return hipError_t of the launch.

@@ -229,7 +229,9 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
     if (sched == 2 && K + 1 > 16)
         return fail(CHEM_EUNSUP, "the tile schedule supports at most 15 species");
     if (o.jac_batch < 0 || o.jac_batch > 64) return fail(CHEM_EINVAL, "jac_batch must be in 0..64");
-    chem::BdfParams prm{o.rtol, o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16, n_dev, idx, n_idx};
+    if (o.qmax < 0 || o.qmax > chem::kQmax) return fail(CHEM_EINVAL, "qmax must be in 0..5");
+    chem::BdfParams prm{o.rtol,  o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16,
+                        n_dev,   idx,    n_idx,       o.qmax > 0 ? o.qmax : chem::kQmax};
     // each call takes its own queue counter (64 rotate), so that calls in
     // flight on different streams do not share one
     unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);

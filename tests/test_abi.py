@@ -33,7 +33,7 @@ def test_default_opts():
     from paper_2312_13513_amd import chem
     o = chem.chem_default_opts()
     assert o.rtol == 1e-8 and o.atol == 1e-12 and o.max_steps == 20000
-    assert o.precision == 0 and o.schedule == -1
+    assert o.precision == 0 and o.schedule == -1 and o.qmax == 0
 
 
 def test_bad_mechanism_files_are_rejected(tmp_path, mech_dir):

@@ -114,7 +114,7 @@ def oracle_envelope(om, T, p, Y, dt, base):
 ULP_PERTURBATIONS = [(q, k) for q in ("T", "p", "rtol") for k in (1, -1, 2, -2)]
 
 
-def compare_flips_to_oracle_alternatives(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, To, Yo, so, co):
+def compare_flips_to_oracle_alternatives(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, To, Yo, so, co, okw=None):
     """Plain bars for cells whose step counts agree with the oracle.  A cell
     where round-off flipped a Newton or error-test decision is compared with
     the oracle run on its inputs perturbed by one or two ulps (T, p or rtol):
@@ -135,7 +135,7 @@ def compare_flips_to_oracle_alternatives(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, T
         for q, k in ULP_PERTURBATIONS:
             f = 1.0 + k * 2.0 ** -52
             Ta, Ya, sa, ca, _ = om.integrate(T[sl] * (f if q == "T" else 1.0), p[sl] * (f if q == "p" else 1.0),
-                                             Y[:, sl], dt, rtol=1e-8 * (f if q == "rtol" else 1.0))
+                                             Y[:, sl], dt, rtol=1e-8 * (f if q == "rtol" else 1.0), **(okw or {}))
             spread_T = max(spread_T, abs(Ta[0] - To[i]))
             spread_Y = max(spread_Y, np.abs(Ya[:, 0] - Yo[:, i]).max())
             if np.array_equal(ca[0], cg[i]) and sa[0] == sg[i]:
@@ -450,3 +450,29 @@ def test_isomerisation_closed_form_gpu(torch, tmp_path):
     assert np.all(np.abs(Yg[0] - exact) <= 100 * (1e-8 * np.abs(exact) + 1e-12))
     assert np.allclose(Tg, T, rtol=1e-12)
     gm.close()
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 2])
+def test_maximum_order_option(torch, gm9, om9, cells4096_run, schedule):
+    """opts.qmax caps the BDF order on every schedule, with the oracle run at
+    the same cap as the reference; an out-of-range cap is rejected."""
+    from paper_2312_13513_amd import chem
+    f = cells4096_run[0]
+    for qmax in (1, 2, 3):
+        # backward Euler (qmax 1) needs thousands of steps on the stiff cells
+        # (some hit max_steps, on both sides): fewer cells there
+        sel = np.arange(0, 100 if qmax == 1 else 600)
+        o = chem.chem_default_opts()
+        o.schedule = schedule
+        o.qmax = qmax
+        Tg, Yg, sg, cg = run_gpu(torch, gm9, f.T[sel], f.p[sel], f.Y[:, sel], f.dt, opts=o)
+        To, Yo, so, co, _ = om9.integrate(f.T[sel], f.p[sel], f.Y[:, sel], f.dt, qmax=qmax)
+        flips = compare_flips_to_oracle_alternatives(f"qmax{qmax}-schedule{schedule}", om9, f.T[sel], f.p[sel],
+                                                     f.Y[:, sel], f.dt, Tg, Yg, sg, cg, To, Yo, so, co,
+                                                     okw={"qmax": qmax})
+        assert flips.size <= max(6, sel.size // 10)
+    o = chem.chem_default_opts()
+    o.qmax = 6
+    T = torch.full((4,), 1500.0, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(chem.ChemError):
+        gm9.integrate(T, T, torch.full((9, 4), 1.0 / 9, dtype=torch.float64, device="cuda:0"), 1e-6, opts=o)
