@@ -400,10 +400,10 @@ constexpr int kApplyMaxE = 8;   // elements the decode kernel handles
 
 // mass-specific enthalpy and cp of the mixture Y[0..K) (KM >= K, static loop)
 // Thermo of species k at T (the NASA range of the lane's T): cp/R and H/(R T).
-__device__ __forceinline__ void species_cp_hrt(const ApplyArgs &a, int k, double T, double invT, double &cp,
-                                               double &hrt)
+__device__ __forceinline__ void species_cp_hrt(const ApplyArgs &a, const double *species, int k, double T,
+                                               double invT, double &cp, double &hrt)
 {
-    const double *s = a.species + k * kSpeciesLen;
+    const double *s = species + k * kSpeciesLen;
     const bool low = !a.two_range || T < s[0];
     double r[11];
     const double *c = s + 1 + (low ? 0 : kRangeLen);
@@ -417,8 +417,8 @@ __device__ __forceinline__ void species_cp_hrt(const ApplyArgs &a, int k, double
 // Mixture enthalpy (J/kg) and cp (J/(kg K)) at T: sums over species in order,
 // each term Y_k (R/W_k) times T H_k/(R T), resp. cp_k/R.
 template <int KM>
-__device__ __forceinline__ void mix_h_cp(const ApplyArgs &a, double T, const double (&Y)[KM], double &hm,
-                                         double &cm)
+__device__ __forceinline__ void mix_h_cp(const ApplyArgs &a, const double *species, double T,
+                                         const double (&Y)[KM], double &hm, double &cm)
 {
     double h = 0.0, c = 0.0;
     const double invT = 1.0 / T;
@@ -426,7 +426,7 @@ __device__ __forceinline__ void mix_h_cp(const ApplyArgs &a, double T, const dou
     for (int k = 0; k < KM; k++) {
         if (k < a.K) {
             double cp, hrt;
-            species_cp_hrt(a, k, T, invT, cp, hrt);
+            species_cp_hrt(a, species, k, T, invT, cp, hrt);
             const double yr = Y[k] * a.rw[k];
             h += yr * (T * hrt);
             c += yr * cp;
@@ -439,8 +439,12 @@ __device__ __forceinline__ void mix_h_cp(const ApplyArgs &a, double T, const dou
 // Decode, checks and temperature recovery, one thread per cell.  The input
 // state is read once: its element content, the element residual of the
 // prediction and the input enthalpy are accumulated in the same pass, so
-// only the predicted mass fractions stay in registers.
-template <int KM, int KE>
+// only the predicted mass fractions stay in registers.  The block first
+// copies the species thermo blocks into LDS, where the enthalpy Newton
+// iterations read them.  With V4 (the output rows 16-byte aligned) a cell's
+// network outputs are read four at a time; one float per load touches a
+// different cache line in every lane of a wave for each species.
+template <int KM, int KE, bool V4>
 __global__ void __launch_bounds__(256, 3) apply_kernel(ApplyArgs a, double *__restrict__ T,
                                                     const double *__restrict__ p,
                                                     double *__restrict__ Y, int64_t ldY, int64_t n,
@@ -450,6 +454,9 @@ __global__ void __launch_bounds__(256, 3) apply_kernel(ApplyArgs a, double *__re
                                                     int32_t *__restrict__ list,
                                                     int64_t *__restrict__ count)
 {
+    __shared__ double sp_lds[KM * kSpeciesLen];
+    for (int j = threadIdx.x; j < a.K * kSpeciesLen; j += 256) sp_lds[j] = a.species[j];
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool reject = false;
     if (i < n) {
@@ -463,12 +470,21 @@ __global__ void __launch_bounds__(256, 3) apply_kernel(ApplyArgs a, double *__re
         double res[KE], ref[KE];
 #pragma unroll
         for (int e = 0; e < KE; e++) res[e] = ref[e] = 0.0;
+        float4 o4 = make_float4(0.f, 0.f, 0.f, 0.f);   // outputs k .. k+3 (V4)
 #pragma unroll
         for (int k = 0; k < KM; k++) {
             Y1[k] = 0.0;
             if (k < K) {
                 const double y0 = Y[(int64_t)k * ldY + i];
-                const double v = y0 + a.mu_y[k] + a.sig_y[k] * (double)out[i * nout_pad + k];
+                float ok;
+                if constexpr (V4) {
+                    // k + 3 < round_up(K, 4) <= nout_pad: inside the row
+                    if (k % 4 == 0) o4 = *(const float4 *)(out + i * nout_pad + k);
+                    ok = (k % 4 == 0) ? o4.x : (k % 4 == 1) ? o4.y : (k % 4 == 2) ? o4.z : o4.w;
+                } else {
+                    ok = out[i * nout_pad + k];
+                }
+                const double v = y0 + a.mu_y[k] + a.sig_y[k] * (double)ok;
                 Y1[k] = v;
                 ok = ok && isfinite(v);
                 sum += v;
@@ -481,7 +497,7 @@ __global__ void __launch_bounds__(256, 3) apply_kernel(ApplyArgs a, double *__re
                         ref[e] += nk * y0;
                     }
                 double cp, hrt;
-                species_cp_hrt(a, k, T0, invT0, cp, hrt);
+                species_cp_hrt(a, sp_lds, k, T0, invT0, cp, hrt);
                 h0 += (y0 * a.rw[k]) * (T0 * hrt);
             }
         }
@@ -511,7 +527,12 @@ __global__ void __launch_bounds__(256, 3) apply_kernel(ApplyArgs a, double *__re
             double Tk = T0;
             for (int it = 0; it < 20; it++) {
                 double hm, cm;
-                mix_h_cp<KM>(a, Tk, Y1, hm, cm);
+                // an offset the compiler cannot see through keeps the table
+                // reads inside the loop: hoisted, the coefficients of every
+                // species would be held in registers across the iterations
+                int off = 0;
+                asm volatile("" : "+v"(off));
+                mix_h_cp<KM>(a, sp_lds + off, Tk, Y1, hm, cm);
                 const double dT = -(hm - h0) / cm;
                 Tk += dT;
                 Tk = fmin(fmax(Tk, 200.0), 3500.0);
@@ -784,13 +805,22 @@ hipError_t launch_apply(const ApplyArgs &a, double *T, const double *p, double *
 {
     if (n <= 0) return hipSuccess;
     if (a.E > kApplyMaxE) return hipErrorInvalidValue;
-#define CHEM_APPLY(KM)                                                                                        \
-    if (a.E <= 4)                                                                                             \
-        hipLaunchKernelGGL((apply_kernel<KM, 4>), dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, ldY, n, \
-                           base, out, nout_pad, mask, status, list, count);                                   \
+    const bool v4 = ((uintptr_t)out % 16 == 0) && nout_pad % 4 == 0;
+#define CHEM_APPLY_E(KM, KE)                                                                                  \
+    if (v4)                                                                                                   \
+        hipLaunchKernelGGL((apply_kernel<KM, KE, true>), dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y,  \
+                           ldY, n, base, out, nout_pad, mask, status, list, count);                           \
     else                                                                                                      \
-        hipLaunchKernelGGL((apply_kernel<KM, kApplyMaxE>), dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, \
+        hipLaunchKernelGGL((apply_kernel<KM, KE, false>), dim3(blocks_for(n, 256)), dim3(256), 0, s, a, T, p, Y, \
                            ldY, n, base, out, nout_pad, mask, status, list, count)
+#define CHEM_APPLY(KM)                                                                                        \
+    do {                                                                                                      \
+        if (a.E <= 4) {                                                                                       \
+            CHEM_APPLY_E(KM, 4);                                                                              \
+        } else {                                                                                              \
+            CHEM_APPLY_E(KM, kApplyMaxE);                                                                     \
+        }                                                                                                     \
+    } while (0)
     if (a.K <= 16)
         CHEM_APPLY(16);
     else if (a.K <= 32)
@@ -804,6 +834,7 @@ hipError_t launch_apply(const ApplyArgs &a, double *T, const double *p, double *
     else
         return hipErrorInvalidValue;
 #undef CHEM_APPLY
+#undef CHEM_APPLY_E
     return hipGetLastError();
 }
 

@@ -315,6 +315,37 @@ def test_apply_checks_parity(torch, mechs, m35py, om35):
     s.close()
 
 
+def test_apply_unaligned_output_rows(torch, mechs, m35py):
+    """A network output buffer that is not 16-byte aligned (a view one float
+    into a larger allocation) takes the one-float-per-load decode; the result
+    equals the vector-load decode of an aligned copy bit for bit."""
+    from paper_2312_13513_amd import chem
+    rng = np.random.default_rng(43)
+    T, p, Y, yhat, mu_y, sig_y = _apply_case(m35py, rng)
+    K, n = m35py.K, T.size
+    s = chem.Surrogate(mechs["M35"], 64, 64, 64)
+    s.set_norm(np.concatenate([np.zeros(K + 2), np.ones(K + 2), mu_y, sig_y, [1e-5]]))
+    out = np.zeros((n, s.nout_pad), dtype=np.float32)
+    out[:, :K] = yhat
+    aligned = _dev(torch, out, torch.float32)
+    big = torch.zeros(n * s.nout_pad + 1, dtype=torch.float32, device="cuda:0")
+    shifted = big[1:].view(n, s.nout_pad)
+    shifted.copy_(aligned)
+    assert aligned.data_ptr() % 16 == 0 and shifted.data_ptr() % 16 == 4
+    res = []
+    for o in (aligned, shifted):
+        Tg, Yg = _dev(torch, T), _dev(torch, Y)
+        mask = torch.full((n,), -1, dtype=torch.int32, device="cuda:0")
+        s.apply(Tg, _dev(torch, p), Yg, o, checks=chem.chem_surrogate_default_checks(), mask=mask)
+        torch.cuda.synchronize()
+        res.append((Tg.cpu().numpy(), Yg.cpu().numpy(), mask.cpu().numpy()))
+    _say(f"[apply unaligned] accepted {np.sum(res[0][2] == 0)} of {n}")
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+    assert 0 < np.sum(res[0][2] == 0) < n
+    s.close()
+
+
 def _train_set(torch, chem, mech, mpy, n_flame, n_traj, traj_steps, dt, seed):
     """Training states and their successors over dt, labelled by the GPU
     integrator (trajectory states are recorded step by step)."""
