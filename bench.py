@@ -102,12 +102,12 @@ def traffic_for(workload: str, kernel: str):
     return None
 
 
-def kernel_name(mech, schedule: int, precision: int) -> str:
+def kernel_name(mech, schedule: int, precision: int, n: int) -> str:
     lt = "float" if precision == 1 else "double"
     if schedule < 0:   # the library's own choice
         schedule = 2 if mech.N <= 16 else 1
-    if schedule == 2:
-        return f"bdf_tile_kernel<{12 if mech.N <= 12 else 16},{lt},true>"
+    if schedule == 2:   # refreshes deferred from 65,536 cells on
+        return f"bdf_tile_kernel<{12 if mech.N <= 12 else 16},{lt},true,{'true' if n >= 65536 else 'false'}>"
     if schedule == 1 or precision == 1 or (mech.variant == "table" and mech.K > 9):
         np_rows = 16 if mech.N <= 16 else (40 if mech.N <= 40 else 64)
         return f"bdf_wave_kernel<{np_rows},{lt},true>"
@@ -230,7 +230,7 @@ def run_integrator(args, workload: str):
     Tg, Yg = T.cpu().numpy(), Y.cpu().numpy()
     fl = algorithmic_flops(K, R, cnt)
     achieved = fl["total"] / avg_kern_s / 1e12
-    kname = kernel_name(mech, schedule, precision)
+    kname = kernel_name(mech, schedule, precision, n)
     traffic = traffic_for(workload, kname)
     result = {
         "metric": METRIC,

@@ -475,7 +475,7 @@ __device__ __forceinline__ double wave_solve(const WaveLds<NP, LT, G> &L, int N,
 // the work queue as soon as its cell is done, whatever the other groups of
 // the wave are doing: each pass of the loop is one step of the group's cell
 // (preceded by taking and starting a new cell when the group has none).
-template <int NP, typename LT, int G>
+template <int NP, typename LT, int G, bool DEFER>
 __device__ void run_cells(const DevMechView &m, const WaveTables &wt, const CellIO &io,
                           double t_end, unsigned long long *queue, double *qbuf,
                           WaveLds<NP, LT, G> &L)
@@ -505,6 +505,8 @@ __device__ void run_cells(const DevMechView &m, const WaveTables &wt, const Cell
     int nst = 0, nfe = 0, nje = 0, nni = 0, netf = 0, ncfn = 0, status = 0;
     int q = 1, qwait = 2, nst_M = 0;
     bool have_M = false, ehat_ok = false;
+    bool waited = false;    // the group sat out the last pass (refresh deferral)
+    unsigned long long ticket = 0;   // the group's last work-queue position
     double gamma_M = 0.0, crate = 1.0, ehat_h = 0.0, ehat = 0.0;
     auto wnorm = [&](double v) { const double u = active ? v * w : 0.0; return sqrt(Gp::sum(u * u) * (1.0 / N)); };
     auto all_finite = [&](double v) { return Gp::ballot(active && !isfinite(v)) == 0ull; };
@@ -514,6 +516,7 @@ __device__ void run_cells(const DevMechView &m, const WaveTables &wt, const Cell
             if (lane == 0) c = atomicAdd(queue, 1ull);
             c = Gp::first(c);
             if (c >= (unsigned long long)io.nq) break;
+            ticket = c;
             const int64_t cc = io.idx ? (int64_t)io.idx[c] : (int64_t)c;
             if (cc < 0 || cc >= io.n) continue;   // an index outside the arrays is skipped
             cell = cc;
@@ -583,6 +586,40 @@ __device__ void run_cells(const DevMechView &m, const WaveTables &wt, const Cell
             if (nst >= io.prm->max_steps) {
                 status = 1;
                 break;
+            }
+            if constexpr (Gp::kCells > 1 && DEFER) {
+                // The cells of a wave share its instruction stream: a Newton
+                // matrix refresh (Jacobian and LU) for one of them costs the
+                // whole wave.  A cell whose step will start with a refresh
+                // sits out one pass unless another cell of the wave needs one
+                // too (or it is the only cell stepping), so refreshes are
+                // shared more often.  Only while more cells were queued than
+                // the grid holds groups when this one took its cell: in the
+                // tail the slowest cell's latency is the run time, and waiting
+                // would lengthen it.  Its state is untouched while it waits:
+                // results do not depend on this.  The test estimates the
+                // step's gamma = h / l_1, l_1 = sum of 1/xi_i over the order;
+                // the refresh itself is decided exactly inside the step.
+                bool need = false;
+                if ((unsigned long long)io.nq - ticket > (unsigned long long)gridDim.x * Gp::kCells) {
+                    const double hh = (t + h >= t_end) ? t_end - t : h;
+                    double l1 = 0.0, s = hh;
+#pragma unroll
+                    for (int i = 1; i <= kQmax; i++)
+                        if (i <= q) {
+                            l1 += hh / s;
+                            s += tau[i];
+                        }
+                    need = !have_M || nst >= nst_M + kMsbp || fabs((hh / l1) / gamma_M - 1.0) > kDgmax;
+                }
+                const bool lead = lane == 0;
+                const int n_need = __popcll(__ballot(lead && need));
+                const int n_step = __popcll(__ballot(lead));
+                if (need && !waited && n_need < 2 && n_step >= 2) {
+                    waited = true;
+                    break;
+                }
+                waited = false;
             }
             bool last = false;
             if (t + h >= t_end) {
@@ -893,7 +930,7 @@ __device__ void run_cells(const DevMechView &m, const WaveTables &wt, const Cell
 // cell in flight): in LDS after `qlds` (QLDS), else a global slice per group
 // (qscratch).  Fixing the choice at compile time keeps LDS accesses as LDS
 // instructions.
-template <int NP, typename LT, int G, bool QLDS>
+template <int NP, typename LT, int G, bool QLDS, bool DEFER>
 __device__ __forceinline__ void run_block(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
                                           double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
                                           int32_t *status, int32_t *counters, unsigned long long *queue,
@@ -907,7 +944,7 @@ __device__ __forceinline__ void run_block(const DevMechView &m, const WaveTables
         qbuf = qlds + slot * q7;
     else
         qbuf = qscratch + ((size_t)blockIdx.x * Grp<G>::kCells + slot) * q7;
-    run_cells<NP, LT, G>(m, wt, io, dt, queue, qbuf, Ls[slot]);
+    run_cells<NP, LT, G, DEFER>(m, wt, io, dt, queue, qbuf, Ls[slot]);
 }
 
 // One 64-lane wave per cell.
@@ -921,14 +958,16 @@ __global__ void __launch_bounds__(64) bdf_wave_kernel(DevMechView m, WaveTables 
 {
     __shared__ WaveLds<NP, LT, 64> Ls[1];
     extern __shared__ double dyn[];
-    run_block<NP, LT, 64, QLDS>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, dyn, Ls);
+    run_block<NP, LT, 64, QLDS, false>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, dyn, Ls);
 }
 
 // Tile schedule: 16 lanes per cell, four cells per wave (N <= NP <= 16).  With
 // STAGE the mechanism tables (species .. incidence entries, one contiguous
 // range) are first copied into LDS, where the four cells share them, and the
 // reaction scratch follows them there; without it both stay in global memory.
-template <int NP, typename LT, bool STAGE>
+// DEFER: Newton-matrix refreshes are deferred by a pass to share them between
+// the cells of a wave (for large batches; scheduling only).
+template <int NP, typename LT, bool STAGE, bool DEFER>
 __global__ void __launch_bounds__(64) bdf_tile_kernel(DevMechView m, WaveTables wt, double *__restrict__ T,
                                                       const double *__restrict__ p, double *__restrict__ Y,
                                                       int64_t ldY, int64_t n, double dt, BdfParams prm,
@@ -954,10 +993,11 @@ __global__ void __launch_bounds__(64) bdf_tile_kernel(DevMechView m, WaveTables 
         WaveTables wl;
         wl.inc_off = (const int *)(lds + ((const char *)wt.inc_off - base));
         wl.inc = (const int2 *)(lds + ((const char *)wt.inc - base));
-        run_block<NP, LT, 16, true>(ml, wl, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch,
-                                    dyn + tb / 8, Ls);
+        run_block<NP, LT, 16, true, DEFER>(ml, wl, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch,
+                                           dyn + tb / 8, Ls);
     } else {
-        run_block<NP, LT, 16, false>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, dyn, Ls);
+        run_block<NP, LT, 16, false, DEFER>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch, dyn,
+                                            Ls);
     }
 }
 
@@ -997,6 +1037,7 @@ static hipError_t launch_groups(Kern kern, int cells_per_wave, size_t dyn, bool 
 
 constexpr size_t kQbufLdsMax = 49152;     // reaction scratch of one wave kept in LDS up to this size
 constexpr size_t kTileStageMax = 24576;   // tables + scratch of a tile block staged in LDS up to this size
+constexpr int64_t kDeferMinCells = 65536; // tile batches from this size defer Newton-matrix refreshes
 
 template <int NP, typename LT>
 static hipError_t launch_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p, double *Y,
@@ -1019,11 +1060,21 @@ static hipError_t launch_tile(const DevMechView &m, const WaveTables &wt, double
                               hipStream_t s)
 {
     const size_t lds = (size_t)m.table_bytes + (size_t)4 * 7 * (m.R > 0 ? m.R : 1) * sizeof(double);
-    if (lds <= kTileStageMax)
-        return launch_groups(bdf_tile_kernel<NP, LT, true>, 4, lds, false, m, wt, T, p, Y, ldY, n, dt, prm, status,
-                             counters, queue, qscratch, max_groups, s);
-    return launch_groups(bdf_tile_kernel<16, LT, false>, 4, 0, true, m, wt, T, p, Y, ldY, n, dt, prm, status,
-                         counters, queue, qscratch, max_groups, s);
+    // refresh deferral pays when the queue holds many cells per group; a
+    // small batch is latency bound and runs the plain loop.  A count that
+    // lives on the device is taken as small.
+    const int64_t nq = prm.n_dev ? 0 : (prm.idx ? prm.n_idx : n);
+    const bool defer = nq >= kDeferMinCells;
+#define CHEM_TILE(NPV, STAGE, DEF, DYN, QG)                                                                      \
+    return launch_groups(bdf_tile_kernel<NPV, LT, STAGE, DEF>, 4, DYN, QG, m, wt, T, p, Y, ldY, n, dt, prm, status, \
+                         counters, queue, qscratch, max_groups, s)
+    if (lds <= kTileStageMax) {
+        if (defer) CHEM_TILE(NP, true, true, lds, false);
+        CHEM_TILE(NP, true, false, lds, false);
+    }
+    if (defer) CHEM_TILE(16, false, true, 0, true);
+    CHEM_TILE(16, false, false, 0, true);
+#undef CHEM_TILE
 }
 
 hipError_t launch_bdf_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p,

@@ -168,3 +168,33 @@ def test_tile_full_width_unstaged_tables(torch, m15_path, oracle_lib):
     compare_cell_envelope("tile-M15", om, f.T, f.p, f.Y, f.dt, *tile, To, Yo, so, co)
     assert np.array_equal(tile[2], wave[2])
     g.close()
+
+
+def test_refresh_deferral_is_bitwise_plain(torch, g9, mech_dir):
+    """From 65,536 queued cells the tile kernel lets a cell that needs a new
+    Newton matrix wait a pass for a second cell of its wave (scheduling only).
+    The whole 64^3 flame field (262,144 cells, deferral on) gives bit for bit
+    the state, status and counters of the same cells run as five index lists
+    of under 65,536 cells each (the plain loop)."""
+    from chemgen.fields import flame64
+    from chemgen.mechanism import read_mechanism
+    f = flame64(read_mechanism(str(mech_dir / "M9.mech")))
+    n = f.n
+    assert n >= 4 * 65536
+    full = run_gpu(torch, g9, f.T, f.p, f.Y, f.dt, opts=_opts(2))
+    dev = torch.device("cuda:0")
+    T = torch.tensor(f.T, dtype=torch.float64, device=dev)
+    p = torch.tensor(f.p, dtype=torch.float64, device=dev)
+    Y = torch.tensor(np.ascontiguousarray(f.Y), dtype=torch.float64, device=dev)
+    st = torch.full((n,), -1, dtype=torch.int32, device=dev)
+    cn = torch.zeros(6 * n, dtype=torch.int32, device=dev)
+    perm = np.random.default_rng(5).permutation(n).astype(np.int32)
+    for part in np.array_split(perm, 5):
+        assert part.size < 65536
+        idx = torch.tensor(part, device=dev)
+        g9.integrate_indexed(T, p, Y, idx, f.dt, opts=_opts(2), status=st, counters=cn)
+    torch.cuda.synchronize()
+    parts = (T.cpu().numpy(), Y.cpu().numpy(), st.cpu().numpy(), cn.cpu().numpy().reshape(6, n).T)
+    _say(f"[deferral] {n} cells: full run vs five index lists, steps mean {parts[3][:, 0].mean():.2f}")
+    for a, b in zip(full, parts):
+        assert a.shape == b.shape and np.array_equal(a, b)
