@@ -256,7 +256,7 @@ int chem_surrogate_forward(chem_surr surr, const uint16_t *X, int64_t n, float *
                            void *hip_stream);
 /* The same with a choice of kernels: path 0 = library choice (as
  * chem_surrogate_forward), 1 = one GEMM per layer with the activations in
- * device memory, 2 = the fused kernel (all layers per 64-row tile, activations
+ * device memory, 2 = the fused kernel (all layers per 32-row block, activations
  * in LDS; CHEM_EUNSUP unless every width is <= 512).  Paths 1 and 2 give the
  * same output bit for bit (same MFMA accumulation order, same epilogues). */
 int chem_surrogate_forward_path(chem_surr surr, const uint16_t *X, int64_t n, float *out, int64_t ldo,
