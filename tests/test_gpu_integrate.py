@@ -152,7 +152,8 @@ def compare_flips_to_oracle_alternatives(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, T
     return flip
 
 
-def compare_cell_envelope(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, To, Yo, so, co, factor=4.0, per_cell=True):
+def compare_cell_envelope(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, To, Yo, so, co, factor=4.0, per_cell=True,
+                          okw=None):
     """For ill-conditioned workloads (hundreds of steps per cell, where
     round-off in any implementation moves the result beyond the plain bars
     even without a flipped decision): every cell stays within `factor` times
@@ -165,7 +166,8 @@ def compare_cell_envelope(tag, om, T, p, Y, dt, Tg, Yg, sg, cg, To, Yo, so, co, 
     sY = np.zeros(Tg.size)
     for q, k in ((q, k) for q in ("T", "rtol") for k in (1, 2)):
         f = 1.0 + k * 2.0 ** -52
-        Ta, Ya = om.integrate(T * (f if q == "T" else 1.0), p, Y, dt, rtol=1e-8 * (f if q == "rtol" else 1.0))[:2]
+        Ta, Ya = om.integrate(T * (f if q == "T" else 1.0), p, Y, dt, rtol=1e-8 * (f if q == "rtol" else 1.0),
+                              **(okw or {}))[:2]
         sT = np.maximum(sT, np.abs(Ta - To))
         sY = np.maximum(sY, np.abs(Ya - Yo).max(axis=0))
     dT = np.abs(Tg - To)

@@ -170,7 +170,8 @@ def test_tile_full_width_unstaged_tables(torch, m15_path, oracle_lib):
     g.close()
 
 
-def test_refresh_deferral_is_bitwise_plain(torch, g9, mech_dir):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_refresh_deferral_is_bitwise_plain(torch, g9, mech_dir, precision):
     """From 65,536 queued cells the tile kernel lets a cell that needs a new
     Newton matrix wait a pass for a second cell of its wave (scheduling only).
     The whole 64^3 flame field (262,144 cells, deferral on) gives bit for bit
@@ -181,7 +182,7 @@ def test_refresh_deferral_is_bitwise_plain(torch, g9, mech_dir):
     f = flame64(read_mechanism(str(mech_dir / "M9.mech")))
     n = f.n
     assert n >= 4 * 65536
-    full = run_gpu(torch, g9, f.T, f.p, f.Y, f.dt, opts=_opts(2))
+    full = run_gpu(torch, g9, f.T, f.p, f.Y, f.dt, opts=_opts(2, precision))
     dev = torch.device("cuda:0")
     T = torch.tensor(f.T, dtype=torch.float64, device=dev)
     p = torch.tensor(f.p, dtype=torch.float64, device=dev)
@@ -192,9 +193,9 @@ def test_refresh_deferral_is_bitwise_plain(torch, g9, mech_dir):
     for part in np.array_split(perm, 5):
         assert part.size < 65536
         idx = torch.tensor(part, device=dev)
-        g9.integrate_indexed(T, p, Y, idx, f.dt, opts=_opts(2), status=st, counters=cn)
+        g9.integrate_indexed(T, p, Y, idx, f.dt, opts=_opts(2, precision), status=st, counters=cn)
     torch.cuda.synchronize()
     parts = (T.cpu().numpy(), Y.cpu().numpy(), st.cpu().numpy(), cn.cpu().numpy().reshape(6, n).T)
-    _say(f"[deferral] {n} cells: full run vs five index lists, steps mean {parts[3][:, 0].mean():.2f}")
+    _say(f"[deferral precision={precision}] {n} cells: full run vs five index lists, steps mean {parts[3][:, 0].mean():.2f}")
     for a, b in zip(full, parts):
         assert a.shape == b.shape and np.array_equal(a, b)

@@ -98,6 +98,24 @@ def test_wave_m35_mixed_precision_error(torch, gm35, zones_field, zones_oracle):
     assert dT.max() < 1e-3 and dY.max() < 1e-6
 
 
+def test_wave_m35_maximum_order(torch, gm35, zones_field, om35):
+    """The order cap on the wave schedule with the 35-species mechanism:
+    qmax = 2 roughly triples the steps of flame-front and burnt cells; 128
+    cells of each zone stay within the oracle's own one- and two-ulp spread
+    (same cap) of the oracle run."""
+    f = zones_field
+    rng = np.random.default_rng(3)
+    sel = np.concatenate([rng.choice(np.where(f.zone == z)[0], 128, replace=False) for z in range(3)])
+    T, p, Y = f.T[sel], f.p[sel], np.ascontiguousarray(f.Y[:, sel])
+    o = _opts(1, 0)
+    o.qmax = 2
+    Tg, Yg, sg, cg = run_gpu(torch, gm35, T, p, Y, f.dt, opts=o)
+    To, Yo, so, co = om35.integrate(T, p, Y, f.dt, qmax=2)[:4]
+    _say(f"[zones-qmax2] steps gpu/oracle mean {cg[:, 0].mean():.1f}/{co[:, 0].mean():.1f}")
+    assert np.all(sg == 0)
+    compare_cell_envelope("zones-qmax2", om35, T, p, Y, f.dt, Tg, Yg, sg, cg, To, Yo, so, co, okw={"qmax": 2})
+
+
 def test_thread_schedule_rejects_large_mechanism(torch, gm35):
     from paper_2312_13513_amd import chem
     dev = torch.device("cuda:0")
