@@ -209,8 +209,12 @@ const char *chem_last_error(void);
  *
  * A surrogate handle refers to its mechanism, which must outlive it.  The
  * surrogate grows workspace on first use (chem_surrogate_infer at a given
- * ncells); later calls of at most that size neither allocate nor
- * synchronise and may be captured in a HIP graph.
+ * ncells) or through chem_surrogate_reserve; later calls of at most that
+ * size neither allocate nor synchronise and may be captured in a HIP graph.
+ * A call that would have to grow the workspace while its stream is being
+ * captured fails with CHEM_EINVAL instead; buffers replaced by growth stay
+ * allocated until the handle is freed, so graphs captured earlier stay
+ * valid.
  * ------------------------------------------------------------------------ */
 typedef struct chem_surr_s *chem_surr;
 
@@ -261,6 +265,22 @@ int chem_surrogate_forward(chem_surr surr, const uint16_t *X, int64_t n, float *
  * same output bit for bit (same MFMA accumulation order, same epilogues). */
 int chem_surrogate_forward_path(chem_surr surr, const uint16_t *X, int64_t n, float *out, int64_t ldo,
                                 int32_t path, void *hip_stream);
+/* Size the inference workspace for calls of up to ncells cells (the same
+ * allocation the first chem_surrogate_infer of that size makes), so that
+ * such calls can then be captured.  Not capturable itself. */
+int chem_surrogate_reserve(chem_surr surr, int64_t ncells, void *hip_stream);
+/* Rows per inference pass of chem_surrogate_infer (encode, network, decode
+ * and checks run pass by pass over the cells): 0 = the library's choice
+ * (2,097,152 rows with the fused forward, 262,144 with the per-layer GEMMs);
+ * a smaller value caps it.  Results do not depend on it. */
+int chem_surrogate_set_pass_rows(chem_surr surr, int64_t rows);
+/* The per-layer path (path 1) with its hidden activations kept: H1, H2, H3
+ * (device, n x h1, n x h2, n x h3 BF16 bit patterns, row-major) receive the
+ * BF16 outputs of the three GELU layers and out the network output, as
+ * chem_surrogate_forward_path writes it.  A diagnostics call for layer-wise
+ * checks of the kernels; n <= 2^20. */
+int chem_surrogate_forward_trace(chem_surr surr, const uint16_t *X, int64_t n, uint16_t *H1, uint16_t *H2,
+                                 uint16_t *H3, float *out, int64_t ldo, void *hip_stream);
 /* Decode, temperature recovery and checks of n cells from a network output
  * (device, layout of chem_surrogate_forward): accepted cells take the
  * prediction in place, mask[i] = 1 marks the rejected ones (their state is

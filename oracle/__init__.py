@@ -66,6 +66,9 @@ def lib():
                                    C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _ip_opt, _ip_opt]
         L.om_bdf_user.argtypes = [C.c_int, USER_F, USER_F, C.c_void_p, _dp, C.c_double, C.c_double,
                                   C.c_double, C.c_int, C.c_int, _ip]
+        L.om_bdf_user_trace.argtypes = [C.c_int, USER_F, USER_F, C.c_void_p, _dp, C.c_double, C.c_double,
+                                        C.c_double, C.c_int, C.c_int, _ip, _dp, C.c_int, C.POINTER(C.c_int)]
+        L.om_order_change.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp]
         L.om_bdf_prescribed.argtypes = [C.c_int, USER_F, USER_F, C.c_void_p, C.c_int, C.c_double,
                                         _dp, _dp, C.c_int, _dp]
         L.om_rk4.argtypes = [C.c_void_p, C.c_double, _dp, C.c_double, C.c_int64]
@@ -197,6 +200,37 @@ def bdf_user(f, jac, y0, t_end: float, rtol=1e-8, atol=1e-12, max_steps=100000, 
     st = lib().om_bdf_user(N, cf, cj, None, y, float(t_end), float(rtol), float(atol), int(max_steps), int(qmax),
                            counters)
     return y, st, counters
+
+
+def bdf_user_trace(f, jac, y0, t_end: float, rtol=1e-8, atol=1e-12, max_steps=100000, qmax=5, cap=100000):
+    """bdf_user, also returning every accepted step as rows (t, h, q, dsm,
+    failed attempts before it was accepted)."""
+    y = np.array(y0, dtype=np.float64)
+    N = y.size
+    f.__out_size__ = N
+    cj_fn = lambda t, yy: np.asarray(jac(t, yy)).reshape(-1)
+    cj_fn.__out_size__ = N * N
+    cf, cj = _wrap_user(N, f), _wrap_user(N, cj_fn)
+    counters = np.zeros(6, dtype=np.int32)
+    trace = np.zeros(5 * cap)
+    nrec = C.c_int()
+    st = lib().om_bdf_user_trace(N, cf, cj, None, y, float(t_end), float(rtol), float(atol), int(max_steps),
+                                 int(qmax), counters, trace, int(cap), C.byref(nrec))
+    return y, st, counters, trace[: 5 * nrec.value].reshape(-1, 5).copy()
+
+
+def order_change(q: int, qnew: int, xi, l, e, z):
+    """The integrator's order change of a Nordsieck array z ((max(q,qnew)+1) x N)
+    with the step's xi[1..q+1] (xi[0] unused), l[0..q] and correction e."""
+    z = np.array(z, dtype=np.float64)
+    rows, N = z.shape
+    flat = np.ascontiguousarray(z.reshape(-1))
+    xi8 = np.zeros(8)
+    xi8[: len(xi)] = xi
+    l8 = np.zeros(8)
+    l8[: len(l)] = l
+    lib().om_order_change(N, int(q), int(qnew), xi8, l8, np.ascontiguousarray(e, dtype=np.float64), flat)
+    return flat.reshape(rows, N)
 
 
 def bdf_prescribed(f, jac, q: int, t0: float, z0, tau, hseq):

@@ -558,7 +558,52 @@ typedef struct {
     om_j_fn jac;
     void *ctx;
     int qmax;            /* highest order the step selection may raise to (1..BDF_QMAX) */
+    double *trace;       /* optional: per accepted step (t, h, q, dsm, failed attempts), at most trace_cap steps */
+    int trace_cap;
+    int *trace_n;
 } om_problem;
+
+/* Order change of the Nordsieck array after an accepted step (rows 0..q+1
+ * used), from the step's xi and l and its correction e.
+ * Down (qnew = q - 1): subtract z_q times x prod_{i=1..q-1} (x + xi_i), a
+ * polynomial that vanishes at x = 0 and at the q - 1 past points x = -xi_i,
+ * so the result interpolates the same values with degree q - 1.
+ * Up (qnew = q + 1): add e times (x / xi_{q+1}) Lambda_q(x), Lambda_q(x) =
+ * prod_{i=1..q} (1 + x / xi_i) with coefficients l, which also vanishes at x
+ * = 0 and at the q past points and brings in the degree q + 1 term. */
+static void order_change(int N, int q, int qnew, const double *xi, const double *l, const double *e,
+                         double z[][OM_NMAX])
+{
+    if (qnew == q - 1) {
+        double d[BDF_QMAX + 2];
+        d[0] = 0.0;
+        d[1] = 1.0;
+        for (int j = 2; j <= q; j++) d[j] = 0.0;
+        for (int i = 1; i <= q - 1; i++)
+            for (int j = i + 1; j >= 1; j--) d[j] = d[j - 1] + xi[i] * d[j];
+        for (int j = 1; j < q; j++)
+            for (int i = 0; i < N; i++) z[j][i] -= d[j] * z[q][i];
+    } else if (qnew == q + 1) {
+        for (int i = 0; i < N; i++) z[q + 1][i] = 0.0;
+        for (int j = 1; j <= q + 1; j++)
+            for (int i = 0; i < N; i++) z[j][i] += e[i] * l[j - 1] / xi[q + 1];
+    }
+}
+
+/* The order change on a flat array (rows 0..max(q, qnew), row j at
+ * zflat[j * N]): the same arithmetic as inside the integrator, exposed for
+ * tests of its interpolation property. */
+void om_order_change(int N, int q, int qnew, const double *xi, const double *l, const double *e,
+                     double *zflat)
+{
+    double z[BDF_QMAX + 2][OM_NMAX];
+    const int rows = (qnew > q ? qnew : q) + 1;
+    for (int j = 0; j < rows; j++)
+        for (int i = 0; i < N; i++) z[j][i] = zflat[j * N + i];
+    order_change(N, q, qnew, xi, l, e, z);
+    for (int j = 0; j < rows; j++)
+        for (int i = 0; i < N; i++) zflat[j * N + i] = z[j][i];
+}
 
 /* Controlled integration of y from t = 0 to t_end.  On failure y is restored
  * to its input and a non-zero status returned. */
@@ -757,6 +802,15 @@ static int bdf_integrate(const om_problem *P, double *y, double t_end, double rt
         }
         t = last ? t_end : t + h;
         cnt->nst++;
+        if (P->trace && *P->trace_n < P->trace_cap) {
+            double *r = P->trace + 5 * (*P->trace_n);
+            r[0] = t;
+            r[1] = h;
+            r[2] = q;
+            r[3] = dsm;
+            r[4] = nef + ncf;
+            (*P->trace_n)++;
+        }
         if (t >= t_end) break;
 
         /* ---- step size and order for the next step ---- */
@@ -811,24 +865,8 @@ static int bdf_integrate(const om_problem *P, double *y, double t_end, double rt
             }
         }
         /* history of step sizes (before any order change, the new z uses it) */
-        if (qnew == q - 1) {
-            /* drop to order q-1: subtract z_q * x * prod_{i=1..q-1} (x + xi_i) */
-            double d[BDF_QMAX + 2];
-            d[0] = 0.0;
-            d[1] = 1.0;
-            for (int j = 2; j <= q; j++) d[j] = 0.0;
-            for (int i = 1; i <= q - 1; i++)
-                for (int j = i + 1; j >= 1; j--) d[j] = d[j - 1] + xi[i] * d[j];
-            for (int j = 1; j < q; j++)
-                for (int i = 0; i < N; i++) z[j][i] -= d[j] * z[q][i];
-            q = qnew;
-            qwait = q + 1;
-            ehat_valid = 0;
-        } else if (qnew == q + 1) {
-            /* raise to order q+1: add e * (x / xi_{q+1}) * Lambda_q(x) */
-            for (int i = 0; i < N; i++) z[q + 1][i] = 0.0;
-            for (int j = 1; j <= q + 1; j++)
-                for (int i = 0; i < N; i++) z[j][i] += e[i] * l[j - 1] / xi[q + 1];
+        if (qnew != q) {
+            order_change(N, q, qnew, xi, l, e, z);
             q = qnew;
             qwait = q + 1;
             ehat_valid = 0;
@@ -945,15 +983,32 @@ static int user_j(void *ctx, double t, const double *y, double *J)
     return 0;
 }
 
+int om_bdf_user_trace(int N, om_user_f f, om_user_j j, void *ud, double *y, double t_end, double rtol,
+                      double atol, int max_steps, int qmax, int32_t *counters, double *trace, int trace_cap,
+                      int *trace_n);
+
 /* Controlled integration of a user ODE y' = f(t, y) over [0, t_end], orders
  * up to qmax (1..5, anything else means 5). */
 int om_bdf_user(int N, om_user_f f, om_user_j j, void *ud, double *y, double t_end, double rtol,
                 double atol, int max_steps, int qmax, int32_t *counters)
 {
+    return om_bdf_user_trace(N, f, j, ud, y, t_end, rtol, atol, max_steps, qmax, counters, NULL, 0, NULL);
+}
+
+/* The same, recording (t, h, q, dsm, failed attempts before acceptance) of
+ * every accepted step (at most trace_cap) into trace[5 * k ..]; *trace_n
+ * receives the number recorded. */
+int om_bdf_user_trace(int N, om_user_f f, om_user_j j, void *ud, double *y, double t_end, double rtol,
+                      double atol, int max_steps, int qmax, int32_t *counters, double *trace, int trace_cap,
+                      int *trace_n)
+{
     user_ctx u = {f, j, ud};
-    om_problem P = {N, user_f, user_j, &u, (qmax >= 1 && qmax <= BDF_QMAX) ? qmax : BDF_QMAX};
+    int nrec = 0;
+    om_problem P = {N, user_f, user_j, &u, (qmax >= 1 && qmax <= BDF_QMAX) ? qmax : BDF_QMAX,
+                    trace, trace_cap, &nrec};
     om_counts cnt;
     int st = bdf_integrate(&P, y, t_end, rtol, atol, max_steps, &cnt);
+    if (trace_n) *trace_n = nrec;
     if (counters) {
         counters[0] = cnt.nst;
         counters[1] = cnt.nfe;

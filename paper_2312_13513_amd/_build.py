@@ -2,6 +2,7 @@
 into an in-tree shared library ``libchem.so`` (explicit hipcc, no JIT cache)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -46,17 +47,22 @@ def build(verbose: bool = False) -> str:
     gendir = os.path.join(objdir, "gen")
     os.makedirs(objdir, exist_ok=True)
     gen_sources = codegen.write_generated(specialised_mechanisms(gendir), gendir)
-    objs = []
+    jobs = []
     for src in sources() + gen_sources:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         cmd = ["hipcc", *HIPCC_FLAGS, "-I", CSRC, "-x", "hip", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, stderr=subprocess.PIPE, text=True)
+        jobs.append((src, obj, cmd))
+    # one compiler process per source file, at most one per host core
+    width = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+    with concurrent.futures.ThreadPoolExecutor(width) as pool:
+        runs = list(pool.map(lambda j: subprocess.run(j[2], stderr=subprocess.PIPE, text=True), jobs))
+    for (src, _, _), r in zip(jobs, runs):
         if r.returncode != 0:
             sys.stderr.write(r.stderr)
             raise RuntimeError(f"hipcc failed on {src}")
-        objs.append(obj)
+    objs = [obj for _, obj, _ in jobs]
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)

@@ -91,6 +91,9 @@ def _load():
     L.chem_surrogate_adam.argtypes = [vp, C.c_double, vp]
     L.chem_surrogate_train.argtypes = [vp, dp, dp, dp, i64, dp, i64, i64, dp, C.c_int32, C.c_int32,
                                        C.c_double, C.c_double, dblp, vp]
+    L.chem_surrogate_forward_trace.argtypes = [vp, dp, i64, dp, dp, dp, dp, i64, vp]
+    L.chem_surrogate_reserve.argtypes = [vp, i64, vp]
+    L.chem_surrogate_set_pass_rows.argtypes = [vp, i64]
     L.chem_surrogate_save.argtypes = [vp, C.c_char_p]
     L.chem_surrogate_load.argtypes = [vp, C.c_char_p, C.POINTER(vp)]
     return L
@@ -108,7 +111,8 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_fit_norm", "chem_surrogate_encode", "chem_surrogate_forward", "chem_surrogate_forward_path",
             "chem_surrogate_apply", "chem_surrogate_infer", "chem_surrogate_grad",
             "chem_surrogate_get_grads", "chem_surrogate_set_grads", "chem_surrogate_adam",
-            "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load")
+            "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_reserve",
+            "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace")
 
 
 def lib():
@@ -339,6 +343,12 @@ class Surrogate:
         _check(_lib.chem_surrogate_forward_path(C.c_void_p(self.handle), _ptr(X), X.shape[0], _ptr(out),
                                                 out.shape[1], int(path), _stream(stream)))
 
+    def forward_trace(self, X, H1, H2, H3, out, stream=None):
+        """Per-layer forward keeping the BF16 hidden activations (int16 GPU
+        tensors of shape (n, h1), (n, h2), (n, h3))."""
+        _check(_lib.chem_surrogate_forward_trace(C.c_void_p(self.handle), _ptr(X), X.shape[0], _ptr(H1), _ptr(H2),
+                                                 _ptr(H3), _ptr(out), out.shape[1], _stream(stream)))
+
     def apply(self, T, p, Y, out, checks=None, mask=None, stream=None):
         _check(_lib.chem_surrogate_apply(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
                                          T.shape[0], _ptr(out), out.shape[1],
@@ -351,6 +361,14 @@ class Surrogate:
                                          T.shape[0], float(dt), C.byref(opts) if opts is not None else None,
                                          C.byref(checks) if checks is not None else None, _ptr(mask),
                                          _ptr(status), _ptr(fallback_count), _stream(stream)))
+
+    def reserve(self, ncells: int, stream=None):
+        """Size the inference workspace for calls of up to ncells cells."""
+        _check(_lib.chem_surrogate_reserve(C.c_void_p(self.handle), int(ncells), _stream(stream)))
+
+    def set_pass_rows(self, rows: int):
+        """Rows per inference pass (0 = the library's choice)."""
+        _check(_lib.chem_surrogate_set_pass_rows(C.c_void_p(self.handle), int(rows)))
 
     def grad(self, X, Yt, stream=None) -> float:
         loss = C.c_double()

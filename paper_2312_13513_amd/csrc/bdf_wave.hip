@@ -1039,6 +1039,13 @@ constexpr size_t kQbufLdsMax = 49152;     // reaction scratch of one wave kept i
 constexpr size_t kTileStageMax = 24576;   // tables + scratch of a tile block staged in LDS up to this size
 constexpr int64_t kDeferMinCells = 65536; // tile batches from this size defer Newton-matrix refreshes
 
+bool wave_uses_global_scratch(const DevMechView &m, int lanes)
+{
+    const size_t q7 = (size_t)7 * (m.R > 0 ? m.R : 1) * sizeof(double);
+    if (lanes == 16) return (size_t)m.table_bytes + 4 * q7 > kTileStageMax;
+    return q7 > kQbufLdsMax;
+}
+
 template <int NP, typename LT>
 static hipError_t launch_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p, double *Y,
                               int64_t ldY, int64_t n, double dt, const BdfParams &prm, int32_t *status,

@@ -135,6 +135,8 @@ int parse_mech(const char *path, HostMech &m)
 
 namespace {
 constexpr int kQueues = 64;
+constexpr int kScratchParts = 4;               // reaction-scratch partitions (calls in flight)
+constexpr size_t kScratchBudget = size_t(1) << 30;   // bytes of reaction scratch per mechanism, at most
 
 unsigned long long fnv1a64(const std::string &data)
 {
@@ -236,9 +238,17 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
     // flight on different streams do not share one
     unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);
     hipError_t e;
-    if (sched == 1 || sched == 2)
-        e = chem::launch_bdf_wave(m->view, m->wave, T, p, Y, ldY, n, dt, prm, status, counters, queue,
-                                  m->wave_scratch, m->wave_slots, o.precision == 1, sched == 2 ? 16 : 64, stream);
+    if (sched == 1 || sched == 2) {
+        const int lanes = sched == 2 ? 16 : 64;
+        double *qs = nullptr;
+        if (chem::wave_uses_global_scratch(m->view, lanes)) {
+            // calls in flight on different streams take different partitions
+            const unsigned part = __atomic_fetch_add(&m->next_part, 1u, __ATOMIC_RELAXED) % kScratchParts;
+            qs = m->wave_scratch + (size_t)part * m->wave_slots * 7 * (m->host.R > 0 ? m->host.R : 1);
+        }
+        e = chem::launch_bdf_wave(m->view, m->wave, T, p, Y, ldY, n, dt, prm, status, counters, queue, qs,
+                                  m->wave_slots, o.precision == 1, lanes, stream);
+    }
     else if (m->gen)
         e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, stream);
     else
@@ -361,8 +371,21 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     const size_t table_bytes = a16(off_inc + inc_flat.size() * sizeof(int));
     const size_t off_q = (table_bytes + 255) & ~size_t(255);
     const size_t off_ws = off_q + kQueues * 256;
-    const int wave_slots = 4096;   // cells in flight of the wave / tile kernels (global reaction scratch)
-    const size_t total = off_ws + (size_t)wave_slots * 7 * (R > 0 ? R : 1) * sizeof(double);
+    // global reaction scratch, only when a wave or tile variant needs it:
+    // kScratchParts partitions of up to 4096 slices (cells in flight)
+    chem::DevMechView probe{};
+    probe.K = K;
+    probe.R = R;
+    probe.table_bytes = (int32_t)table_bytes;
+    const size_t slice = (size_t)7 * (R > 0 ? R : 1) * sizeof(double);
+    const bool need_ws = (chem::wave_kernel_rows(K + 1) > 0 && chem::wave_uses_global_scratch(probe, 64)) ||
+                         (K + 1 <= 16 && chem::wave_uses_global_scratch(probe, 16));
+    int wave_slots = 0;
+    if (need_ws) {
+        size_t slots = kScratchBudget / (kScratchParts * slice);
+        wave_slots = (int)(slots < 4096 ? (slots < 64 ? 64 : slots) : 4096);
+    }
+    const size_t total = off_ws + (size_t)kScratchParts * wave_slots * slice;
     int prev = 0;
     if ((rc = check_hip(hipGetDevice(&prev), "hipGetDevice")) != CHEM_OK) {
         delete m;
@@ -405,7 +428,7 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     m->queues = (unsigned long long *)(blk + off_q);
     m->wave.inc_off = (const int *)(blk + off_io);
     m->wave.inc = (const int2 *)(blk + off_inc);
-    m->wave_scratch = (double *)(blk + off_ws);
+    m->wave_scratch = wave_slots > 0 ? (double *)(blk + off_ws) : nullptr;
     m->wave_slots = wave_slots;
     *out = m;
     return CHEM_OK;

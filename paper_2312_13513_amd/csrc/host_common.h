@@ -44,8 +44,12 @@ struct chem_mech_s {
     const chem::GenEntry *gen = nullptr;    // mechanism-specialised kernels, if compiled
     std::string variant = "table";
     chem::WaveTables wave{};                // species -> reaction incidence (wave kernel)
-    double *wave_scratch = nullptr;         // per-wave reaction buffers (7 R doubles each)
+    // reaction scratch of the kernels whose 7 R doubles per cell in flight do
+    // not fit in LDS: kScratchParts partitions of wave_slots slices, one
+    // partition per call in rotation (NULL when no variant needs it)
+    double *wave_scratch = nullptr;
     int wave_slots = 0;
+    unsigned next_part = 0;
     // autotuned schedule per precision (used when opts.schedule == -2)
     struct Tuned {
         bool valid = false;

@@ -476,15 +476,15 @@ __global__ void __launch_bounds__(256, 3) apply_kernel(ApplyArgs a, double *__re
             Y1[k] = 0.0;
             if (k < K) {
                 const double y0 = Y[(int64_t)k * ldY + i];
-                float ok;
+                float o;   // the network's output for species k
                 if constexpr (V4) {
                     // k + 3 < round_up(K, 4) <= nout_pad: inside the row
                     if (k % 4 == 0) o4 = *(const float4 *)(out + i * nout_pad + k);
-                    ok = (k % 4 == 0) ? o4.x : (k % 4 == 1) ? o4.y : (k % 4 == 2) ? o4.z : o4.w;
+                    o = (k % 4 == 0) ? o4.x : (k % 4 == 1) ? o4.y : (k % 4 == 2) ? o4.z : o4.w;
                 } else {
-                    ok = out[i * nout_pad + k];
+                    o = out[i * nout_pad + k];
                 }
-                const double v = y0 + a.mu_y[k] + a.sig_y[k] * (double)ok;
+                const double v = y0 + a.mu_y[k] + a.sig_y[k] * (double)o;
                 Y1[k] = v;
                 ok = ok && isfinite(v);
                 sum += v;

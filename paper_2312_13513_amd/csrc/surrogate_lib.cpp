@@ -28,24 +28,40 @@ constexpr double kPi = 3.14159265358979323846;
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// A device workspace that only grows.  Growing is refused while the stream
+// is being captured (a graph must not record an allocation), and a replaced
+// buffer is kept until release(): a graph captured earlier may still refer
+// to it.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
-    int grow(size_t want)
+    std::vector<void *> retired;
+    int grow(size_t want, hipStream_t st)
     {
         if (want <= bytes) return CHEM_OK;
-        if (p) hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        if (hipMalloc(&p, want) != hipSuccess) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CHEM_EHIP, "hipStreamIsCapturing failed");
+        }
+        if (cs != hipStreamCaptureStatusNone)
+            return fail(CHEM_EINVAL, "the surrogate workspace is too small for this call and cannot grow while "
+                                     "the stream is captured: call chem_surrogate_reserve (or the same call "
+                                     "eagerly) before capturing");
+        void *q = nullptr;
+        if (hipMalloc(&q, want) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CHEM_ENOMEM, "surrogate workspace allocation failed");
         }
+        if (p) retired.push_back(p);
+        p = q;
         bytes = want;
         return CHEM_OK;
     }
     void release()
     {
+        for (void *r : retired) hipFree(r);
+        retired.clear();
         if (p) hipFree(p);
         p = nullptr;
         bytes = 0;
@@ -95,6 +111,7 @@ struct chem_surr_s {
     int64_t fb_cap = 0;
     DevBuf io;                        // encoded rows and outputs of the fused inference pass
     int64_t io_rows = 0;
+    int64_t pass_rows = 0;            // rows per inference pass (0: the library's choice)
 };
 
 namespace {
@@ -129,12 +146,12 @@ size_t acts_bytes(const chem_surr_s *s, int64_t rows, bool train)
     return b;
 }
 
-int ensure_acts(chem_surr_s *s, int64_t rows, bool train)
+int ensure_acts(chem_surr_s *s, int64_t rows, bool train, hipStream_t st)
 {
     if (rows <= s->act_rows && (!train || s->act_train)) return CHEM_OK;
     const int64_t r = rows > s->act_rows ? rows : s->act_rows;
     const bool t = train || s->act_train;
-    int rc = s->act.grow(acts_bytes(s, r, t));
+    int rc = s->act.grow(acts_bytes(s, r, t), st);
     if (rc != CHEM_OK) return rc;
     s->act_rows = r;
     s->act_train = t;
@@ -305,14 +322,13 @@ struct Fallback {
     int64_t cap;
 };
 
-int ensure_fb(chem_surr_s *s, int64_t n, Fallback &f)
+int ensure_fb(chem_surr_s *s, int64_t n, Fallback &f, hipStream_t st)
 {
     const int K = s->K;
     if (n > s->fb_cap) {
-        s->fb_cap = 0;
         const size_t b = carve_size<int32_t>(n) + 2 * carve_size<double>(n) + carve_size<double>(n * K) +
                          carve_size<int32_t>(n);
-        int rc = s->fb.grow(b);
+        int rc = s->fb.grow(b, st);
         if (rc != CHEM_OK) return rc;
         s->fb_cap = n;
     }
@@ -590,17 +606,33 @@ int chem_surrogate_forward_path(chem_surr s, const uint16_t *X, int64_t n, float
     if (path != 1 && fused_ok(s)) return check_hip(forward_fused(s, (const bf16_t *)X, n, out, ldo, (hipStream_t)stream),
                                                    "fused forward");
     const int64_t rows = n < kChunk ? n : kChunk;
-    rc = ensure_acts(s, rows, false);
+    hipStream_t st = (hipStream_t)stream;
+    rc = ensure_acts(s, rows, false, st);
     if (rc != CHEM_OK) return rc;
     Acts a = carve_acts(s);
     float *noU[3] = {nullptr, nullptr, nullptr};
-    hipStream_t st = (hipStream_t)stream;
     for (int64_t r0 = 0; r0 < n; r0 += kChunk) {
         const int rr = (int)(n - r0 < kChunk ? n - r0 : kChunk);
         hipError_t e = forward(s, X + r0 * kInPad, rr, a.H, noU, out + r0 * ldo, ldo, st, true);
         if (e != hipSuccess) return check_hip(e, "forward");
     }
     return CHEM_OK;
+}
+
+int chem_surrogate_forward_trace(chem_surr s, const uint16_t *X, int64_t n, uint16_t *H1, uint16_t *H2,
+                                 uint16_t *H3, float *out, int64_t ldo, void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (n == 0) return CHEM_OK;
+    if (n < 0 || n > (1 << 20) || ldo < s->nout_pad)
+        return fail(CHEM_EINVAL, "need 0 <= ncells <= 2^20 and ldo >= K rounded up to 16");
+    if (!is_device_ptr(X) || !is_device_ptr(H1) || !is_device_ptr(H2) || !is_device_ptr(H3) || !is_device_ptr(out))
+        return fail(CHEM_EINVAL, "X, H1, H2, H3 and out must be device pointers");
+    bf16_t *const H[3] = {(bf16_t *)H1, (bf16_t *)H2, (bf16_t *)H3};
+    float *noU[3] = {nullptr, nullptr, nullptr};
+    return check_hip(forward(s, (const bf16_t *)X, (int)n, H, noU, out, ldo, (hipStream_t)stream, true),
+                     "forward trace");
 }
 
 int chem_surrogate_apply(chem_surr s, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
@@ -620,14 +652,77 @@ int chem_surrogate_apply(chem_surr s, double *T, const double *p, double *Y, int
     if (checks) c = *checks;
     if (ldo != s->nout_pad) return fail(CHEM_EINVAL, "ldo must equal K rounded up to 16 here");
     Fallback fb;
-    rc = ensure_fb(s, n, fb);
-    if (rc != CHEM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
+    rc = ensure_fb(s, n, fb, st);
+    if (rc != CHEM_OK) return rc;
     rc = check_hip(chem::launch_zero_i64(s->scalars, 1, st), "zero");
     if (rc != CHEM_OK) return rc;
     return check_hip(chem::launch_apply(apply_args(s, c), T, p, Y, ldY, n, 0, out, (int)ldo, mask, nullptr,
                                         fb.list, s->scalars, st),
                      "apply");
+}
+
+namespace {
+
+// Workspace of an inference call over n cells: the encoded rows and outputs
+// of one pass (fused forward) or every activation of one pass (per-layer
+// GEMMs), and the fallback compaction buffers for all n cells.
+struct InferWork {
+    bool fused = false;
+    int64_t chunk = 0;   // rows per pass
+    bf16_t *X = nullptr;
+    float *OUT = nullptr;
+    Acts a{};
+    Fallback fb{};
+};
+
+int infer_workspace(chem_surr_s *s, int64_t n, hipStream_t st, InferWork &w)
+{
+    // the fused forward needs only the encoded rows and the outputs, so it
+    // takes larger passes; the layered GEMMs keep every activation
+    w.fused = fused_ok(s);
+    w.chunk = w.fused ? kFusedChunk : kChunk;
+    if (s->pass_rows > 0 && s->pass_rows < w.chunk) w.chunk = s->pass_rows;
+    const int64_t rows = n < w.chunk ? n : w.chunk;
+    int rc;
+    if (w.fused) {
+        if (rows > s->io_rows) {
+            rc = s->io.grow(carve_size<bf16_t>(rows * kInPad) + carve_size<float>(rows * s->nout_pad), st);
+            if (rc != CHEM_OK) return rc;
+            s->io_rows = rows;
+        }
+        Carver ic{(char *)s->io.p};
+        w.X = ic.take<bf16_t>(s->io_rows * kInPad);
+        w.OUT = ic.take<float>(s->io_rows * s->nout_pad);
+    } else {
+        rc = ensure_acts(s, rows, false, st);
+        if (rc != CHEM_OK) return rc;
+        w.a = carve_acts(s);
+        w.X = w.a.X;
+        w.OUT = w.a.OUT;
+    }
+    return ensure_fb(s, n, w.fb, st);
+}
+
+}  // namespace
+
+int chem_surrogate_reserve(chem_surr s, int64_t ncells, void *stream)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (ncells < 0 || ncells > INT32_MAX) return fail(CHEM_EINVAL, "ncells must be in 0..2^31-1");
+    if (ncells == 0) return CHEM_OK;
+    InferWork w;
+    return infer_workspace(s, ncells, (hipStream_t)stream, w);
+}
+
+int chem_surrogate_set_pass_rows(chem_surr s, int64_t rows)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (rows < 0 || rows > INT32_MAX) return fail(CHEM_EINVAL, "rows must be in 0..2^31-1");
+    s->pass_rows = rows;
+    return CHEM_OK;
 }
 
 int chem_surrogate_infer(chem_surr s, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
@@ -649,35 +744,17 @@ int chem_surrogate_infer(chem_surr s, double *T, const double *p, double *Y, int
     chem_surrogate_default_checks(&c);
     if (checks) c = *checks;
     const int K = s->K;
-    // the fused forward needs only the encoded rows and the outputs, so it
-    // takes larger passes; the layered GEMMs keep every activation
-    const bool fused = fused_ok(s);
-    const int64_t chunk = fused ? kFusedChunk : kChunk;
-    const int64_t rows = n < chunk ? n : chunk;
-    bf16_t *Xc = nullptr;
-    float *OUTc = nullptr;
-    Acts a{};
-    if (fused) {
-        if (rows > s->io_rows) {
-            rc = s->io.grow(carve_size<bf16_t>(rows * kInPad) + carve_size<float>(rows * s->nout_pad));
-            if (rc != CHEM_OK) return rc;
-            s->io_rows = rows;
-        }
-        Carver ic{(char *)s->io.p};
-        Xc = ic.take<bf16_t>(s->io_rows * kInPad);
-        OUTc = ic.take<float>(s->io_rows * s->nout_pad);
-    } else {
-        rc = ensure_acts(s, rows, false);
-        if (rc != CHEM_OK) return rc;
-        a = carve_acts(s);
-        Xc = a.X;
-        OUTc = a.OUT;
-    }
-    Fallback fb;
-    rc = ensure_fb(s, n, fb);
-    if (rc != CHEM_OK) return rc;
-    float *noU[3] = {nullptr, nullptr, nullptr};
     hipStream_t st = (hipStream_t)stream;
+    InferWork w;
+    rc = infer_workspace(s, n, st, w);
+    if (rc != CHEM_OK) return rc;
+    const bool fused = w.fused;
+    const int64_t chunk = w.chunk;
+    bf16_t *Xc = w.X;
+    float *OUTc = w.OUT;
+    Acts &a = w.a;
+    Fallback &fb = w.fb;
+    float *noU[3] = {nullptr, nullptr, nullptr};
     int64_t *count = fallback_count ? fallback_count : s->scalars;
     rc = check_hip(chem::launch_zero_i64(count, 1, st), "zero");
     if (rc != CHEM_OK) return rc;
@@ -712,10 +789,10 @@ int chem_surrogate_grad(chem_surr s, const uint16_t *X, const float *Yt, int64_t
     if (rc != CHEM_OK) return rc;
     if (n < 1 || n > (1 << 20) || ldt < s->K) return fail(CHEM_EINVAL, "need 1 <= n <= 2^20 and ldt >= K");
     if (!is_device_ptr(X) || !is_device_ptr(Yt)) return fail(CHEM_EINVAL, "X and Yt must be device pointers");
-    rc = ensure_acts(s, n, true);
+    hipStream_t st = (hipStream_t)stream;
+    rc = ensure_acts(s, n, true, st);
     if (rc != CHEM_OK) return rc;
     Acts a = carve_acts(s);
-    hipStream_t st = (hipStream_t)stream;
     // targets into the padded layout
     rc = check_hip(hipMemsetAsync(a.Yb, 0, (size_t)n * s->nout_pad * sizeof(float), st), "clear");
     if (rc != CHEM_OK) return rc;
@@ -784,10 +861,10 @@ int chem_surrogate_train(chem_surr s, const double *T, const double *p, const do
         return fail(CHEM_EINVAL, "arrays must be device pointers");
     hipStream_t st = (hipStream_t)stream;
     const int64_t rows = batch < n ? batch : n;
-    rc = ensure_acts(s, rows, true);
+    rc = ensure_acts(s, rows, true, st);
     if (rc != CHEM_OK) return rc;
     DevBuf data;
-    rc = data.grow(carve_size<bf16_t>(n * kInPad) + carve_size<float>(n * s->nout_pad));
+    rc = data.grow(carve_size<bf16_t>(n * kInPad) + carve_size<float>(n * s->nout_pad), st);
     if (rc != CHEM_OK) return rc;
     Carver dc{(char *)data.p};
     bf16_t *Xall = dc.take<bf16_t>(n * kInPad);

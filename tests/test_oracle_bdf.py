@@ -327,3 +327,110 @@ def test_maximum_order_option_on_cells(om9, mech_dir):
     assert np.all(s5 == 0) and np.all(s2 == 0)
     assert np.all(c2[:, 0] >= c5[:, 0]) and c2[:, 0].sum() > c5[:, 0].sum()
     assert np.max(np.abs(T2 - T5)) < 1e-3
+
+
+def test_initial_step_and_first_step_error_closed_form(oracle_lib):
+    """Step selection pinned on y' = lam y, y(0) = 1 (a linear problem, so the
+    difference quotient of the initial-step estimate is exact):
+      * h0 = 0.5 sqrt(2 / (lam^2 w)), w = 1 / (rtol + atol): half the step
+        whose second-derivative error estimate equals the tolerance;
+      * the first step is backward Euler from the Taylor start (Nordsieck
+        (1, h lam)): its correction is e = (h lam)^2 / (1 - h lam) and, with
+        no past steps, the error constant is 1/2, so dsm_1 = |e| w / 2; this
+        estimate equals the true local error exp(h lam) - 1/(1 - h lam) to
+        leading order in h lam;
+      * that error, dsm_1 = 1/4, asks for a step factor (6 dsm_1)^(-1/2) < 1.5,
+        so the second step keeps h_1."""
+    for lam, rtol, atol in ((-1.0, 1e-6, 1e-12), (-250.0, 1e-8, 1e-14), (3.0, 1e-7, 1e-12)):
+        f = lambda t, y, lam=lam: lam * y
+        j = lambda t, y, lam=lam: np.array([[lam]])
+        y, st, c, tr = oracle_lib.bdf_user_trace(f, j, [1.0], 40.0 / abs(lam), rtol=rtol, atol=atol)
+        assert st == 0 and tr.shape[0] == c[0]
+        w = 1.0 / (rtol + atol)
+        h0 = 0.5 * math.sqrt(2.0 / (lam * lam * w))
+        assert tr[0, 1] == pytest.approx(h0, rel=1e-12)
+        assert tr[0, 0] == pytest.approx(h0, rel=1e-15) and tr[0, 2] == 1
+        x = h0 * lam
+        e = x * x / (1.0 - x)
+        assert tr[0, 3] == pytest.approx(0.5 * abs(e) * w, rel=1e-9)
+        true_err = abs(math.exp(x) - 1.0 / (1.0 - x))
+        assert (tr[0, 3] / w) / true_err == pytest.approx(1.0, abs=3 * abs(x))
+        assert tr[0, 3] == pytest.approx(0.25, rel=1e-2)
+        assert tr[1, 1] == tr[0, 1]
+
+
+def test_order_sequence_on_smooth_decay(oracle_lib):
+    """Order selection on y' = -y over [0, 25] at tight tolerances (a smooth
+    solution, where higher orders pay): the order starts at 1, changes by one
+    at a time, is kept at least q + 1 steps after each change (2 at the
+    start), climbs to the cap, and every accepted step meets the tolerance;
+    the cap itself is honoured.  Step sizes, between accepted steps whose
+    successor passed at its first attempt: h never shrinks; a change is at
+    least a factor 1.5 and at most 10 (1e4 after the first step); where the
+    order stays and h changes below the cap, the same-order error predicted
+    for the new step, dsm (h_new/h)^(q+1), is one sixth of the tolerance
+    (safety factor 6).  The last step lands on t_end."""
+    f = lambda t, y: -y
+    j = lambda t, y: np.array([[-1.0]])
+    for qmax in (5, 3):
+        y, st, c, tr = oracle_lib.bdf_user_trace(f, j, [1.0], 25.0, rtol=1e-10, atol=1e-16, qmax=qmax)
+        assert st == 0
+        q = tr[:, 2].astype(int)
+        assert q[0] == 1 and q.max() == qmax and q.min() >= 1
+        assert np.all(np.abs(np.diff(q)) <= 1)
+        change = np.where(np.diff(q) != 0)[0] + 1          # first step at a new order
+        runs = np.diff(np.concatenate([[0], change]))        # lengths of the completed runs
+        assert runs[0] >= 2
+        assert np.all(runs[1:] >= q[change[:-1]] + 1), (q.tolist(),)
+        assert np.all(tr[:, 3] <= 1.0)
+        assert abs(y[0] - math.exp(-25.0)) <= 1e2 * 1e-10 * math.exp(-25.0) + 1e-14
+        assert tr[-1, 0] == 25.0
+        ratio = tr[1:-1, 1] / tr[:-2, 1]                    # last step clipped to t_end: excluded
+        clean = tr[1:-1, 4] == 0
+        assert clean.sum() >= 0.9 * ratio.size
+        cap = np.where(np.arange(ratio.size) == 0, 1e4, 10.0)
+        ok = (ratio == 1.0) | ((ratio >= 1.5 * (1 - 1e-12)) & (ratio <= cap * (1 + 1e-12)))
+        assert np.all(ok[clean])
+        same = clean & (q[1:-1] == q[:-2]) & (ratio != 1.0) & (ratio < cap * (1 - 1e-12))
+        pred = 6.0 * tr[:-2, 3] * ratio ** (q[:-2] + 1)
+        assert same.sum() >= 5
+        assert np.allclose(pred[same], 1.0, rtol=1e-4), pred[same]
+
+
+def _lambda_coeffs(xi, q):
+    """Coefficients (ascending) of prod_{i=1..q} (1 + x / xi_i)."""
+    c = np.array([1.0])
+    for i in range(1, q + 1):
+        c = np.convolve(c, [1.0, 1.0 / xi[i]])
+    return c
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 5])
+def test_order_change_keeps_the_interpolated_values(oracle_lib, q):
+    """The Nordsieck order change, checked as polynomials in x = (t - t_n)/h:
+    lowering to q - 1 keeps the values at x = 0 and at the q - 1 most recent
+    past points x = -xi_i and drops the degree-q term; raising to q + 1 keeps
+    the values at x = 0 and at the q past points and adds exactly
+    e (x / xi_{q+1}) prod_{i<=q} (1 + x / xi_i)."""
+    rng = np.random.default_rng(q)
+    N = 3
+    xi = np.zeros(q + 2)
+    xi[1] = 1.0
+    for i in range(2, q + 2):
+        xi[i] = xi[i - 1] + rng.uniform(0.3, 2.0)
+    z = rng.normal(size=(q + 2, N))
+    z[q + 1] = 0.0
+    lam = _lambda_coeffs(xi, q)
+    e = rng.normal(size=N)
+
+    def P(zz, deg, x):
+        return sum(zz[k] * x ** k for k in range(deg + 1))
+
+    down = oracle_lib.order_change(q, q - 1, xi, lam, e, z[: q + 1])
+    for x in [0.0] + [-xi[i] for i in range(1, q)]:
+        assert np.allclose(P(down, q - 1, x), P(z, q, x), rtol=1e-12, atol=1e-12)
+    up = oracle_lib.order_change(q, q + 1, xi, lam, e, z)
+    for x in [0.0] + [-xi[i] for i in range(1, q + 1)]:
+        assert np.allclose(P(up, q + 1, x), P(z, q, x), rtol=1e-12, atol=1e-12)
+    added = np.convolve([0.0, 1.0 / xi[q + 1]], lam)     # (x / xi_{q+1}) Lambda_q(x)
+    assert np.allclose(up[: q + 2] - z[: q + 2], np.outer(added, e), rtol=1e-13, atol=1e-14)
