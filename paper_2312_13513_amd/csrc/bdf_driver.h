@@ -14,6 +14,8 @@
 //   rhs(p, y[K+1], f[K+1])   and   jac(p, y[K+1], J[(K+1)*(K+1)]).
 #pragma once
 
+#include <utility>
+
 #include "chem_internal.h"
 
 namespace chem {
@@ -33,82 +35,108 @@ __device__ __forceinline__ double reg_value(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Factor in place; ties keep the upper row.  The pivot row of column k is
-// kept in bits 4k..4k+3 of one 64-bit word (N <= 16).
+// Compile-time loops: f(std::integral_constant<int, i>) for i in [B, E).  The
+// index is a constant expression in the body, so every array access it makes
+// is static whatever the loop unroller decides (a dynamic index would push
+// the whole per-lane state out of registers into scratch memory).
+template <int B, class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, B + I>{}), ...);
+}
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (E > B) static_for_impl<B>(f, std::make_integer_sequence<int, E - B>{});
+}
+
+// Factor in place; ties keep the upper row (the pivot is the first row of
+// largest magnitude).  Rows are exchanged by selects on the pivot index; the
+// pivot row of column k is kept in bits 4k..4k+3 of one 64-bit word (N <= 16).
+// Operation order per element as a textbook LU: l = m_rk / m_kk, then
+// m_rc -= l m_kc for c = k+1..N-1.
 template <int N>
 __device__ __forceinline__ bool lu_factor(double *M, unsigned long long &piv)
 {
     static_assert(N <= 16, "packed pivots hold at most 16 rows");
     bool ok = true;
     piv = 0ull;
-#pragma unroll
-    for (int k = 0; k < N; k++) {
+    static_for<0, N>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
         int pk = k;
         double best = fabs(M[k * N + k]);
-#pragma unroll
-        for (int r = k + 1; r < N; r++) {
+        static_for<k + 1, N>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
             const double v = fabs(M[r * N + k]);
             if (v > best) {
                 best = v;
                 pk = r;
             }
-        }
+        });
         piv |= (unsigned long long)pk << (4 * k);
         ok = ok && (best != 0.0);
-        if (pk != k) {
-#pragma unroll
-            for (int c = 0; c < N; c++) {
-                const double mk = reg_value(M[k * N + c]);
-                double nk = mk;
-#pragma unroll
-                for (int r = k + 1; r < N; r++) {
-                    const double mr = reg_value(M[r * N + c]);
-                    const bool sw = (pk == r);
-                    nk = sw ? mr : nk;
-                    M[r * N + c] = sw ? mk : mr;
-                }
-                M[k * N + c] = nk;
+        if constexpr (k + 1 < N) {
+            if (pk != k) {
+                static_for<0, N>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    const double mk = reg_value(M[k * N + c]);
+                    double nk = mk;
+                    static_for<k + 1, N>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        const double mr = reg_value(M[r * N + c]);
+                        const bool sw = (pk == r);
+                        nk = sw ? mr : nk;
+                        M[r * N + c] = sw ? mk : mr;
+                    });
+                    M[k * N + c] = nk;
+                });
             }
         }
-        const double inv = 1.0 / M[k * N + k];
-#pragma unroll
-        for (int r = k + 1; r < N; r++) {
-            const double l = M[r * N + k] * inv;
+        static_for<k + 1, N>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            const double l = M[r * N + k] / M[k * N + k];
             M[r * N + k] = l;
-#pragma unroll
-            for (int c = k + 1; c < N; c++) M[r * N + c] -= l * M[k * N + c];
-        }
-    }
+            static_for<k + 1, N>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                M[r * N + c] -= l * M[k * N + c];
+            });
+        });
+    });
     return ok;
 }
 
 template <int N>
 __device__ __forceinline__ void lu_solve(const double *M, unsigned long long piv, double *b)
 {
-#pragma unroll
-    for (int k = 0; k < N; k++) {
+    static_for<0, N>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
         const int pk = (int)((piv >> (4 * k)) & 15ull);
         const double bk = reg_value(b[k]);
         double nk = bk;
-#pragma unroll
-        for (int r = k + 1; r < N; r++) {
+        static_for<k + 1, N>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
             const double br = reg_value(b[r]);
             const bool sw = (pk == r);
             nk = sw ? br : nk;
             b[r] = sw ? bk : br;
-        }
+        });
         b[k] = nk;
-    }
-#pragma unroll
-    for (int r = 1; r < N; r++)
-#pragma unroll
-        for (int c = 0; c < r; c++) b[r] -= M[r * N + c] * b[c];
-#pragma unroll
-    for (int r = N - 1; r >= 0; r--) {
-#pragma unroll
-        for (int c = r + 1; c < N; c++) b[r] -= M[r * N + c] * b[c];
+    });
+    static_for<1, N>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        static_for<0, r>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            b[r] -= M[r * N + c] * b[c];
+        });
+    });
+    static_for<0, N>([&](auto ri) {
+        constexpr int r = N - 1 - decltype(ri)::value;
+        static_for<r + 1, N>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            b[r] -= M[r * N + c] * b[c];
+        });
         b[r] /= M[r * N + r];
-    }
+    });
 }
 
 // ---------------------------------------------------------------------------
