@@ -112,7 +112,7 @@ def traffic_for(workload: str, kernel: str):
 def kernel_name(mech, schedule: int, precision: int, n: int) -> str:
     lt = "float" if precision == 1 else "double"
     if schedule < 0:   # the library's own choice
-        schedule = 2 if mech.N <= 16 else 1
+        schedule = 0 if (mech.variant.startswith("specialised:") and precision == 0) else (2 if mech.N <= 16 else 1)
     if schedule == 2:   # refreshes deferred from 65,536 cells on
         return f"bdf_tile_kernel<{12 if mech.N <= 12 else 16},{lt},true,{'true' if n >= 65536 else 'false'}>"
     if schedule == 1 or precision == 1 or (mech.variant == "table" and mech.K > 9):
@@ -266,7 +266,8 @@ def run_integrator(args, workload: str):
         "config": {"workload": f"{desc}, dt={field.dt:g} s, rtol 1e-8, atol 1e-12",
                    "ncells": n, "species": K, "reactions": R, "dt": field.dt,
                    "schedule": ("tile: 16 lanes per cell, 4 cells per wave" if kname.startswith("bdf_tile") else
-                                "wave per cell" if kname.startswith("bdf_wave") else "thread per cell")},
+                                "wave per cell" if kname.startswith("bdf_wave") else
+                                "thread per cell, mechanism compiled in")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kname,
                      "kernel_ms": avg_kern_s * 1e3, "flops_per_launch": fl["total"],

@@ -69,8 +69,9 @@ typedef struct {
                            differ from FP64 at the level of the integration
                            tolerance) */
     int32_t schedule;   /* -2 = the autotuned choice (chem_autotune), else as -1;
-                           -1 = library choice (the tile schedule when K <= 15,
-                           else one wave per cell), 0 = one thread per cell
+                           -1 = library choice (one thread per cell for a
+                           compiled-in mechanism in FP64, else the tile schedule
+                           when K <= 15, else one wave per cell), 0 = one thread per cell
                            (FP64 only; K <= 9 table kernel or
                            a compiled-in mechanism), 1 = one 64-lane wave per
                            cell (any K <= 63), 2 = tile: 16 lanes per cell, four

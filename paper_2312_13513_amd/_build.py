@@ -19,6 +19,21 @@ HIPCC_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
                "-I", INCLUDE, "-Wall"]
 
 
+# The one-thread-per-cell integrators keep a whole cell's state per lane.
+# Machine-level loop-invariant code motion hoists every FP64 constant of the
+# mechanism (and every per-element slot address) out of the cell loop into
+# registers, which then spill to scratch (about 1 KB per lane); without it
+# the kernels need no scratch at all.
+NO_MACHINE_LICM = ["-mllvm", "-disable-machine-licm"]
+
+
+def per_file_flags(src: str) -> list:
+    name = os.path.basename(src)
+    if name.startswith("gen_") or name == "chem_kernels.hip":
+        return NO_MACHINE_LICM
+    return []
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
@@ -50,7 +65,7 @@ def build(verbose: bool = False) -> str:
     jobs = []
     for src in sources() + gen_sources:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = ["hipcc", *HIPCC_FLAGS, "-I", CSRC, "-x", "hip", "-c", src, "-o", obj]
+        cmd = ["hipcc", *HIPCC_FLAGS, *per_file_flags(src), "-I", CSRC, "-x", "hip", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         jobs.append((src, obj, cmd))

@@ -178,7 +178,12 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
     # Species block accumulated straight into J: J_kl += (W_k/W_l) nu_k dq/dC_l.
     # A C (needed for the density/mean-molar-mass chain rule) follows from the
     # homogeneity of mass action: sum_l C_l dq/dC_l = m_f fwd - m_r rev.
-    out.append("    __device__ __forceinline__ void jac(double p, const double *__restrict__ y, double *__restrict__ J) const")
+    # Sums over species of per-species reaction sums are taken reaction by
+    # reaction instead (sum_k h_k sum_r nu_kr x_r = sum_r x_r dh_r), so only
+    # one accumulator per species (sum_r nu_kr (q_r - qh_r)) and four scalars
+    # stay live beside J while the reactions are walked.
+    out.append("    template <class JA>")
+    out.append("    __device__ __forceinline__ void jac(double p, const double *__restrict__ y, JA J) const")
     out.append("    {")
     out.append(f"        const double T = y[{K}];")
     out.append("        const double invT = 1.0 / T;")
@@ -198,7 +203,9 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
                 for l in set(sr) | set(sp):
                     touched.add((k, l))
     for k in range(K):
-        out.append(f"        double w{k} = 0.0, wT{k} = 0.0, AC{k} = 0.0;")
+        out.append(f"        double v{k} = 0.0;")
+        out.append(f"        J[{k * N + K}] = 0.0;")
+    out.append("        double sh = 0.0, shAC = 0.0, shT = 0.0, scp = 0.0;")
     for k in range(K):
         for l in range(K):
             if (k, l) in touched:
@@ -210,6 +217,7 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
         dnu = len(sp) - len(sr)
         dg = " + ".join(f"g{k}" for k in sp) + " - " + " - ".join(f"g{k}" for k in sr)
         dh = " + ".join(f"h{k}" for k in sp) + " - " + " - ".join(f"h{k}" for k in sr)
+        dcp = " + ".join(f"cp{k}" for k in sp) + " - " + " - ".join(f"cp{k}" for k in sr)
         out.append(f"        {{   // reaction {i}")
         out.append(f"            const double lnkf = {_lit(lnA)} + {_lit(b)} * lnT - {_lit(Ea / RU)} * invT;")
         lnkr = f"lnkf + ({dg})" + (f" - {float(dnu)!r} * ln_c0" if dnu else "")
@@ -219,9 +227,16 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
         out.append(f"            const double rev = kr * {_prod_expr(sp)};")
         out.append("            const double q = fwd - rev;")
         out.append(f"            const double qh = {float(len(sr))!r} * fwd - {float(len(sp))!r} * rev;")
+        out.append(f"            const double dh = {dh};")
         out.append(f"            const double dlnkf = ({_lit(b)} + {_lit(Ea / RU)} * invT) * invT;")
-        out.append(f"            const double dlnkr = dlnkf - (({dh}) - {float(dnu)!r}) * invT;")
+        out.append(f"            const double dlnkr = dlnkf - (dh - {float(dnu)!r}) * invT;")
         out.append("            const double dqT = fwd * dlnkf - rev * dlnkr;")
+        out.append("            const double qv = q - qh;")
+        out.append("            const double qa = dqT + qv * invT;")
+        out.append("            sh += q * dh;")
+        out.append("            shAC += qh * dh;")
+        out.append("            shT += dh * (dqT - qh * invT);")
+        out.append(f"            scp += q * ({dcp});")
         species = sorted(set(sr) | set(sp))
         for sidx in species:
             terms = []
@@ -233,16 +248,13 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
         for k, nu in sorted(net.items()):
             if not nu:
                 continue
-            out.append(f"            w{k} += {float(nu)!r} * q;")
-            out.append(f"            wT{k} += {float(nu)!r} * dqT;")
-            out.append(f"            AC{k} += {float(nu)!r} * qh;")
+            out.append(f"            v{k} += {float(nu)!r} * qv;")
+            out.append(f"            J[{k * N + K}] += {float(nu)!r} * qa;")
             for sidx in species:
                 out.append(f"            J[{k * N + sidx}] += {_lit(nu * W[k] / W[sidx])} * dq{sidx};")
         out.append("        }")
     out.append("        const double gq = wbar / rho;")
     out.append(f"        const double RT = {_lit(RU)} * T;")
-    for k in range(K):
-        out.append(f"        const double cp{k}b = cp{k};")
     out.append(f"        const double cpm = {_lit(RU)} * (" + " + ".join(f"y[{k}] * cp{k} * {_lit(1.0 / W[k])}" for k in range(K)) + ");")
     dcp_terms = []
     for k in range(K):
@@ -256,13 +268,11 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
     out.append("        const double rcp = rho * cpm;")
     out.append("        const double inv_rcp = 1.0 / rcp;")
     out.append("        const double inv_rho = 1.0 / rho;")
-    out.append("        const double S = RT * (" + " + ".join(f"h{k} * w{k}" for k in range(K)) + ");")
-    out.append("        const double hAC = " + " + ".join(f"h{k} * AC{k}" for k in range(K)) + ";")
-    dst = []
+    out.append("        const double S = RT * sh;")
+    out.append("        const double hAC = shAC;")
+    out.append(f"        const double dST = {_lit(RU)} * scp + RT * shT;")
     for k in range(K):
-        out.append(f"        J[{k * N + K}] = {_lit(W[k])} * inv_rho * (wT{k} + (w{k} - AC{k}) * invT);")
-        dst.append(f"{_lit(RU)} * cp{k} * w{k} + RT * h{k} * (wT{k} - AC{k} * invT)")
-    out.append("        const double dST = " + " + ".join(dst) + ";")
+        out.append(f"        J[{k * N + K}] *= {_lit(W[k])} * inv_rho;")
     # temperature row from the accumulated block (before its rank-one term)
     for j in range(K):
         col = [f"{_lit(1.0 / W[k])} * h{k} * J[{k * N + j}]" for k in range(K) if (k, j) in touched]
@@ -272,7 +282,7 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
         out.append(f"          J[{K * N + j}] = (-dS + S * drcp * inv_rcp) * inv_rcp; }}")
     # rank-one term of the species block: (W_k/W_j) gq (w_k - AC_k)
     for k in range(K):
-        out.append(f"        {{ const double u = {_lit(W[k])} * gq * (w{k} - AC{k});")
+        out.append(f"        {{ const double u = {_lit(W[k])} * gq * v{k};")
         for j in range(K):
             if (k, j) in touched:
                 out.append(f"          J[{k * N + j}] += u * {_lit(1.0 / W[j])};")

@@ -164,7 +164,7 @@ constexpr double kBiasQm1 = 6.0, kBiasQ = 6.0, kBiasQp1 = 10.0;
 constexpr double kAddon = 1e-6;
 constexpr int kH0Iters = 4;
 
-enum Phase : int { FETCH = 0, F0 = 1, H0 = 2, NEWTON = 3, RESTART = 4, LUFAIL = 5, DONE = 6 };
+enum Phase : int { FETCH = 0, NEWTON = 3, RESTART = 4, LUFAIL = 5, DONE = 6 };
 }  // namespace bdf
 
 template <int N>
@@ -237,9 +237,9 @@ struct LaneState {
     unsigned long long piv;     // packed pivot rows
     double e[N], fy[N];
     double tau[kQmax + 2];      // past step sizes, tau[1] most recent
-    double p, t, h, t_end, gamma, gamma_M, Cq, inv_l1, crate, del_old, dsm, ehat_h, s_eval, hg, hub;
+    double p, t, h, t_end, gamma, gamma_M, Cq, inv_l1, crate, del_old, dsm, ehat_h;
     int64_t cell;
-    int phase, q, qwait, nst_M, it, nef, ncf, h0_it;
+    int phase, q, qwait, nst_M, it, nef, ncf;
     bool have_M, ehat_ok, force_M, last, jcur, need_J;
     int nst, nfe, nje, nni, netf, ncfn;
 };
@@ -337,6 +337,26 @@ __device__ __forceinline__ CellIO make_cell_io(double *T, const double *p, doubl
     return CellIO{T, p, Y, ldY, n, status, counters, &prm, nq, prm.idx};
 }
 
+// Start pass of the one-thread-per-cell kernels.  Before the integration
+// proper, one straight-line pass computes every work item's start -- f(y0)
+// and the initial step h0, the same arithmetic the integration would do at
+// its first step -- and files the item under a cost bucket from dt/h0 (a
+// small initial step marks a stiff cell: many steps).  The integration then
+// takes the items most costly bucket first, so that the longest cells start
+// first and the last cells of the queue are short ones (longest processing
+// time first), and cells of alike cost share a wave.  Scheduling only: each
+// cell's result does not depend on the order.
+constexpr int kCostBuckets = 64;
+struct StartPass {
+    double *f0;        // N rows of `stride`: f(y0) per work item
+    double *h0;        // initial step per work item
+    int32_t *info;     // right-hand sides used | status << 8 (4: f(y0) not finite)
+    int32_t *key;      // cost bucket per work item
+    int32_t *cnt;      // kCostBuckets counts, then running offsets
+    int32_t *ord;      // work items, most costly bucket first
+    int64_t stride;    // >= work items of the launch
+};
+
 template <int N>
 __device__ __forceinline__ void finish_cell(LaneState<N> &S, const CellIO &io, int st)
 {
@@ -383,7 +403,6 @@ __device__ __forceinline__ void begin_attempt(LaneState<N> &S, const CellIO &io)
                fabs(S.gamma / S.gamma_M - 1.0) > bdf::kDgmax;
     S.it = 0;   // the accumulated correction e starts at 0 (set after the first solve)
     S.del_old = 0.0;
-    S.s_eval = 1.0;
     S.phase = bdf::NEWTON;
 }
 
@@ -595,7 +614,6 @@ __device__ __forceinline__ void error_test(LaneState<N> &S, const CellIO &io)
         if (S.nef >= kNefRestart) {
             S.h *= kEtaMinEf;
             S.q = 1;
-            S.s_eval = 0.0;
             S.phase = RESTART;   // needs f(z0)
             return;
         }
@@ -626,9 +644,117 @@ __device__ __forceinline__ void error_test(LaneState<N> &S, const CellIO &io)
     begin_step(S, io);
 }
 
+// The integration's start for one cell: f0 = f(y0) and the initial step
+// (the step whose second-derivative estimate gives a local error of 0.5,
+// refined at most kH0Iters times, half of the estimate, bounded by a 10 %
+// change of any component, at most t_end).  st = 4 when f(y0) is not finite.
+template <class Mech>
+__device__ __forceinline__ void initial_step(const Mech &mech, double p, const double *y0, double rtol,
+                                             double atol, double t_end, double *f0, double &h, int &nfe,
+                                             int &st)
+{
+    constexpr int N = Mech::K + 1;
+    mech.rhs(p, y0, f0);
+    nfe = 1;
+    st = 0;
+    h = t_end;
+    if (!finite_vec<N>(f0)) {
+        st = 4;
+        return;
+    }
+    double w[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) w[i] = 1.0 / (rtol * fabs(y0[i]) + atol);
+    if (wrms_norm<N>(f0, w) == 0.0) return;
+    double hub = t_end;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        const double lim = 0.1 * fabs(y0[i]) + 1.0 / w[i];
+        if (fabs(f0[i]) * hub > lim) hub = lim / fabs(f0[i]);
+    }
+    double hg = hub;
+    for (int it = 0; it < bdf::kH0Iters; it++) {
+        double yv[N], fy[N];
+#pragma unroll
+        for (int i = 0; i < N; i++) yv[i] = y0[i] + hg * f0[i];
+        mech.rhs(p, yv, fy);
+        nfe++;
+        if (!finite_vec<N>(fy)) {
+            hg *= 0.1;
+            continue;
+        }
+        double dv[N];
+#pragma unroll
+        for (int i = 0; i < N; i++) dv[i] = (fy[i] - f0[i]) / hg;
+        const double ydd = wrms_norm<N>(dv, w);
+        double hnew = ydd > 0.0 ? sqrt(2.0 / ydd) : hub;
+        if (hnew > hub) hnew = hub;
+        const double ratio = hnew / hg;
+        hg = hnew;
+        if (ratio >= 0.5 && ratio <= 2.0) break;
+    }
+    h = 0.5 * hg;
+    if (h > t_end) h = t_end;
+}
+
+// Cost bucket of a cell from its start: 3 log2(dt / h0), clamped (0 for a
+// cell that fails at the start).
+__device__ __forceinline__ int cost_bucket(double h, double t_end, int st)
+{
+    if (st != 0 || !(h > 0.0)) return 0;
+    const double b = 3.0 * log2(t_end / h);
+    return b < 1.0 ? 0 : (b >= kCostBuckets - 1 ? kCostBuckets - 1 : (int)b);
+}
+
+// Start pass: one thread per work item; bucket counts per block in LDS, then
+// one atomic per non-empty bucket.
+template <class Mech>
+__global__ void __launch_bounds__(256) bdf_start_kernel(Mech mech, double *__restrict__ T,
+                                                        const double *__restrict__ p,
+                                                        double *__restrict__ Y, int64_t ldY, int64_t n,
+                                                        double dt, BdfParams prm, StartPass sp)
+{
+    constexpr int N = Mech::K + 1;
+    __shared__ int hist[kCostBuckets];
+    if (threadIdx.x < kCostBuckets) hist[threadIdx.x] = 0;
+    __syncthreads();
+    const CellIO io = make_cell_io(T, p, Y, ldY, n, nullptr, nullptr, prm);
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it < io.nq) {
+        const int64_t cc = io.idx ? (int64_t)io.idx[it] : it;
+        int key = 0;
+        if (cc >= 0 && cc < io.n) {   // an index outside the arrays is skipped by the integration
+            double y0[N], f0[N], h;
+            int nfe, st;
+#pragma unroll
+            for (int k = 0; k < N - 1; k++) y0[k] = io.Y[k * io.ldY + cc];
+            y0[N - 1] = io.T[cc];
+            initial_step(mech, io.p[cc], y0, prm.rtol, prm.atol, dt, f0, h, nfe, st);
+#pragma unroll
+            for (int i = 0; i < N; i++) sp.f0[i * sp.stride + it] = f0[i];
+            sp.h0[it] = h;
+            sp.info[it] = nfe | (st << 8);
+            key = cost_bucket(h, dt, st);
+        }
+        sp.key[it] = key;
+        atomicAdd(&hist[key], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kCostBuckets && hist[threadIdx.x] != 0) atomicAdd(&sp.cnt[threadIdx.x], hist[threadIdx.x]);
+}
+
+// Clears the work-queue counter and the bucket counts (a kernel, not a
+// memset, so that a captured graph replays it like any other node).
+__global__ void start_reset_kernel(unsigned long long *queue, int32_t *cnt);
+// Bucket counts -> offsets, most costly bucket first.
+__global__ void start_scan_kernel(int32_t *cnt);
+// Files every work item at the next offset of its bucket.
+__global__ void __launch_bounds__(256) start_scatter_kernel(const int32_t *key, int32_t *cnt, int32_t *ord,
+                                                            int64_t n, BdfParams prm);
+
 template <class Mech>
 __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
-                          unsigned long long *queue, double *lds)
+                          unsigned long long *queue, double *lds, const StartPass &sp)
 {
     constexpr int K = Mech::K;
     constexpr int N = K + 1;
@@ -653,8 +779,8 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
                 if (want) {
                     const unsigned long long rank = __popcll(mask & ((1ull << lane) - 1ull));
                     const unsigned long long c = base + rank;
-                    const int64_t cc = c < (unsigned long long)io.nq
-                                           ? (io.idx ? (int64_t)io.idx[c] : (int64_t)c) : -1;
+                    const int64_t item = c < (unsigned long long)io.nq ? (int64_t)sp.ord[c] : -1;
+                    const int64_t cc = item >= 0 ? (io.idx ? (int64_t)io.idx[item] : item) : -1;
                     if (c < (unsigned long long)io.nq && (cc < 0 || cc >= io.n)) {
                         // an index outside the arrays is skipped: this lane fetches again
                     } else if (c < (unsigned long long)io.nq) {
@@ -667,9 +793,17 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
                         S.nst = S.nfe = S.nje = S.nni = S.netf = S.ncfn = 0;
 #pragma unroll
                         for (int j = 0; j < kQmax + 2; j++) S.tau[j] = 0.0;
-                        S.s_eval = 0.0;
                         S.need_J = false;
-                        S.phase = F0;
+                        // the start from the start pass: e = f(y0), h = h0
+#pragma unroll
+                        for (int k = 0; k < N; k++) S.e[k] = sp.f0[k * sp.stride + item];
+                        S.h = sp.h0[item];
+                        const int inf = sp.info[item];
+                        S.nfe = inf & 0xff;
+                        if (inf >> 8)
+                            finish_cell(S, io, inf >> 8);
+                        else
+                            begin_integration(S, io);
                     } else {
                         S.phase = DONE;
                     }
@@ -686,8 +820,7 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
         const unsigned long long mJ = __ballot(waitJ);
         bool runJ = false;
         if (mJ) {
-            const bool progress = ((S.phase == F0 || S.phase == H0 || S.phase == NEWTON ||
-                                    S.phase == RESTART) && !waitJ) || S.phase == LUFAIL;
+            const bool progress = ((S.phase == NEWTON || S.phase == RESTART) && !waitJ) || S.phase == LUFAIL;
             runJ = __popcll(mJ) >= io.prm->jac_batch || __ballot(progress) == 0ull;
         }
         if (runJ && waitJ) {
@@ -714,13 +847,13 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
         const bool waiting = S.need_J && S.phase == NEWTON;
 
         // ---- right-hand side (the single call site) ----
-        if ((S.phase == F0 || S.phase == H0 || S.phase == NEWTON || S.phase == RESTART) && !waiting) {
+        if ((S.phase == NEWTON || S.phase == RESTART) && !waiting) {
             double yv[N];
-            // prediction itself (first Newton iteration, F0, RESTART), or the
-            // prediction plus s_eval * e (later iterations; H0 with e = f(y0))
-            const bool use_e = (S.phase == H0) || (S.phase == NEWTON && S.it > 0);
+            // the prediction itself (first Newton iteration, RESTART), or
+            // the prediction plus the accumulated correction e
+            const bool use_e = S.phase == NEWTON && S.it > 0;
 #pragma unroll
-            for (int i = 0; i < N; i++) yv[i] = use_e ? S.z(0, i) + S.s_eval * S.e[i] : S.z(0, i);
+            for (int i = 0; i < N; i++) yv[i] = use_e ? S.z(0, i) + S.e[i] : S.z(0, i);
             mech.rhs(S.p, yv, S.fy);
             S.nfe++;
         }
@@ -764,55 +897,6 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
                 conv_fail(S, io);
         } else if (S.phase == LUFAIL) {
             conv_fail(S, io);
-        } else if (S.phase == F0) {
-            if (!finite_vec<N>(S.fy)) {
-                finish_cell(S, io, 4);
-            } else {
-#pragma unroll
-                for (int i = 0; i < N; i++) {
-                    S.e[i] = S.fy[i];   // e keeps f(y0) until the first step
-                    S.z(kWeightRow, i) = 1.0 / (io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
-                }
-                if (wrms_norm<N>(S.fy, S.z) == 0.0) {
-                    S.h = t_end;
-                    begin_integration(S, io);
-                } else {
-                    double hub = t_end;
-#pragma unroll
-                    for (int i = 0; i < N; i++) {
-                        const double lim = 0.1 * fabs(S.z(0, i)) + 1.0 / S.z(kWeightRow, i);
-                        if (fabs(S.fy[i]) * hub > lim) hub = lim / fabs(S.fy[i]);
-                    }
-                    S.hub = hub;
-                    S.hg = hub;
-                    S.s_eval = hub;
-                    S.h0_it = 0;
-                    S.phase = H0;
-                }
-            }
-        } else if (S.phase == H0) {
-            bool done = false;
-            if (!finite_vec<N>(S.fy)) {
-                S.hg *= 0.1;
-            } else {
-                double dv[N];
-#pragma unroll
-                for (int i = 0; i < N; i++) dv[i] = (S.fy[i] - S.e[i]) / S.hg;
-                const double ydd = wrms_norm<N>(dv, S.z);
-                double hnew = ydd > 0.0 ? sqrt(2.0 / ydd) : S.hub;
-                if (hnew > S.hub) hnew = S.hub;
-                const double ratio = hnew / S.hg;
-                S.hg = hnew;
-                done = (ratio >= 0.5 && ratio <= 2.0);
-            }
-            S.h0_it++;
-            if (done || S.h0_it >= kH0Iters) {
-                S.h = 0.5 * S.hg;
-                if (S.h > t_end) S.h = t_end;
-                begin_integration(S, io);
-            } else {
-                S.s_eval = S.hg;
-            }
         } else if (S.phase == RESTART) {
             if (!finite_vec<N>(S.fy)) {
                 finish_cell(S, io, 4);
@@ -836,11 +920,12 @@ __global__ void __launch_bounds__(64) bdf_queue_kernel(Mech mech, double *__rest
                                                        int64_t n, double dt, BdfParams prm,
                                                        int32_t *__restrict__ status,
                                                        int32_t *__restrict__ counters,
-                                                       unsigned long long *__restrict__ queue)
+                                                       unsigned long long *__restrict__ queue,
+                                                       StartPass sp)
 {
     __shared__ double nord[kLdsRows * (Mech::K + 1) * 64];
     const CellIO io = make_cell_io(T, p, Y, ldY, n, status, counters, prm);
-    run_lanes(mech, io, dt, queue, nord);
+    run_lanes(mech, io, dt, queue, nord, sp);
 }
 
 template <class Mech>
@@ -886,10 +971,59 @@ __global__ void reset_queue_kernel(unsigned long long *queue);
 // kernel's occupancy, never more lanes than cells.
 int queue_grid(const void *kernel, int64_t n);
 
+// Bytes of the start-pass workspace for `items` work items of an N-component
+// cell, and its layout in such a buffer (256-byte aligned pieces).
+inline size_t start_pass_bytes(int N, int64_t items)
+{
+    auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t m = (size_t)(items > 0 ? items : 1);
+    return a(N * m * 8) + a(m * 8) + 3 * a(m * 4) + a(kCostBuckets * 4);
+}
+inline StartPass start_pass_carve(void *base, int N, int64_t items)
+{
+    auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t m = (size_t)(items > 0 ? items : 1);
+    char *c = (char *)base;
+    StartPass sp;
+    sp.f0 = (double *)c;
+    c += a(N * m * 8);
+    sp.h0 = (double *)c;
+    c += a(m * 8);
+    sp.info = (int32_t *)c;
+    c += a(m * 4);
+    sp.key = (int32_t *)c;
+    c += a(m * 4);
+    sp.ord = (int32_t *)c;
+    c += a(m * 4);
+    sp.cnt = (int32_t *)c;
+    sp.stride = (int64_t)m;
+    return sp;
+}
+
+// The one-thread-per-cell integration of at most `items` work items: reset,
+// start pass, bucket offsets, filing, then the integration in that order.
+template <class Mech>
+hipError_t launch_thread_integrate(const Mech &mech, double *T, const double *p, double *Y, int64_t ldY,
+                                   int64_t n, double dt, const BdfParams &prm, int32_t *status,
+                                   int32_t *counters, unsigned long long *queue, const StartPass &sp,
+                                   int64_t items, hipStream_t s)
+{
+    const unsigned gb = (unsigned)((items + 255) / 256);
+    hipLaunchKernelGGL(start_reset_kernel, dim3(1), dim3(64), 0, s, queue, sp.cnt);
+    hipLaunchKernelGGL(bdf_start_kernel<Mech>, dim3(gb), dim3(256), 0, s, mech, T, p, Y, ldY, n, dt, prm, sp);
+    hipLaunchKernelGGL(start_scan_kernel, dim3(1), dim3(64), 0, s, sp.cnt);
+    hipLaunchKernelGGL(start_scatter_kernel, dim3(gb), dim3(256), 0, s, sp.key, sp.cnt, sp.ord, n, prm);
+    const int blocks = queue_grid((const void *)bdf_queue_kernel<Mech>, items);
+    hipLaunchKernelGGL(bdf_queue_kernel<Mech>, dim3(blocks), dim3(64), 0, s, mech, T, p, Y, ldY, n, dt, prm,
+                       status, counters, queue, sp);
+    return hipGetLastError();
+}
+
 // Launchers of a mechanism-specialised functor (defined by generated code).
 typedef hipError_t (*gen_integrate_fn)(double *T, const double *p, double *Y, int64_t ldY,
                                        int64_t n, double dt, const BdfParams &prm, int32_t *status,
-                                       int32_t *counters, unsigned long long *queue, hipStream_t s);
+                                       int32_t *counters, unsigned long long *queue, const StartPass &sp,
+                                       int64_t items, hipStream_t s);
 typedef hipError_t (*gen_eval_fn)(const double *T, const double *p, const double *Y, int64_t ldY,
                                   int64_t n, double *out, int64_t ld, hipStream_t s);
 
@@ -907,7 +1041,7 @@ const GenEntry *gen_registry(int *count);
 #define CHEM_DECLARE_GEN_LAUNCHERS(TAG)                                                          \
     hipError_t gen_integrate_##TAG(double *, const double *, double *, int64_t, int64_t, double,  \
                                    const BdfParams &, int32_t *, int32_t *, unsigned long long *, \
-                                   hipStream_t);                                                  \
+                                   const StartPass &, int64_t, hipStream_t);                      \
     hipError_t gen_rhs_##TAG(const double *, const double *, const double *, int64_t, int64_t,    \
                              double *, int64_t, hipStream_t);                                     \
     hipError_t gen_jac_##TAG(const double *, const double *, const double *, int64_t, int64_t,    \
@@ -916,13 +1050,11 @@ const GenEntry *gen_registry(int *count);
 #define CHEM_DEFINE_GEN_LAUNCHERS(MECH, TAG)                                                      \
     hipError_t gen_integrate_##TAG(double *T, const double *p, double *Y, int64_t ldY, int64_t n, \
                                    double dt, const BdfParams &prm, int32_t *status,              \
-                                   int32_t *counters, unsigned long long *queue, hipStream_t s)   \
+                                   int32_t *counters, unsigned long long *queue,                  \
+                                   const StartPass &sp, int64_t items, hipStream_t s)             \
     {                                                                                             \
-        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, queue);                    \
-        const int blocks = queue_grid((const void *)bdf_queue_kernel<MECH>, n);                   \
-        hipLaunchKernelGGL(bdf_queue_kernel<MECH>, dim3(blocks), dim3(64), 0, s, MECH{}, T, p, Y, \
-                           ldY, n, dt, prm, status, counters, queue);                             \
-        return hipGetLastError();                                                                 \
+        return launch_thread_integrate(MECH{}, T, p, Y, ldY, n, dt, prm, status, counters, queue, \
+                                       sp, items, s);                                             \
     }                                                                                             \
     hipError_t gen_rhs_##TAG(const double *T, const double *p, const double *Y, int64_t ldY,      \
                              int64_t n, double *F, int64_t ldF, hipStream_t s)                    \

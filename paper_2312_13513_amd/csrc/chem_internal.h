@@ -57,10 +57,11 @@ hipError_t launch_rhs(const DevMechView &m, const double *T, const double *p, co
                       int64_t ldY, int64_t n, double *F, int64_t ldF, hipStream_t s);
 hipError_t launch_jacobian(const DevMechView &m, const double *T, const double *p, const double *Y,
                            int64_t ldY, int64_t n, double *J, int64_t ldJ, hipStream_t s);
+struct StartPass;
 hipError_t launch_bdf_thread(const DevMechView &m, double *T, const double *p, double *Y,
                              int64_t ldY, int64_t n, double dt, const BdfParams &prm,
                              int32_t *status, int32_t *counters, unsigned long long *queue,
-                             hipStream_t s);
+                             const StartPass &sp, int64_t items, hipStream_t s);
 bool thread_kernel_supports(int K);
 
 }  // namespace chem

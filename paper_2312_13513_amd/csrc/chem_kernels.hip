@@ -212,6 +212,44 @@ struct TableMech {
 
 __global__ void reset_queue_kernel(unsigned long long *queue) { *queue = 0ull; }
 
+__global__ void start_reset_kernel(unsigned long long *queue, int32_t *cnt)
+{
+    if (threadIdx.x < kCostBuckets) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *queue = 0ull;
+}
+
+__global__ void start_scan_kernel(int32_t *cnt)
+{
+    if (threadIdx.x != 0) return;
+    int32_t s = 0;
+    for (int b = kCostBuckets - 1; b >= 0; b--) {
+        const int32_t c = cnt[b];
+        cnt[b] = s;
+        s += c;
+    }
+}
+
+// Ranks within the block by LDS atomics, then one global atomic per
+// non-empty bucket of the block reserves its range (a global atomic per item
+// would serialise on the few buckets that hold most cells).
+__global__ void __launch_bounds__(256) start_scatter_kernel(const int32_t *key, int32_t *cnt, int32_t *ord,
+                                                            int64_t n, BdfParams prm)
+{
+    __shared__ int hist[kCostBuckets], base[kCostBuckets];
+    if (threadIdx.x < kCostBuckets) hist[threadIdx.x] = 0;
+    __syncthreads();
+    const CellIO io = make_cell_io(nullptr, nullptr, nullptr, 0, n, nullptr, nullptr, prm);
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = it < io.nq;
+    const int k = in ? key[it] : 0;
+    const int rank = in ? atomicAdd(&hist[k], 1) : 0;
+    __syncthreads();
+    if (threadIdx.x < kCostBuckets)
+        base[threadIdx.x] = hist[threadIdx.x] != 0 ? atomicAdd(&cnt[threadIdx.x], hist[threadIdx.x]) : 0;
+    __syncthreads();
+    if (in) ord[base[k] + rank] = (int32_t)it;
+}
+
 int queue_grid(const void *kernel, int64_t n)
 {
     int dev = 0, cus = 0, per_cu = 0;
@@ -266,16 +304,12 @@ hipError_t launch_jacobian(const DevMechView &m, const double *T, const double *
 hipError_t launch_bdf_thread(const DevMechView &m, double *T, const double *p, double *Y,
                              int64_t ldY, int64_t n, double dt, const BdfParams &prm,
                              int32_t *status, int32_t *counters, unsigned long long *queue,
-                             hipStream_t s)
+                             const StartPass &sp, int64_t items, hipStream_t s)
 {
 #define CHEM_CASE(KK)                                                                             \
-    if (m.K == KK) {                                                                              \
-        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, queue);                    \
-        const int blocks = queue_grid((const void *)bdf_queue_kernel<TableMech<KK>>, n);          \
-        hipLaunchKernelGGL(bdf_queue_kernel<TableMech<KK>>, dim3(blocks), dim3(64), 0, s,         \
-                           TableMech<KK>{m}, T, p, Y, ldY, n, dt, prm, status, counters, queue);  \
-        return hipGetLastError();                                                                 \
-    }
+    if (m.K == KK)                                                                                \
+        return launch_thread_integrate(TableMech<KK>{m}, T, p, Y, ldY, n, dt, prm, status, counters, \
+                                       queue, sp, items, s);
     CHEM_FOR_EACH_K(CHEM_CASE)
 #undef CHEM_CASE
     return hipErrorInvalidValue;

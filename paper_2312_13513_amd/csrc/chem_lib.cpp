@@ -219,9 +219,10 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
     const int K = m->host.K;
     const bool thread_ok = m->gen != nullptr || chem::thread_kernel_supports(K);
     const bool wave_ok = chem::wave_kernel_rows(K + 1) > 0;
-    // automatic choice: the 16-lane tile when a cell fits in it (N <= 16),
-    // else one wave per cell; one thread per cell only when asked for
-    const int sched = o.schedule >= 0 ? o.schedule : (K + 1 <= 16 ? 2 : 1);
+    // automatic choice: one thread per cell for a compiled-in mechanism
+    // (state in registers and LDS, no spill), else the 16-lane tile when a
+    // cell fits in it (N <= 16), else one wave per cell
+    const int sched = o.schedule >= 0 ? o.schedule : (m->gen && o.precision == 0 ? 0 : (K + 1 <= 16 ? 2 : 1));
     if (sched == 0 && !thread_ok)
         return fail(CHEM_EUNSUP, "no one-thread-per-cell kernel is built for K = " + std::to_string(K));
     if (sched == 0 && o.precision != 0)
@@ -249,11 +250,26 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
         e = chem::launch_bdf_wave(m->view, m->wave, T, p, Y, ldY, n, dt, prm, status, counters, queue, qs,
                                   m->wave_slots, o.precision == 1, lanes, stream);
     }
-    else if (m->gen)
-        e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, stream);
-    else
-        e = chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status, counters, queue,
-                                    stream);
+    else {
+        // one thread per cell: the start pass and its cost order need
+        // workspace for every work item of the call
+        const int64_t items = idx ? n_idx : n;
+        if (items <= 0) return CHEM_OK;
+        void *wp = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(m->ws_mu);
+            chem_host::DevBuf &wb = m->start_ws[(void *)stream];
+            const int rc = wb.grow(chem::start_pass_bytes(K + 1, items), stream);
+            if (rc != CHEM_OK) return rc;
+            wp = wb.p;
+        }
+        const chem::StartPass sp = chem::start_pass_carve(wp, K + 1, items);
+        if (m->gen)
+            e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, sp, items, stream);
+        else
+            e = chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status, counters, queue, sp, items,
+                                        stream);
+    }
     return check_hip(e, "integrator launch");
 }
 
@@ -442,6 +458,7 @@ void chem_free_mechanism(chem_mech m)
         hipGetDevice(&prev);
         hipSetDevice(m->device);
         hipFree(m->dev_block);
+        for (auto &w : m->start_ws) w.second.release();
         hipSetDevice(prev);
     }
     delete m;

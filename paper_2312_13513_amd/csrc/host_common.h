@@ -2,6 +2,8 @@
 // the mechanism handle, error reporting and the internal integrate call.
 #pragma once
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -31,6 +33,46 @@ int fail(int code, const std::string &msg);
 int check_hip(hipError_t e, const char *what);
 bool is_device_ptr(const void *p);
 
+// A device workspace that only grows.  Growing is refused while the stream
+// is being captured (a graph must not record an allocation), and a replaced
+// buffer is kept until release(): a graph captured earlier may still refer
+// to it.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    std::vector<void *> retired;
+    int grow(size_t want, hipStream_t st)
+    {
+        if (want <= bytes) return CHEM_OK;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CHEM_EHIP, "hipStreamIsCapturing failed");
+        }
+        if (cs != hipStreamCaptureStatusNone)
+            return fail(CHEM_EINVAL, "the workspace is too small for this call and cannot grow while the "
+                                     "stream is captured: make the same call (or the reserve call) eagerly "
+                                     "before capturing");
+        void *q = nullptr;
+        if (hipMalloc(&q, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CHEM_ENOMEM, "workspace allocation failed");
+        }
+        if (p) retired.push_back(p);
+        p = q;
+        bytes = want;
+        return CHEM_OK;
+    }
+    void release()
+    {
+        for (void *r : retired) hipFree(r);
+        retired.clear();
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
 }  // namespace chem_host
 
 struct chem_mech_s {
@@ -50,6 +92,11 @@ struct chem_mech_s {
     double *wave_scratch = nullptr;
     int wave_slots = 0;
     unsigned next_part = 0;
+    // start-pass workspaces of the one-thread-per-cell kernels, one per
+    // stream (calls on one stream run in order, so they can share one); each
+    // grows to the largest call made on its stream outside graph capture
+    std::map<void *, chem_host::DevBuf> start_ws;
+    std::mutex ws_mu;
     // autotuned schedule per precision (used when opts.schedule == -2)
     struct Tuned {
         bool valid = false;

@@ -17,6 +17,7 @@ using chem::bf16_t;
 using chem_host::check_hip;
 using chem_host::fail;
 using chem_host::is_device_ptr;
+using chem_host::DevBuf;
 
 namespace {
 
@@ -27,46 +28,6 @@ constexpr double kBeta1 = 0.9, kBeta2 = 0.999, kEps = 1e-8;
 constexpr double kPi = 3.14159265358979323846;
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
-
-// A device workspace that only grows.  Growing is refused while the stream
-// is being captured (a graph must not record an allocation), and a replaced
-// buffer is kept until release(): a graph captured earlier may still refer
-// to it.
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    std::vector<void *> retired;
-    int grow(size_t want, hipStream_t st)
-    {
-        if (want <= bytes) return CHEM_OK;
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CHEM_EHIP, "hipStreamIsCapturing failed");
-        }
-        if (cs != hipStreamCaptureStatusNone)
-            return fail(CHEM_EINVAL, "the surrogate workspace is too small for this call and cannot grow while "
-                                     "the stream is captured: call chem_surrogate_reserve (or the same call "
-                                     "eagerly) before capturing");
-        void *q = nullptr;
-        if (hipMalloc(&q, want) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CHEM_ENOMEM, "surrogate workspace allocation failed");
-        }
-        if (p) retired.push_back(p);
-        p = q;
-        bytes = want;
-        return CHEM_OK;
-    }
-    void release()
-    {
-        for (void *r : retired) hipFree(r);
-        retired.clear();
-        if (p) hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-};
 
 // Carves aligned sub-buffers out of one allocation.
 struct Carver {
