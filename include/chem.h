@@ -120,6 +120,24 @@ int chem_integrate(chem_mech mech, double *T, const double *p, double *Y, int64_
                    int64_t ncells, double dt, const chem_opts *opts, int32_t *status,
                    int32_t *counters, void *hip_stream);
 
+/* chem_integrate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and kernels as chem_integrate, but the
+ * one-thread-per-cell schedule keeps its per-call start-pass workspace (f(y0),
+ * initial step and cost order of every cell, (8 K + 28) bytes per cell) in a
+ * fixed array of 32 MiB that the library holds on each GPU until the process
+ * ends, instead of a workspace it grows; the call makes no hipMalloc or
+ * hipFree.  That schedule then serves every call of up to
+ * floor((2^25 - 1276) / (8 K + 28)) cells (335,531 for K = 9; the exact
+ * bound, set by 256-byte alignment of the pieces, is a few cells higher);
+ * a call beyond the array fails with CHEM_EINVAL and a message giving the
+ * limit.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap in time on one GPU (different streams) race: order them.  The
+ * other schedules use no such workspace and behave as in chem_integrate. */
+int chem_integrate_noalloc(chem_mech mech, double *T, const double *p, double *Y, int64_t ldY,
+                           int64_t ncells, double dt, const chem_opts *opts, int32_t *status,
+                           int32_t *counters, void *hip_stream);
+
 /* Advance the listed cells only, in list order: work item j integrates cell
  * cell_idx[j] of the arrays (sizes as chem_integrate; status and counters,
  * if given, are indexed by cell).  cell_idx is a device array of nidx

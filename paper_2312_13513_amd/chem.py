@@ -59,6 +59,7 @@ def _load():
     L.chem_mechanism_variant.restype = C.c_char_p
     L.chem_mechanism_variant.argtypes = [vp]
     L.chem_integrate.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), vp, vp, vp]
+    L.chem_integrate_noalloc.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), vp, vp, vp]
     L.chem_eval_rhs.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, vp]
     L.chem_eval_jacobian.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, vp]
     L.chem_integrate_indexed.argtypes = [vp, dp, dp, dp, i64, i64, dp, i64, C.c_double, C.POINTER(chem_opts),
@@ -112,7 +113,7 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_apply", "chem_surrogate_infer", "chem_surrogate_grad",
             "chem_surrogate_get_grads", "chem_surrogate_set_grads", "chem_surrogate_adam",
             "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_reserve",
-            "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace")
+            "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace", "chem_integrate_noalloc")
 
 
 def lib():
@@ -176,6 +177,17 @@ def chem_integrate(handle: int, T, p, Y, dt: float, opts: Optional[chem_opts] = 
                                _ptr(status), _ptr(counters), _stream(stream)))
 
 
+def chem_integrate_noalloc(handle: int, T, p, Y, dt: float, opts: Optional[chem_opts] = None,
+                           status=None, counters=None, stream=None, ncells: Optional[int] = None) -> None:
+    """chem_integrate with the start-pass workspace in the library's fixed
+    per-GPU array (no device allocation; calls overlapping on one GPU race)."""
+    n = T.shape[0] if ncells is None else int(ncells)
+    _check(_lib.chem_integrate_noalloc(C.c_void_p(handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1], n,
+                                       float(dt), C.byref(opts) if opts is not None else None,
+                                       _ptr(status), _ptr(counters), _stream(stream)))
+
+
+
 def chem_eval_rhs(handle: int, T, p, Y, F, stream=None) -> None:
     _check(_lib.chem_eval_rhs(C.c_void_p(handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1], T.shape[0],
                               _ptr(F), F.shape[1], _stream(stream)))
@@ -210,6 +222,9 @@ class Mechanism:
 
     def integrate(self, T, p, Y, dt, opts=None, status=None, counters=None, stream=None):
         chem_integrate(self.handle, T, p, Y, dt, opts, status, counters, stream)
+
+    def integrate_noalloc(self, T, p, Y, dt, opts=None, status=None, counters=None, stream=None):
+        chem_integrate_noalloc(self.handle, T, p, Y, dt, opts, status, counters, stream)
 
     def integrate_indexed(self, T, p, Y, idx, dt, opts=None, status=None, counters=None, stream=None):
         """Advance cells idx (int32 GPU tensor) of the arrays, in list order."""

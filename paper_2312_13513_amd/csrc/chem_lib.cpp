@@ -138,6 +138,52 @@ constexpr int kQueues = 64;
 constexpr int kScratchParts = 4;               // reaction-scratch partitions (calls in flight)
 constexpr size_t kScratchBudget = size_t(1) << 30;   // bytes of reaction scratch per mechanism, at most
 
+// Start-pass workspace of chem_integrate_noalloc: one copy of this array on
+// every GPU the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel (in host code it is only a
+// stand-in): once per device, with that device current, it takes the device
+// address of that GPU's copy with hipGetSymbolAddress and uses that address.
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `device`'s copy of the array (resolved once, with that
+// device current).
+int noalloc_scratch(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices) return chem_host::fail(CHEM_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        int prev = 0;
+        if (hipGetDevice(&prev) != hipSuccess) return chem_host::fail(CHEM_EHIP, "hipGetDevice failed");
+        void *ptr = nullptr;
+        hipError_t e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        hipSetDevice(prev);
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return chem_host::fail(CHEM_EHIP, std::string("hipGetSymbolAddress of the fixed workspace: ") +
+                                                  hipGetErrorString(e));
+        }
+        g_scratch_addr[device] = ptr;
+    }
+    *out = g_scratch_addr[device];
+    return CHEM_OK;
+}
+
+// Work items of an N-component mechanism that fit the fixed workspace.
+int64_t noalloc_max_items(int N)
+{
+    int64_t lo = 0, hi = (int64_t)(kNoAllocBytes / 8);
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (chem::start_pass_bytes(N, mid) <= kNoAllocBytes) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 unsigned long long fnv1a64(const std::string &data)
 {
     unsigned long long h = 0xCBF29CE484222325ull;
@@ -196,7 +242,8 @@ namespace chem_host {
 
 int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
                     double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
-                    hipStream_t stream, const int64_t *n_dev, const int32_t *idx, int64_t n_idx)
+                    hipStream_t stream, const int64_t *n_dev, const int32_t *idx, int64_t n_idx,
+                    void *fixed_ws, size_t fixed_bytes)
 {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be finite and > 0");
     chem_opts o;
@@ -255,8 +302,13 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
         // workspace for every work item of the call
         const int64_t items = idx ? n_idx : n;
         if (items <= 0) return CHEM_OK;
-        void *wp = nullptr;
-        {
+        void *wp = fixed_ws;
+        if (fixed_ws) {
+            if (chem::start_pass_bytes(K + 1, items) > fixed_bytes)
+                return fail(CHEM_EINVAL, "too many cells for the fixed workspace: at most " +
+                                             std::to_string(noalloc_max_items(K + 1)) + " work items for K = " +
+                                             std::to_string(K));
+        } else {
             std::lock_guard<std::mutex> lk(m->ws_mu);
             chem_host::DevBuf &wb = m->start_ws[(void *)stream];
             const int rc = wb.grow(chem::start_pass_bytes(K + 1, items), stream);
@@ -446,6 +498,12 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     m->wave.inc = (const int2 *)(blk + off_inc);
     m->wave_scratch = wave_slots > 0 ? (double *)(blk + off_ws) : nullptr;
     m->wave_slots = wave_slots;
+    // set-up of the fixed workspace of this device (chem_integrate_noalloc)
+    void *fixed = nullptr;
+    if ((rc = noalloc_scratch(device, &fixed)) != CHEM_OK) {
+        chem_free_mechanism(m);
+        return rc;
+    }
     *out = m;
     return CHEM_OK;
 }
@@ -504,6 +562,18 @@ int chem_integrate(chem_mech m, double *T, const double *p, double *Y, int64_t l
     if (rc != CHEM_OK) return rc;
     return chem_host::integrate_cells(m, T, p, Y, ldY, n, dt, opts, status, counters,
                                       (hipStream_t)stream, nullptr);
+}
+
+int chem_integrate_noalloc(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
+                           double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
+                           void *stream)
+{
+    int rc = check_state_args(m, T, p, Y, ldY, n);
+    if (rc != CHEM_OK) return rc;
+    void *ws = nullptr;
+    if ((rc = noalloc_scratch(m->device, &ws)) != CHEM_OK) return rc;
+    return chem_host::integrate_cells(m, T, p, Y, ldY, n, dt, opts, status, counters, (hipStream_t)stream,
+                                      nullptr, nullptr, 0, ws, kNoAllocBytes);
 }
 
 int chem_eval_rhs(chem_mech m, const double *T, const double *p, const double *Y, int64_t ldY,

@@ -109,9 +109,13 @@ namespace chem_host {
 // chem_integrate after argument checks of the state arrays; when n_dev is not
 // NULL the kernels integrate the first *n_dev cells (read on the device, at
 // most n), so that a count produced by an earlier kernel needs no host sync.
+// fixed_ws (fixed_bytes long, device memory), when given, serves as the
+// start-pass workspace of the one-thread-per-cell schedule instead of the
+// stream's growing one: the call then allocates nothing, and fails with
+// CHEM_EINVAL when its work items do not fit.
 int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t ldY, int64_t n,
                     double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
                     hipStream_t stream, const int64_t *n_dev, const int32_t *idx = nullptr,
-                    int64_t n_idx = 0);
+                    int64_t n_idx = 0, void *fixed_ws = nullptr, size_t fixed_bytes = 0);
 
 }  // namespace chem_host
