@@ -109,7 +109,10 @@ int chem_mechanism_info(chem_mech mech, int32_t *K, int32_t *R, int32_t *E, doub
  * The string is owned by the handle. */
 const char *chem_mechanism_variant(chem_mech mech);
 
-/* Advance ncells cells over [0, dt] in place.
+/* Advance ncells cells over [0, dt] in place (the per-cell chemistry source
+ * of one flow step, integrated as a stiff ODE: paper Section 2, CVODE's
+ * variable-order BDF method; Section 3.1, the chemistry of every cell on the
+ * GPU).
  *   T[ncells]            temperature, K (in/out)
  *   p[ncells]            pressure, Pa (in), constant over the step
  *   Y[K * ldY]           mass fractions (in/out)
@@ -141,9 +144,11 @@ int chem_integrate_noalloc(chem_mech mech, double *T, const double *p, double *Y
 /* Advance the listed cells only, in list order: work item j integrates cell
  * cell_idx[j] of the arrays (sizes as chem_integrate; status and counters,
  * if given, are indexed by cell).  cell_idx is a device array of nidx
- * indices; an index outside [0, ncells) is skipped.  The list order is the
- * order in which the work queue hands cells to the lanes (e.g. from
- * chem_lpt_order).  nidx == 0 is a no-op. */
+ * indices; an index outside [0, ncells) is skipped.  On the wave and tile
+ * schedules the list order is the order in which the work queue hands cells
+ * to the lanes (e.g. from chem_lpt_order); the one-thread-per-cell schedule
+ * orders the listed cells itself, most costly first by its start pass.
+ * Results per cell do not depend on the order.  nidx == 0 is a no-op. */
 int chem_integrate_indexed(chem_mech mech, double *T, const double *p, double *Y, int64_t ldY,
                            int64_t ncells, const int32_t *cell_idx, int64_t nidx, double dt,
                            const chem_opts *opts, int32_t *status, int32_t *counters,
