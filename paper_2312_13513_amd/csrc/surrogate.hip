@@ -27,24 +27,28 @@ __device__ __forceinline__ bf16_t to_bf16(float f)
 }
 
 // GELU(u) = u Phi(u) without branches: Phi(-|u|) = erfc(z)/2, z = |u|/sqrt(2),
-// with erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2), P of degree 7 fitted in
-// FP64 to ln(erfcx(z)/t) (gelu_fit.py).  The FP32 evaluation stays within a
-// relative 3e-5 of the exact GELU for all u; the activations are then rounded
-// to BF16 (unit roundoff 2^-8).
+// in the form erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2) (Numerical
+// Recipes' erfcc), P of degree 7 refitted in FP64 (gelu_fit.py).  Evaluated
+// through the hardware base-2 exponential with 1/2 and log2(e) folded into
+// the coefficients, Phi(-|u|) = t 2^(Q(t) - u^2 log2(e)/2), Q = log2(e) P - 1,
+// and GELU(u) = max(u, 0) - |u| Phi(-|u|) (one fused multiply-add for both
+// signs; an infinite u gives NaN there).  Relative error within 1.7e-5 of
+// the exact GELU for every finite u; the activations are then rounded to
+// BF16 (unit roundoff 2^-8).
 __device__ __forceinline__ float gelu(float u)
 {
-    const float z = fabsf(u) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);
-    float p = -1.661221119e-01f;
-    p = fmaf(p, t, 6.685151608e-01f);
-    p = fmaf(p, t, -8.729041482e-01f);
-    p = fmaf(p, t, 2.482906394e-01f);
-    p = fmaf(p, t, 4.035713614e-03f);
-    p = fmaf(p, t, 3.840898445e-01f);
-    p = fmaf(p, t, 9.996045788e-01f);
-    p = fmaf(p, t, -1.265509297e+00f);
-    const float half = 0.5f * t * __expf(p - z * z);
-    return u * (u >= 0.0f ? 1.0f - half : half);
+    const float a = fabsf(u);
+    const float t = __builtin_amdgcn_rcpf(fmaf(a, 0.35355339059327373f, 1.0f));
+    float q = -2.396635413e-01f;
+    q = fmaf(q, t, 9.644635320e-01f);
+    q = fmaf(q, t, -1.259334445e+00f);
+    q = fmaf(q, t, 3.582076728e-01f);
+    q = fmaf(q, t, 5.822304171e-03f);
+    q = fmaf(q, t, 5.541245341e-01f);
+    q = fmaf(q, t, 1.442124605e+00f);
+    q = fmaf(q, t, -2.825743914e+00f);
+    const float half = t * __builtin_amdgcn_exp2f(fmaf(u * u, -0.72134752044448170f, q));
+    return fmaf(-a, half, fmaxf(u, 0.0f));
 }
 
 // Activation FP32 -> BF16 with the hardware conversion (round to nearest even).
@@ -203,12 +207,15 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
             bf16x8 a[kMlpRB];
 #pragma unroll
             for (int i = 0; i < kMlpRB; i++) __builtin_memcpy(&a[i], arow + i * 16 * ldi + ks * 32, 16);
+            // weights as the first operand: the output tile comes out
+            // transposed (lane l: columns 4 (l/16) .. +3 of row l % 16), so
+            // each lane's four results are adjacent in a row of the output
 #pragma unroll
             for (int j = 0; j < J; j++)
                 if (w + kMlpWaves * j < nblk)
 #pragma unroll
                     for (int i = 0; i < kMlpRB; i++)
-                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bq[d][j], acc[j][i], 0, 0, 0);
+                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[d][j], a[i], acc[j][i], 0, 0, 0);
             const int kn = ks + kMlpDepth;
 #pragma unroll
             for (int j = 0; j < J; j++)
@@ -219,20 +226,26 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
     for (int j = 0; j < J; j++) {
         const int jb = w + kMlpWaves * j;
         if (jb >= nblk) continue;
-        const int n = jb * 16 + (lane & 15);
-        const float bn = bias[n];
+        const int n0 = jb * 16 + (lane >> 4) * 4;
+        float bn[4];
 #pragma unroll
-        for (int i = 0; i < kMlpRB; i++)
+        for (int r = 0; r < 4; r++) bn[r] = bias[n0 + r];
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int m = i * 16 + (lane >> 4) * 4 + r;
-                const float u = acc[j][i][r] + bn;
-                if (outs) {
-                    outs[m * lds_out + n] = act_bf16(gelu(u));
-                } else if (r0 + m < rows) {
-                    outg[(r0 + m) * ldg + n] = u;
-                }
+        for (int i = 0; i < kMlpRB; i++) {
+            const int m = i * 16 + (lane & 15);
+            if (outs) {
+                // four activations of row m, columns n0 .. n0 + 3: one 8-byte store
+                bf16_t h[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) h[r] = act_bf16(gelu(acc[j][i][r] + bn[r]));
+                uint2 pk;
+                __builtin_memcpy(&pk, h, 8);
+                *(uint2 *)(outs + m * lds_out + n0) = pk;
+            } else if (r0 + m < rows) {
+#pragma unroll
+                for (int r = 0; r < 4; r++) outg[(r0 + m) * ldg + n0 + r] = acc[j][i][r] + bn[r];
             }
+        }
     }
 }
 
