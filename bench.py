@@ -32,8 +32,11 @@ Other workloads (``--workload``):
              256^3 field (16,777,216 cells) and --graph replays the captured
              step; the plain integrator then runs on a seeded sample.  With
              --evolve the timed steps advance the field (no restore inside the
-             step) and the drift against the plain integrator over the same
-             steps is reported on a seeded sample of cells.
+             step), the network is first trained further on the states it
+             visits itself (three rollout rounds, each labelled by the
+             integrator), and the fallback count and the drift against the
+             plain integrator, advanced in step on a seeded sample of cells,
+             are reported after every step.
 """
 from __future__ import annotations
 
@@ -320,8 +323,11 @@ def run_surrogate(args, nested: bool = False):
     t0 = time.perf_counter()
     n_half = args.train_samples // 2
     T1, p1, Y1 = flame_like_states(mpy, n_half, seed=7)
-    n_traj = max(1, n_half // args.traj_steps)
-    T2, p2, Y2 = trajectory_starts(mpy, n_traj, seed=8)
+    n_traj = max(2, n_half // args.traj_steps)
+    # trajectories from cold unburnt mixtures and from flame-like states
+    T2, p2, Y2 = trajectory_starts(mpy, n_traj // 2, seed=8)
+    T3, p3, Y3 = flame_like_states(mpy, n_traj - n_traj // 2, seed=9)
+    T2, p2, Y2 = np.concatenate([T2, T3]), np.concatenate([p2, p3]), np.concatenate([Y2, Y3], axis=1)
     Tt, pt, Yt = t(T2), t(p2), t(Y2)
     Ts, Ys = [], []
     for _ in range(args.traj_steps):
@@ -348,7 +354,49 @@ def run_surrogate(args, nested: bool = False):
     losses = surr.train(Td, pd, Yd, Yn, epochs=args.epochs, batch=4096, lr0=1e-3, lr1=1e-5, order=order)
     log["train_s"] = time.perf_counter() - t0
     progress(f"trained {args.epochs} epochs in {log['train_s']:.1f} s")
-    del Td, pd, Yd, Yn, Tn, order
+    del order
+    # ---- rollout rounds (data aggregation, DAgger): the trained surrogate
+    # advances fresh flame-like states for several flow steps, feeding on its
+    # own output (with its checks and fallback, as served); every state it
+    # visits is labelled by one step of the GPU integrator and added to the
+    # training set, which the network is then trained on further
+    log["rollout"] = []
+    for r in range(args.rollout_rounds):
+        # round r rolls out half as many cells for twice as many steps as
+        # round r - 1 (the same number of visited states): later rounds reach
+        # the states a long served run drifts into
+        t0 = time.perf_counter()
+        r_cells, r_steps = max(64, args.rollout_cells >> r), args.rollout_steps << r
+        T4, p4, Y4 = flame_like_states(mpy, r_cells, seed=20 + r)
+        Tr, pr, Yr = t(T4), t(p4), t(Y4)
+        vis_T, vis_Y = [], []
+        fb_cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        fbs = []
+        for _ in range(r_steps):
+            surr.infer(Tr, pr, Yr, dt, fallback_count=fb_cnt)
+            vis_T.append(Tr.clone())
+            vis_Y.append(Yr.clone())
+            fbs.append(fb_cnt.clone())
+        Tv = torch.cat(vis_T)
+        Yv = torch.cat(vis_Y, dim=1).contiguous()
+        pv = t(np.full(Tv.shape[0], p4[0]))
+        del vis_T, vis_Y
+        Tvn, Yvn = Tv.clone(), Yv.clone()
+        mech.integrate(Tvn, pv, Yvn, dt)
+        Td, pd = torch.cat([Td, Tv]), torch.cat([pd, pv])
+        Yd, Yn = torch.cat([Yd, Yv], dim=1).contiguous(), torch.cat([Yn, Yvn], dim=1).contiguous()
+        del Tv, Yv, Tvn, Yvn, pv
+        n_train = Td.shape[0]
+        order = t(epoch_orders(n_train, args.rollout_epochs, 40 + r), torch.int32)
+        l2 = surr.train(Td, pd, Yd, Yn, epochs=args.rollout_epochs, batch=4096, lr0=3e-4, lr1=1e-5, order=order)
+        del order
+        rollout_fb = [int(x.item()) for x in fbs]
+        log["rollout"].append({"round": r + 1, "cells": r_cells, "steps": r_steps, "visited_states": r_cells * r_steps,
+                               "fallback_per_step": rollout_fb, "loss_first": float(l2[0]),
+                               "loss_last": float(l2[-1]), "s": time.perf_counter() - t0})
+        progress(f"rollout round {r + 1}: fallback per step {rollout_fb}, {n_train} states, "
+                 f"loss {l2[0]:.4g} -> {l2[-1]:.4g}, {time.perf_counter() - t0:.1f} s")
+    del Td, pd, Yd, Yn, Tn
     torch.cuda.empty_cache()
     # ---- the served field
     field = F.flame256x128x128(mpy) if args.field == "flame256x128x128" else F.flame256(mpy)
@@ -392,9 +440,15 @@ def run_surrogate(args, nested: bool = False):
         graph.replay()
     torch.cuda.synchronize()
     if evolve:
-        T_start, Y_start = T.clone(), Y.clone()
+        # the plain integrator advances a seeded sample of the same cells
+        # over the same flow steps, in step with the served field (cells are
+        # independent): drift and fallback are recorded after every step
+        from chemgen.fields import seeded_sample
+        didx = seeded_sample(n, min(args.drift_cells, n), seed=13)
+        di = torch.tensor(didx, dtype=torch.int64, device=dev)
+        Td, Yd, pd = T[di].clone(), Y[:, di].contiguous(), p0[di].contiguous()
+        per_step = []
     t0 = time.perf_counter()
-    fb_trace = []
     for k in range(args.steps):
         if graph is not None:
             events[k][0].record(stream)
@@ -402,30 +456,31 @@ def run_surrogate(args, nested: bool = False):
             events[k][1].record(stream)
         else:
             step(events[k])
-        if evolve and (k % 10 == 9 or k == args.steps - 1):
-            # an evolving field changes its fallback set: report it as it goes
-            fb_trace.append(int(cnt.item()))
-            progress(f"step {k + 1}: {fb_trace[-1]} fallback cells, {time.perf_counter() - t0:.1f} s")
+        if evolve:
+            mech.integrate(Td, pd, Yd, dt)
+            dTk = (T[di] - Td).abs()
+            per_step.append({"step": k + 1, "fallback_cells": int(cnt.item()),
+                             "max_dT": float(dTk.max().item()), "mean_abs_dT": float(dTk.mean().item()),
+                             "max_dY": float((Y[:, di] - Yd).abs().max().item())})
+            if k % 10 == 9 or k == args.steps - 1:
+                progress(f"step {k + 1}: {per_step[-1]['fallback_cells']} fallback cells, drift max|dT| "
+                         f"{per_step[-1]['max_dT']:.3f} K, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    if evolve:
+        # the drift check ran between the steps: the rate is the served
+        # steps' own time (HIP events around each step)
+        wall = kern_ms * 1e-3 * args.steps
     progress(f"{args.steps} timed surrogate steps: {wall / args.steps * 1e3:.2f} ms per step")
     drift = None
     if evolve:
-        # the plain integrator over the same flow steps from the same start,
-        # on a seeded sample of the cells (cells are independent)
-        from chemgen.fields import seeded_sample
-        didx = seeded_sample(n, min(args.drift_cells, n), seed=13)
-        di = torch.tensor(didx, dtype=torch.int64, device=dev)
-        Td, Yd, pd = T_start[di].clone(), Y_start[:, di].contiguous(), p0[di].contiguous()
-        for _ in range(args.steps):
-            mech.integrate(Td, pd, Yd, dt)
-        torch.cuda.synchronize()
-        drift = {"steps": args.steps, "cells": int(didx.size), "fallback_cells_every_10_steps": fb_trace,
-                 "max_dT": float((T[di] - Td).abs().max().item()),
-                 "max_dY": float((Y[:, di] - Yd).abs().max().item()),
-                 "mean_abs_dT": float((T[di] - Td).abs().mean().item())}
-        progress(f"drift after {args.steps} steps on {didx.size} cells: max|dT| {drift['max_dT']:.3f} K")
+        drift = {"steps": args.steps, "cells": int(didx.size), "per_step": per_step,
+                 "max_fallback_frac": max(x["fallback_cells"] for x in per_step) / n,
+                 "max_dT": max(x["max_dT"] for x in per_step),
+                 "max_dY": max(x["max_dY"] for x in per_step)}
+        progress(f"drift over {args.steps} steps on {didx.size} cells: max|dT| {drift['max_dT']:.3f} K, "
+                 f"largest fallback fraction {drift['max_fallback_frac']:.2e}")
         # one step from the pristine field for the single-step accuracy below
         T.copy_(T0)
         Y.copy_(Y0)
@@ -486,7 +541,8 @@ def run_surrogate(args, nested: bool = False):
         "evolving_state": bool(evolve),
         "drift": drift,
         "train": {"samples": n_train, "epochs": args.epochs, "loss_first": float(losses[0]),
-                  "loss_last": float(losses[-1]), "label_s": log["label_s"], "train_s": log["train_s"]},
+                  "loss_last": float(losses[-1]), "label_s": log["label_s"], "train_s": log["train_s"],
+                  "rollout_rounds": log["rollout"]},
     }
     if not args.no_cpu_baseline:
         # the oracle on a seeded uniform subset of the served cells: the
@@ -532,6 +588,13 @@ def main():
                     help="surrogate: timed steps advance the field (no restore); the drift against the plain "
                          "integrator over the same steps is reported on a seeded sample")
     ap.add_argument("--drift-cells", type=int, default=16384, help="surrogate --evolve: cells of the drift check")
+    ap.add_argument("--rollout-rounds", type=int, default=None,
+                    help="surrogate: rounds of rollout data aggregation after the first training "
+                         "(default 3 with --evolve, else 0: the single-step workload trains on 2M states, "
+                         "20 epochs)")
+    ap.add_argument("--rollout-cells", type=int, default=65536, help="surrogate: flame-like states per rollout")
+    ap.add_argument("--rollout-steps", type=int, default=32, help="surrogate: flow steps of each rollout")
+    ap.add_argument("--rollout-epochs", type=int, default=10, help="surrogate: epochs after each rollout")
     ap.add_argument("--shuffle", action="store_true",
                     help="integrator workloads: the field's cells in a seeded random order")
     ap.add_argument("--plain-cells", type=int, default=262144,
@@ -545,6 +608,8 @@ def main():
                     help="only run a plain device copy of 512 MiB three times (scales the HBM "
                          "byte counters of a profiler run)")
     args = ap.parse_args()
+    if args.rollout_rounds is None:
+        args.rollout_rounds = 3 if args.evolve else 0
     if args.copy_calibration:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda:0")
