@@ -19,8 +19,12 @@
  *  - Species arrays are structure-of-arrays: Y[k * ldY + i] for species k of
  *    cell i, with ldY >= ncells.
  *  - hip_stream is a hipStream_t (NULL = default stream).  Calls only enqueue
- *    work on that stream: no host synchronisation and no allocation, so they
- *    may be captured in a HIP graph.  Workspace is allocated at mechanism load.
+ *    work on that stream: no host synchronisation, so they may be captured in
+ *    a HIP graph (paper Section 3.2: one graph launch per time step).
+ *    Workspace is allocated at mechanism load, or grown by the first call of
+ *    a given size on a stream; a call that would have to grow it while the
+ *    stream is being captured fails with CHEM_EINVAL (make the same call
+ *    eagerly first); chem_integrate_noalloc never allocates.
  *  - Per-cell numerical failures are not call errors: they are reported in
  *    status[] and the failed cell keeps its input state.
  */
@@ -88,25 +92,31 @@ typedef struct {
     int32_t reserved[6];
 } chem_opts;
 
-/* Fill opts with the defaults above. */
+/* Fill opts with the defaults above (rtol, atol and the BDF limits of the
+ * paper's CVODE method, Section 2). */
 int chem_default_opts(chem_opts *opts);
 
 /* Read a .mech file (format "CHEMMECH 1": elements with atomic weights,
  * species with element counts and two NASA-7 ranges, reactions with <= 2
  * reactant and <= 2 product molecules, A in cm-mol-s units, b, Ea in J/mol),
  * validate it (element balance, indices, finite coefficients) and upload its
- * tables to `device`.  The handle owns its device memory; it is immutable
- * after loading and may be used from several streams of that device. */
+ * tables to `device` (paper Section 3.2: the constant coefficients of the
+ * property kernels live in fast read-only memory; here one device block that
+ * the kernels copy into LDS).  The handle owns its device memory; it is
+ * immutable after loading and may be used from several streams of that
+ * device. */
 int chem_load_mechanism(const char *path, int device, chem_mech *out);
 void chem_free_mechanism(chem_mech mech);
 /* Number of species, reactions, elements; W (may be NULL) receives the K
- * species molar masses in kg/mol (host memory). */
+ * species molar masses in kg/mol (host memory; the mechanism of Section 2's
+ * detailed kinetics). */
 int chem_mechanism_info(chem_mech mech, int32_t *K, int32_t *R, int32_t *E, double *W);
 
 /* Which kernels serve this mechanism: "specialised:<tag>" when the file was
  * compiled into the library by the mechanism compiler (straight-line
- * right-hand side and Jacobian), "table" for the table-driven kernels.
- * The string is owned by the handle. */
+ * right-hand side and Jacobian: the coefficients in the instruction stream,
+ * Section 3.2's constant-memory placement taken one step further), "table"
+ * for the table-driven kernels.  The string is owned by the handle. */
 const char *chem_mechanism_variant(chem_mech mech);
 
 /* Advance ncells cells over [0, dt] in place (the per-cell chemistry source
@@ -169,7 +179,9 @@ typedef struct {
     int64_t status_count[8];  /* cells per status code 0..7 (CHEM_CELL_*) */
 } chem_stats;
 
-/* Reduce the per-cell outputs of a call: status[n] (device, may be NULL)
+/* Per-call statistics (the work behind Table 1's chemistry time: steps,
+ * rejections, Newton iterations, Jacobians, fallback cells).
+ * Reduce the per-cell outputs of a call: status[n] (device, may be NULL)
  * and counters[6][n] (device, layout of chem_integrate; may be NULL) into
  * *out (host), plus the fallback count of chem_surrogate_infer (device, may
  * be NULL).  A diagnostics call: allocates a small device buffer, enqueues
@@ -179,13 +191,18 @@ typedef struct {
 int chem_get_stats(const int32_t *status, const int32_t *counters, int64_t n, const int64_t *fallback_count,
                    chem_stats *out, void *hip_stream);
 
-/* Longest-processing-time-first order: order[0..n) (device) receives the
+/* Load balance across uneven per-cell stiffness (the chemistry is
+ * communication-free per cell, Section 1; its cost per cell varies by
+ * orders of magnitude between cold and flame-front cells).
+ * Longest-processing-time-first order: order[0..n) (device) receives the
  * indices 0..n-1 sorted by descending cost[i] (device int32, e.g. the step
  * counts of the previous flow step), ties in index order.  A planning call:
  * allocates temporary device memory and synchronises the stream. */
 int chem_lpt_order(const int32_t *cost, int64_t n, int32_t *order, void *hip_stream);
 
-/* Autotuner: times every schedule that can serve the mechanism at
+/* Launch configuration chosen by measurement (Section 3.2: optimisations of
+ * the kernels and of their launch).
+ * Autotuner: times every schedule that can serve the mechanism at
  * opts->precision (one thread per cell with jac_batch 4, 16, 64; one wave
  * per cell; the 16-lane tile when K <= 15), each in natural and in LPT
  * order, on a strided sample of at
@@ -198,13 +215,15 @@ int chem_autotune(chem_mech mech, const double *T, const double *p, const double
                   int64_t ncells, double dt, const chem_opts *opts, int32_t max_sample,
                   chem_opts *best, int32_t *use_lpt, double *best_ms, void *hip_stream);
 
-/* Right-hand side of the reactor ODE at the given states (diagnostics and
- * parity tests of the kernels' building blocks).  F has N = K+1 rows of
+/* Right-hand side of the reactor ODE at the given states (Section 2's
+ * species and temperature equations; diagnostics and parity tests of the
+ * kernels' building blocks).  F has N = K+1 rows of
  * stride ldF (rows 0..K-1: dY_k/dt in 1/s, row K: dT/dt in K/s). */
 int chem_eval_rhs(chem_mech mech, const double *T, const double *p, const double *Y, int64_t ldY,
                   int64_t ncells, double *F, int64_t ldF, void *hip_stream);
 
-/* Analytic Jacobian d f / d y of the same ODE, y = (Y_1..Y_K, T): element
+/* Analytic Jacobian d f / d y of the same ODE (the Newton matrix of the
+ * implicit BDF method, Section 2), y = (Y_1..Y_K, T): element
  * (r, c) of cell i at J[(r * N + c) * ldJ + i]. */
 int chem_eval_jacobian(chem_mech mech, const double *T, const double *p, const double *Y,
                        int64_t ldY, int64_t ncells, double *J, int64_t ldJ, void *hip_stream);
@@ -256,7 +275,8 @@ typedef struct {
 
 int chem_surrogate_default_checks(chem_surr_checks *checks);
 
-/* New surrogate for mech with zero parameters and unset normalisation. */
+/* New surrogate for mech (Section 2's network, hidden widths h1, h2, h3)
+ * with zero parameters and unset normalisation. */
 int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out);
 void chem_free_surrogate(chem_surr surr);
 /* dims[0..5] = K+2, h1, h2, h3, K, number of logical parameters. */
@@ -267,17 +287,20 @@ int chem_surrogate_get_params(chem_surr surr, float *params, int64_t count);
 /* Host FP64 normalisation vector in / out (2 (K+2) + 2 K + 1 values). */
 int chem_surrogate_set_norm(chem_surr surr, const double *norm, int64_t count);
 int chem_surrogate_get_norm(chem_surr surr, double *norm, int64_t count);
-/* Normalisation from training samples (device): states T, p, Y and the mass
+/* Input/output scaling of the network (Section 2's inputs T, p, Y).
+ * Normalisation from training samples (device): states T, p, Y and the mass
  * fractions Ynext[k * ldYn + i] of the same cells one flow step dt later.
  * Population mean and standard deviation of each feature and of each
  * dY_k = Ynext_k - Y_k.  Synchronises the stream. */
 int chem_surrogate_fit_norm(chem_surr surr, const double *T, const double *p, const double *Y,
                             int64_t ldY, const double *Ynext, int64_t ldYn, int64_t n, double dt,
                             void *hip_stream);
-/* Network input of n cells: X[i * 64 + j] BF16 bit patterns (device, n x 64). */
+/* Network input of n cells (Section 2: temperature, pressure and mass
+ * fractions): X[i * 64 + j] BF16 bit patterns (device, n x 64). */
 int chem_surrogate_encode(chem_surr surr, const double *T, const double *p, const double *Y,
                           int64_t ldY, int64_t n, uint16_t *X, void *hip_stream);
-/* Network output for n encoded rows: out[i * ldo + k], k < K (device FP32,
+/* Network output for n encoded rows (Section 2: three GELU hidden layers;
+ * Section 3.1: inference on the GPU): out[i * ldo + k], k < K (device FP32,
  * ldo >= K rounded up to 16; columns K..ldo-1 are written with the padding
  * outputs). */
 int chem_surrogate_forward(chem_surr surr, const uint16_t *X, int64_t n, float *out, int64_t ldo,
@@ -305,14 +328,18 @@ int chem_surrogate_set_pass_rows(chem_surr surr, int64_t rows);
  * checks of the kernels; n <= 2^20. */
 int chem_surrogate_forward_trace(chem_surr surr, const uint16_t *X, int64_t n, uint16_t *H1, uint16_t *H2,
                                  uint16_t *H3, float *out, int64_t ldo, void *hip_stream);
-/* Decode, temperature recovery and checks of n cells from a network output
+/* Decode, temperature recovery and checks (Section 3.1: the temperature
+ * follows from the enthalpy by Newton's method on the temperature
+ * polynomials) of n cells from a network output
  * (device, layout of chem_surrogate_forward): accepted cells take the
  * prediction in place, mask[i] = 1 marks the rejected ones (their state is
  * unchanged).  No integration. */
 int chem_surrogate_apply(chem_surr surr, double *T, const double *p, double *Y, int64_t ldY,
                          int64_t n, const float *out, int64_t ldo, const chem_surr_checks *checks,
                          int32_t *mask, void *hip_stream);
-/* One flow step of n cells by the surrogate with per-cell fallback: encode,
+/* The DNN chemistry of one flow step (Section 2 option 2; Table 1's GPU
+ * chemistry), with per-cell fallback to the integrator (Section 2 option 1).
+ * One flow step of n cells by the surrogate with per-cell fallback: encode,
  * network, decode and checks; rejected cells are integrated by
  * chem_integrate (opts) over dt.  mask (nullable): 1 for fallback cells.
  * status (nullable): integrator status of fallback cells, 0 elsewhere.
@@ -322,7 +349,8 @@ int chem_surrogate_infer(chem_surr surr, double *T, const double *p, double *Y, 
                          int64_t n, double dt, const chem_opts *opts,
                          const chem_surr_checks *checks, int32_t *mask, int32_t *status,
                          int64_t *fallback_count, void *hip_stream);
-/* Loss and parameter gradient of one batch: X (device, n x 64 BF16 rows as
+/* Training building blocks (Section 2: the network is trained with Adam).
+ * Loss and parameter gradient of one batch: X (device, n x 64 BF16 rows as
  * from chem_surrogate_encode), targets Yt[i * ldt + k] (device FP32 z-scored
  * dY, ldt >= K).  Loss = mean over the n x K entries of (out - Yt)^2; the
  * gradient is kept inside the handle.  *loss is written (host).  Synchronises. */
@@ -334,7 +362,8 @@ int chem_surrogate_set_grads(chem_surr surr, const float *grads, int64_t count);
 /* One Adam step (beta 0.9, 0.999, eps 1e-8, bias corrected) with the handle's
  * gradient and learning rate lr; the step counter is kept in the handle. */
 int chem_surrogate_adam(chem_surr surr, double lr, void *hip_stream);
-/* Training: encodes the n samples (states T, p, Y and Ynext one flow step of
+/* Training (Section 2: GELU network trained with Adam on states labelled by
+ * the integrator): encodes the n samples (states T, p, Y and Ynext one flow step of
  * the normalisation's dt later, device; the target is the z-scored
  * Ynext - Y), then `epochs` passes of minibatches of `batch`
  * rows in the sample order order[e * n + i] (device int32, NULL = 0..n-1 every
@@ -346,7 +375,9 @@ int chem_surrogate_train(chem_surr surr, const double *T, const double *p, const
                          int64_t ldY, const double *Ynext, int64_t ldYn, int64_t n,
                          const int32_t *order, int32_t epochs, int32_t batch, double lr0,
                          double lr1, double *loss_per_epoch, void *hip_stream);
-/* Versioned file: magic, dimensions, normalisation, FP32 parameters, checksum. */
+/* Weights file (the trained network the paper's inference loads, Section
+ * 3.1): versioned, magic, dimensions, normalisation, FP32 parameters,
+ * checksum. */
 int chem_surrogate_save(chem_surr surr, const char *path);
 int chem_surrogate_load(chem_mech mech, const char *path, chem_surr *out);
 
