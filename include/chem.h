@@ -375,11 +375,34 @@ int chem_surrogate_train(chem_surr surr, const double *T, const double *p, const
                          int64_t ldY, const double *Ynext, int64_t ldYn, int64_t n,
                          const int32_t *order, int32_t epochs, int32_t batch, double lr0,
                          double lr1, double *loss_per_epoch, void *hip_stream);
+/* Part of a training run (resume after a checkpoint): epochs
+ * [first_epoch, first_epoch + epochs) of a run of total_epochs, with the
+ * cosine learning rate taken over the whole run, so that a run cut into parts
+ * (with the optimiser state kept, in the handle or through a checkpoint file)
+ * takes exactly the steps of the uncut run.  order holds the `epochs` orders
+ * of this part (order[(e - first_epoch) * n + i]); the rest as
+ * chem_surrogate_train, which is the part (0, epochs, epochs). */
+int chem_surrogate_train_part(chem_surr surr, const double *T, const double *p, const double *Y,
+                              int64_t ldY, const double *Ynext, int64_t ldYn, int64_t n,
+                              const int32_t *order, int32_t first_epoch, int32_t epochs,
+                              int32_t total_epochs, int32_t batch, double lr0, double lr1,
+                              double *loss_per_epoch, void *hip_stream);
 /* Weights file (the trained network the paper's inference loads, Section
- * 3.1): versioned, magic, dimensions, normalisation, FP32 parameters,
- * checksum. */
+ * 3.1): magic, version, dimensions, normalisation, FP32 parameters in logical
+ * order, FNV-1a checksum.  chem_surrogate_save writes version 1 (no training
+ * state); chem_surrogate_save_checkpoint writes version 2, which adds the
+ * Adam step and both moment vectors and user_bytes (0..2^20) of the caller's
+ * own data (host memory: the state of the generator of its sample orders).
+ * chem_surrogate_load reads either version (a version 2 file restores the
+ * optimiser state too) and rejects a file whose checksum, sizes or dimensions
+ * do not agree or whose species count is not the mechanism's.
+ * chem_surrogate_checkpoint_user copies a version 2 file's user bytes into
+ * user (host, capacity bytes) and their count into *user_bytes; CHEM_EINVAL
+ * (with *user_bytes set) when they do not fit. */
 int chem_surrogate_save(chem_surr surr, const char *path);
+int chem_surrogate_save_checkpoint(chem_surr surr, const char *path, const void *user, int64_t user_bytes);
 int chem_surrogate_load(chem_mech mech, const char *path, chem_surr *out);
+int chem_surrogate_checkpoint_user(const char *path, void *user, int64_t capacity, int64_t *user_bytes);
 
 #ifdef __cplusplus
 }

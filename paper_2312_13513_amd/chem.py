@@ -97,6 +97,10 @@ def _load():
     L.chem_surrogate_set_pass_rows.argtypes = [vp, i64]
     L.chem_surrogate_save.argtypes = [vp, C.c_char_p]
     L.chem_surrogate_load.argtypes = [vp, C.c_char_p, C.POINTER(vp)]
+    L.chem_surrogate_train_part.argtypes = [vp, dp, dp, dp, i64, dp, i64, i64, dp, C.c_int32, C.c_int32,
+                                            C.c_int32, C.c_int32, C.c_double, C.c_double, dblp, vp]
+    L.chem_surrogate_save_checkpoint.argtypes = [vp, C.c_char_p, C.c_char_p, i64]
+    L.chem_surrogate_checkpoint_user.argtypes = [C.c_char_p, C.c_char_p, i64, i64p]
     return L
 
 
@@ -113,7 +117,8 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_apply", "chem_surrogate_infer", "chem_surrogate_grad",
             "chem_surrogate_get_grads", "chem_surrogate_set_grads", "chem_surrogate_adam",
             "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_reserve",
-            "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace", "chem_integrate_noalloc")
+            "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace", "chem_integrate_noalloc",
+            "chem_surrogate_train_part", "chem_surrogate_save_checkpoint", "chem_surrogate_checkpoint_user")
 
 
 def lib():
@@ -324,6 +329,20 @@ class Surrogate:
     def save(self, path: str):
         _check(_lib.chem_surrogate_save(C.c_void_p(self.handle), path.encode()))
 
+    def save_checkpoint(self, path: str, user: bytes = b""):
+        """Weights, normalisation and optimiser state, plus the caller's bytes."""
+        _check(_lib.chem_surrogate_save_checkpoint(C.c_void_p(self.handle), path.encode(), bytes(user), len(user)))
+
+    @staticmethod
+    def checkpoint_user(path: str) -> bytes:
+        n = C.c_int64(0)
+        rc = _lib.chem_surrogate_checkpoint_user(path.encode(), None, 0, C.byref(n))
+        if rc != CHEM_OK and n.value == 0:
+            _check(rc)
+        buf = C.create_string_buffer(max(1, n.value))
+        _check(_lib.chem_surrogate_checkpoint_user(path.encode(), buf, n.value, C.byref(n)))
+        return buf.raw[:n.value]
+
     def set_params(self, params):
         a, p = _host_f32(params)
         _check(_lib.chem_surrogate_set_params(C.c_void_p(self.handle), p, a.size))
@@ -412,4 +431,15 @@ class Surrogate:
                                          _ptr(Ynext), Ynext.shape[1], T.shape[0], _ptr(order), int(epochs), int(batch),
                                          float(lr0), float(lr1), losses.ctypes.data_as(C.POINTER(C.c_double)),
                                          _stream(stream)))
+        return losses
+
+    def train_part(self, T, p, Y, Ynext, first_epoch: int, epochs: int, total_epochs: int, batch: int,
+                   lr0: float = 1e-3, lr1: float = 1e-5, order=None, stream=None):
+        import numpy as np
+        losses = np.zeros(int(epochs))
+        _check(_lib.chem_surrogate_train_part(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1],
+                                              _ptr(Ynext), Ynext.shape[1], T.shape[0], _ptr(order),
+                                              int(first_epoch), int(epochs), int(total_epochs), int(batch),
+                                              float(lr0), float(lr1), losses.ctypes.data_as(C.POINTER(C.c_double)),
+                                              _stream(stream)))
         return losses

@@ -11,21 +11,9 @@
 #include "chem.h"
 #include "bdf_driver.h"
 #include "bdf_wave.h"
+#include "mech_file.h"
 
 namespace chem_host {
-
-struct HostRxn {
-    std::vector<std::pair<int, int>> reac, prod;   // (species, coefficient)
-    double A = 0, b = 0, Ea = 0;
-};
-
-struct HostMech {
-    int K = 0, R = 0, E = 0;
-    std::vector<double> aw;                 // atomic weights, g/mol
-    std::vector<std::vector<int>> counts;   // K x E
-    std::vector<std::vector<double>> nasa;  // K x 17
-    std::vector<HostRxn> rxn;
-};
 
 // Records msg as the calling thread's last error and returns code.
 int fail(int code, const std::string &msg);
@@ -77,7 +65,7 @@ struct DevBuf {
 
 struct chem_mech_s {
     int device = 0;
-    chem_host::HostMech host;
+    chem_file::HostMech host;
     std::vector<double> W;
     chem::DevMechView view{};
     void *dev_block = nullptr;

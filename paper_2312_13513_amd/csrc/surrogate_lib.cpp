@@ -12,6 +12,7 @@
 
 #include "host_common.h"
 #include "surrogate.h"
+#include "surr_file.h"
 
 using chem::bf16_t;
 using chem_host::check_hip;
@@ -332,15 +333,6 @@ chem::AdamArgs adam_args(chem_surr_s *s, double lr)
     return chem::AdamArgs{s->master, s->am, s->av, s->grad, s->n_pad, (float)lr, (float)kBeta1,
                           (float)kBeta2, (float)(1.0 - kBeta1), (float)(1.0 - kBeta2), (float)kEps,
                           (float)(1.0 - std::pow(kBeta1, t)), (float)(1.0 - std::pow(kBeta2, t))};
-}
-
-unsigned long long fnv1a(const char *p, size_t n, unsigned long long h = 0xCBF29CE484222325ull)
-{
-    for (size_t i = 0; i < n; i++) {
-        h ^= (unsigned char)p[i];
-        h *= 0x100000001B3ull;
-    }
-    return h;
 }
 
 }  // namespace
@@ -806,15 +798,18 @@ int chem_surrogate_adam(chem_surr s, double lr, void *stream)
     return refresh_bf16(s, st);
 }
 
-int chem_surrogate_train(chem_surr s, const double *T, const double *p, const double *Y, int64_t ldY,
-                         const double *Yn, int64_t ldYn, int64_t n, const int32_t *order, int32_t epochs,
-                         int32_t batch, double lr0, double lr1, double *loss_per_epoch, void *stream)
+int chem_surrogate_train_part(chem_surr s, const double *T, const double *p, const double *Y, int64_t ldY,
+                              const double *Yn, int64_t ldYn, int64_t n, const int32_t *order,
+                              int32_t first_epoch, int32_t epochs, int32_t total_epochs, int32_t batch,
+                              double lr0, double lr1, double *loss_per_epoch, void *stream)
 {
     int rc = check_surr(s);
     if (rc != CHEM_OK) return rc;
     if (n < 1 || ldY < n || ldYn < n) return fail(CHEM_EINVAL, "need n >= 1 and ldY, ldYn >= n");
     if (n > INT32_MAX) return fail(CHEM_EINVAL, "n must fit in int32");
     if (epochs < 1 || batch < 1 || batch > (1 << 20)) return fail(CHEM_EINVAL, "bad epochs or batch");
+    if (first_epoch < 0 || total_epochs < 1 || (int64_t)first_epoch + epochs > total_epochs)
+        return fail(CHEM_EINVAL, "need 0 <= first_epoch and first_epoch + epochs <= total_epochs");
     if (!(lr0 >= 0.0) || !(lr1 >= 0.0)) return fail(CHEM_EINVAL, "learning rates must be >= 0");
     if (!s->norm_set) return fail(CHEM_EINVAL, "the surrogate has no normalisation");
     if (!is_device_ptr(T) || !is_device_ptr(p) || !is_device_ptr(Y) || !is_device_ptr(Yn) ||
@@ -836,8 +831,8 @@ int chem_surrogate_train(chem_surr s, const double *T, const double *p, const do
         e = chem::launch_targets(Y, ldY, Yn, ldYn, n, s->K, s->nout_pad, s->norm_dev + 2 * s->nin,
                                  s->norm_dev + 2 * s->nin + s->K, Yall, st);
     const int64_t per_epoch = (n + batch - 1) / batch;
-    const int64_t total = per_epoch * epochs;
-    int64_t step = 0;
+    const int64_t total = per_epoch * total_epochs;
+    int64_t step = per_epoch * first_epoch;
     for (int ep = 0; ep < epochs && e == hipSuccess; ep++) {
         e = hipMemsetAsync(s->loss_dev, 0, sizeof(double), st);
         for (int64_t b = 0; b < per_epoch && e == hipSuccess; b++, step++) {
@@ -869,87 +864,111 @@ int chem_surrogate_train(chem_surr s, const double *T, const double *p, const do
     return check_hip(e, "training");
 }
 
+int chem_surrogate_train(chem_surr s, const double *T, const double *p, const double *Y, int64_t ldY,
+                         const double *Yn, int64_t ldYn, int64_t n, const int32_t *order, int32_t epochs,
+                         int32_t batch, double lr0, double lr1, double *loss_per_epoch, void *stream)
+{
+    return chem_surrogate_train_part(s, T, p, Y, ldY, Yn, ldYn, n, order, 0, epochs, epochs, batch, lr0, lr1,
+                                     loss_per_epoch, stream);
+}
+
+namespace {
+
+// The handle's network, normalisation and, with opt, optimiser state as a file image.
+int surr_to_file(chem_surr s, bool opt, chem_file::SurrFile &f)
+{
+    f.K = s->K;
+    f.nin = s->nin;
+    for (int l = 0; l < 3; l++) f.h[l] = s->h[l];
+    f.norm_set = s->norm_set;
+    f.norm = s->norm;
+    f.norm.resize((size_t)norm_len(s), 0.0);
+    f.params.resize((size_t)s->n_logical);
+    int rc = chem_surrogate_get_params(s, f.params.data(), s->n_logical);
+    if (rc != CHEM_OK || !opt) return rc;
+    f.has_opt = true;
+    f.adam_t = s->adam_t;
+    f.m.resize((size_t)s->n_logical);
+    f.v.resize((size_t)s->n_logical);
+    rc = download_logical(s, s->am, f.m.data(), s->n_logical);
+    if (rc == CHEM_OK) rc = download_logical(s, s->av, f.v.data(), s->n_logical);
+    return rc;
+}
+
+int write_file(const std::string &path, const std::string &bytes)
+{
+    std::ofstream f(path, std::ios::binary);
+    if (!f || !f.write(bytes.data(), (std::streamsize)bytes.size())) return fail(CHEM_EINVAL, "cannot write the file");
+    return CHEM_OK;
+}
+
+}  // namespace
+
 int chem_surrogate_save(chem_surr s, const char *path)
 {
     int rc = check_surr(s);
     if (rc != CHEM_OK) return rc;
     if (!path) return fail(CHEM_EINVAL, "path is NULL");
-    std::vector<float> params((size_t)s->n_logical);
-    rc = chem_surrogate_get_params(s, params.data(), s->n_logical);
+    chem_file::SurrFile f;
+    rc = surr_to_file(s, false, f);
     if (rc != CHEM_OK) return rc;
-    std::string buf("CHEMSURR", 8);
-    auto put = [&](const void *d, size_t n) { buf.append((const char *)d, n); };
-    const int32_t ver = 1, hdr[6] = {s->K, s->nin, s->h[0], s->h[1], s->h[2], s->K};
-    const double lam = 0.1;
-    put(&ver, 4);
-    put(hdr, sizeof(hdr));
-    put(&lam, 8);
-    const int64_t nn = (int64_t)s->norm.size(), np = s->n_logical;
-    const int32_t nset = s->norm_set ? 1 : 0;
-    put(&nset, 4);
-    put(&nn, 8);
-    put(s->norm.data(), (size_t)nn * 8);
-    put(&np, 8);
-    put(params.data(), (size_t)np * 4);
-    const unsigned long long sum = fnv1a(buf.data(), buf.size());
-    put(&sum, 8);
-    std::ofstream f(path, std::ios::binary);
-    if (!f || !f.write(buf.data(), (std::streamsize)buf.size())) return fail(CHEM_EINVAL, "cannot write the file");
-    return CHEM_OK;
+    return write_file(path, chem_file::encode_surr(f));
+}
+
+int chem_surrogate_save_checkpoint(chem_surr s, const char *path, const void *user, int64_t user_bytes)
+{
+    int rc = check_surr(s);
+    if (rc != CHEM_OK) return rc;
+    if (!path) return fail(CHEM_EINVAL, "path is NULL");
+    if (user_bytes < 0 || user_bytes > chem_file::kSurrMaxUser || (user_bytes > 0 && !user))
+        return fail(CHEM_EINVAL, "user bytes: need 0 <= user_bytes <= 2^20 and a pointer when > 0");
+    chem_file::SurrFile f;
+    rc = surr_to_file(s, true, f);
+    if (rc != CHEM_OK) return rc;
+    f.user.assign((const char *)user, (size_t)user_bytes);
+    return write_file(path, chem_file::encode_surr(f));
 }
 
 int chem_surrogate_load(chem_mech mech, const char *path, chem_surr *out)
 {
     if (!mech || !path || !out) return fail(CHEM_EINVAL, "mech, path and out must not be NULL");
     *out = nullptr;
-    std::ifstream f(path, std::ios::binary);
-    if (!f) return fail(CHEM_EINVAL, "cannot open the file");
-    std::string buf((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
-    const size_t fixed = 8 + 4 + 24 + 8 + 4 + 8;
-    if (buf.size() < fixed + 8 + 8 || buf.compare(0, 8, "CHEMSURR") != 0)
-        return fail(CHEM_EINVAL, "not a surrogate file");
-    unsigned long long sum = 0;
-    std::memcpy(&sum, buf.data() + buf.size() - 8, 8);
-    if (fnv1a(buf.data(), buf.size() - 8) != sum) return fail(CHEM_EINVAL, "surrogate file checksum mismatch");
-    size_t o = 8;
-    auto get = [&](void *d, size_t n) -> bool {
-        if (o + n > buf.size() - 8) return false;
-        std::memcpy(d, buf.data() + o, n);
-        o += n;
-        return true;
-    };
-    int32_t ver = 0, hdr[6] = {0, 0, 0, 0, 0, 0}, nset = 0;
-    double lam = 0;
-    int64_t nn = 0, np = 0;
-    if (!get(&ver, 4) || ver != 1 || !get(hdr, sizeof(hdr)) || !get(&lam, 8) || !get(&nset, 4) || !get(&nn, 8))
-        return fail(CHEM_EINVAL, "bad surrogate header");
-    if (hdr[0] != mech->host.K || hdr[1] != mech->host.K + 2 || lam != 0.1)
-        return fail(CHEM_EINVAL, "surrogate does not match the mechanism");
-    chem_surr s = nullptr;
-    int rc = chem_surrogate_create(mech, hdr[2], hdr[3], hdr[4], &s);
-    if (rc != CHEM_OK) return rc;
-    std::vector<double> norm((size_t)(nn > 0 && nn < (1 << 20) ? nn : 0));
-    std::vector<float> params;
-    bool ok = nn == norm_len(s) && get(norm.data(), (size_t)nn * 8) && get(&np, 8) && np == s->n_logical;
-    if (ok) {
-        params.resize((size_t)np);
-        ok = get(params.data(), (size_t)np * 4);
-    }
-    if (!ok) {
-        chem_free_surrogate(s);
-        return fail(CHEM_EINVAL, "truncated or inconsistent surrogate file");
-    }
+    chem_file::SurrFile f;
+    std::string err;
+    if (chem_file::read_surr_file(path, f, err) != 0) return fail(CHEM_EINVAL, err);
+    if (f.K != mech->host.K) return fail(CHEM_EINVAL, "surrogate does not match the mechanism");
     int prev = 0;
     hipGetDevice(&prev);
     hipSetDevice(mech->device);
-    rc = chem_surrogate_set_params(s, params.data(), np);
-    if (rc == CHEM_OK && nset) rc = chem_surrogate_set_norm(s, norm.data(), nn);
+    chem_surr s = nullptr;
+    int rc = chem_surrogate_create(mech, f.h[0], f.h[1], f.h[2], &s);
+    if (rc == CHEM_OK) rc = chem_surrogate_set_params(s, f.params.data(), (int64_t)f.params.size());
+    if (rc == CHEM_OK && f.norm_set) rc = chem_surrogate_set_norm(s, f.norm.data(), (int64_t)f.norm.size());
+    if (rc == CHEM_OK && f.has_opt) {
+        rc = upload_logical(s, s->am, f.m.data(), (int64_t)f.m.size());
+        if (rc == CHEM_OK) rc = upload_logical(s, s->av, f.v.data(), (int64_t)f.v.size());
+        if (rc == CHEM_OK) s->adam_t = f.adam_t;
+    }
     hipSetDevice(prev);
     if (rc != CHEM_OK) {
-        chem_free_surrogate(s);
+        if (s) chem_free_surrogate(s);
         return rc;
     }
     *out = s;
+    return CHEM_OK;
+}
+
+int chem_surrogate_checkpoint_user(const char *path, void *user, int64_t capacity, int64_t *user_bytes)
+{
+    if (!path || !user_bytes || capacity < 0 || (capacity > 0 && !user))
+        return fail(CHEM_EINVAL, "path and user_bytes must not be NULL, capacity >= 0");
+    chem_file::SurrFile f;
+    std::string err;
+    if (chem_file::read_surr_file(path, f, err) != 0) return fail(CHEM_EINVAL, err);
+    if (!f.has_opt) return fail(CHEM_EINVAL, "the file holds no training state");
+    *user_bytes = (int64_t)f.user.size();
+    if ((int64_t)f.user.size() > capacity) return fail(CHEM_EINVAL, "user buffer too small");
+    if (!f.user.empty()) std::memcpy(user, f.user.data(), f.user.size());
     return CHEM_OK;
 }
 

@@ -480,6 +480,60 @@ def test_training_gain_over_untrained(torch, mechs, mech_dir, tmp_path):
     u.close()
 
 
+def test_training_resumes_exactly_from_checkpoint(torch, mechs, mech_dir, tmp_path):
+    """A training run cut in two, with a checkpoint file (parameters, Adam
+    step and moments, and the caller's sample-order generator state) written
+    and read back between the parts, ends on exactly the parameters of the
+    uncut run; resuming from a plain weights file (optimiser state lost) does
+    not."""
+    import json
+    from chemgen.mechanism import read_mechanism
+    from chemgen.surrogate_data import flame_like_states, init_params, network_dims
+    from paper_2312_13513_amd import chem
+    mpy = read_mechanism(str(mech_dir / "M9.mech"))
+    mech = mechs["M9"]
+    dt, K, h, total = 1e-6, mpy.K, (64, 64, 64), 4
+    T, p, Y = flame_like_states(mpy, 6000, 91)
+    Td, pd, Yd = _dev(torch, T), _dev(torch, p), _dev(torch, np.ascontiguousarray(Y))
+    Yn = Yd.clone()
+    mech.integrate(Td.clone(), pd, Yn, dt)
+    n = Td.shape[0]
+    init = init_params(network_dims(K, *h), 92)
+
+    def fresh():
+        s = chem.Surrogate(mech, *h)
+        s.set_params(init)
+        s.fit_norm(Td, pd, Yd, Yn, dt)
+        return s
+
+    def orders(rng, epochs):
+        return _dev(torch, np.concatenate([rng.permutation(n).astype(np.int32) for _ in range(epochs)]),
+                    torch.int32)
+
+    kw = dict(batch=512, lr0=1e-3, lr1=1e-5)
+    a = fresh()
+    la = a.train_part(Td, pd, Yd, Yn, 0, total, total, order=orders(np.random.default_rng(93), total), **kw)
+    b = fresh()
+    rng = np.random.default_rng(93)
+    lb0 = b.train_part(Td, pd, Yd, Yn, 0, 2, total, order=orders(rng, 2), **kw)
+    ck, plain = str(tmp_path / "ck.surr"), str(tmp_path / "plain.surr")
+    b.save_checkpoint(ck, json.dumps(rng.bit_generator.state).encode())
+    b.save(plain)
+    b.close()
+    c = chem.Surrogate.load(mech, ck)
+    rng2 = np.random.default_rng()
+    rng2.bit_generator.state = json.loads(chem.Surrogate.checkpoint_user(ck).decode())
+    lc = c.train_part(Td, pd, Yd, Yn, 2, 2, total, order=orders(rng2, 2), **kw)
+    _say(f"[resume] losses uncut {np.array2string(la, precision=5)} cut {lb0} + {lc}")
+    assert np.array_equal(c.get_params(), a.get_params())
+    assert np.array_equal(np.concatenate([lb0, lc]), la)
+    d = chem.Surrogate.load(mech, plain)
+    d.train_part(Td, pd, Yd, Yn, 2, 2, total, order=orders(np.random.default_rng(93), 4)[2 * n:], **kw)
+    assert not np.array_equal(d.get_params(), a.get_params())
+    for s in (a, c, d):
+        s.close()
+
+
 def test_all_fallback_is_bitwise_plain(torch, mechs, m35py):
     """With checks no cell can pass, the surrogate path is the integrator:
     results are bitwise those of chem_integrate on the same cells."""
