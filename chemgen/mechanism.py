@@ -17,7 +17,7 @@ from __future__ import annotations
 import dataclasses
 import hashlib
 import math
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -28,7 +28,38 @@ T_REF = 298.15
 #: Atomic weights (g/mol) of the synthetic elements E0..E3.
 ATOMIC_WEIGHTS = (1.008, 12.011, 15.999, 14.007)
 FORMAT_VERSION = 1
+#: Version written when a reaction is not elementary-reversible (three-body,
+#: fall-off, irreversible); version 1 files stay byte-identical.
+FORMAT_VERSION_KINETICS = 2
 GENERATOR_TAG = "chemgen-1"
+
+#: Pressure-dependence kinds of the version 2 format.
+KINDS = ("elem", "third", "lind", "troe3", "troe4")
+
+
+@dataclasses.dataclass
+class RxnKinetics:
+    """What a reaction has beyond a reversible mass-action Arrhenius rate.
+
+    ``kind``: "elem" (none), "third" (rate times the third-body concentration
+    [M]), "lind" / "troe3" / "troe4" (fall-off between the low-pressure rate
+    ``low`` = (A0, b0, Ea0) times [M] and the reaction's own Arrhenius triple
+    as the high-pressure limit; Lindemann, or Troe broadening with
+    ``troe`` = (a, T3, T1) or (a, T3, T1, T2)).  [M] = ``default_eff`` times
+    the total concentration plus ``(eff - default_eff) C_k`` for every listed
+    ``(k, eff)``.  ``reversible=False``: no reverse rate.  A0 is in cm-mol-s
+    units of one order above A; Ea0 in J/mol.
+    """
+
+    kind: str = "elem"
+    reversible: bool = True
+    default_eff: float = 1.0
+    effs: List[Tuple[int, float]] = dataclasses.field(default_factory=list)
+    low: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    troe: Tuple[float, ...] = ()
+
+    def is_plain(self) -> bool:
+        return self.kind == "elem" and self.reversible
 
 
 @dataclasses.dataclass
@@ -52,6 +83,16 @@ class Mechanism:
     seed: int = -1
     attempt: int = 0
     generator: str = GENERATOR_TAG
+    #: per reaction, None for an elementary reversible one (None: all are)
+    kinetics: Optional[List[Optional[RxnKinetics]]] = None
+
+    def kin(self, i: int) -> RxnKinetics:
+        if self.kinetics is None or self.kinetics[i] is None:
+            return RxnKinetics()
+        return self.kinetics[i]
+
+    def plain(self) -> bool:
+        return all(self.kin(i).is_plain() for i in range(self.R))
 
     @property
     def K(self) -> int:
@@ -70,7 +111,8 @@ class Mechanism:
         return 1e-3 * (self.counts @ np.asarray(self.element_weights, dtype=np.float64))
 
     def to_text(self) -> str:
-        lines = [f"CHEMMECH {FORMAT_VERSION}",
+        v2 = not self.plain()
+        lines = [f"CHEMMECH {FORMAT_VERSION_KINETICS if v2 else FORMAT_VERSION}",
                  f"generator {self.generator} seed {self.seed} attempt {self.attempt}",
                  "units A cm-mol-s Ea J/mol W g/mol",
                  f"elements {self.E}"]
@@ -85,7 +127,10 @@ class Mechanism:
         for i, (reac, prod, A, b, Ea) in enumerate(self.reactions):
             rs = " ".join(f"{k} {nu}" for k, nu in reac)
             ps = " ".join(f"{k} {nu}" for k, nu in prod)
-            lines.append(f"R{i} {len(reac)} {rs} {len(prod)} {ps} {float(A)!r} {float(b)!r} {float(Ea)!r}")
+            line = f"R{i} {len(reac)} {rs} {len(prod)} {ps} {float(A)!r} {float(b)!r} {float(Ea)!r}"
+            if v2:
+                line += " " + _kinetics_text(self.kin(i))
+            lines.append(line)
         lines.append("end")
         return "\n".join(lines) + "\n"
 
@@ -99,6 +144,24 @@ class Mechanism:
         return hashlib.sha256(self.to_text().encode()).hexdigest()
 
 
+def _kinetics_text(x: RxnKinetics) -> str:
+    """Version 2 tail of a reaction line: reversibility flag, kind, then for
+    pressure-dependent kinds the low-pressure triple (fall-off), the Troe
+    parameters, the default efficiency and the listed efficiencies."""
+    out = [str(int(x.reversible)), x.kind]
+    if x.kind in ("lind", "troe3", "troe4"):
+        out += [repr(float(v)) for v in x.low]
+    if x.kind == "troe3":
+        out += [repr(float(v)) for v in x.troe[:3]]
+    if x.kind == "troe4":
+        out += [repr(float(v)) for v in x.troe[:4]]
+    if x.kind != "elem":
+        out += [repr(float(x.default_eff)), str(len(x.effs))]
+        for k, e in x.effs:
+            out += [str(int(k)), repr(float(e))]
+    return " ".join(out)
+
+
 def read_mechanism(path: str) -> Mechanism:
     """Parse a ``.mech`` file back into plain data (used by generators and tests)."""
     with open(path) as fh:
@@ -110,7 +173,9 @@ def read_mechanism(path: str) -> Mechanism:
         pos += 1
         return tok[pos - 1]
 
-    assert nxt() == "CHEMMECH" and int(nxt()) == FORMAT_VERSION
+    assert nxt() == "CHEMMECH"
+    version = int(nxt())
+    assert version in (FORMAT_VERSION, FORMAT_VERSION_KINETICS)
     assert nxt() == "generator"
     gen = nxt()
     assert nxt() == "seed"
@@ -137,7 +202,7 @@ def read_mechanism(path: str) -> Mechanism:
             nasa[k, j] = float(nxt())
     assert nxt() == "reactions"
     R = int(nxt())
-    reactions = []
+    reactions, kinetics = [], []
     for _ in range(R):
         nxt()
         nr = int(nxt())
@@ -146,8 +211,21 @@ def read_mechanism(path: str) -> Mechanism:
         prod = [(int(nxt()), int(nxt())) for _ in range(np_)]
         A, b, Ea = float(nxt()), float(nxt()), float(nxt())
         reactions.append((reac, prod, A, b, Ea))
+        x = None
+        if version == FORMAT_VERSION_KINETICS:
+            x = RxnKinetics(reversible=bool(int(nxt())), kind=nxt())
+            assert x.kind in KINDS
+            if x.kind in ("lind", "troe3", "troe4"):
+                x.low = (float(nxt()), float(nxt()), float(nxt()))
+            if x.kind in ("troe3", "troe4"):
+                x.troe = tuple(float(nxt()) for _ in range(3 if x.kind == "troe3" else 4))
+            if x.kind != "elem":
+                x.default_eff = float(nxt())
+                x.effs = [(int(nxt()), float(nxt())) for _ in range(int(nxt()))]
+        kinetics.append(x)
     assert nxt() == "end"
-    return Mechanism(en, ew, sn, counts, nasa, reactions, seed, attempt, gen)
+    return Mechanism(en, ew, sn, counts, nasa, reactions, seed, attempt, gen,
+                     kinetics if any(x is not None for x in kinetics) else None)
 
 
 # ----------------------------------------------------------------------------
@@ -307,17 +385,118 @@ def make_mechanism(seed: int, K: int, R: int, E: int, *,
     raise RuntimeError(f"no species set with >= {R} candidate reactions in {max_attempts} attempts")
 
 
-#: The two synthetic mechanisms of the workloads: 9 species / 21 reactions /
-#: 3 elements (stand-in for the H2 case) and 35 / 200 / 4 (larger than the CH4 case).
+def _second_range(rng: np.random.Generator, nasa_row: np.ndarray, scale: float = 0.05) -> np.ndarray:
+    """Give a species a high-temperature NASA-7 range of its own.
+
+    The high range is the low one plus a cp/R correction
+    e1 (T - Tmid) + e2 (T - Tmid)^2 that vanishes at Tmid, with the enthalpy
+    and entropy constants chosen so that cp, H and S are continuous at Tmid
+    (as fitted NASA-7 data are); cp/R stays within ``scale`` times its own
+    range over [Tmid, Thi]."""
+    out = nasa_row.copy()
+    tm, th = nasa_row[1], nasa_row[2]
+    span = th - tm
+    e1 = rng.uniform(-1.0, 1.0) * scale * 4.0 / span
+    e2 = rng.uniform(-1.0, 1.0) * scale * 4.0 / span ** 2
+    d = np.zeros(7)
+    d[0] = -e1 * tm + e2 * tm * tm
+    d[1] = e1 - 2.0 * e2 * tm
+    d[2] = e2
+    d[5] = -(d[0] * tm + d[1] * tm ** 2 / 2.0 + d[2] * tm ** 3 / 3.0)
+    d[6] = -(d[0] * math.log(tm) + d[1] * tm + d[2] * tm ** 2 / 2.0)
+    out[10:17] = nasa_row[3:10] + d
+    return out
+
+
+def make_real_like_mechanism(seed: int, K: int, R: int, E: int, *, n_third: int, n_lind: int,
+                             n_troe: int, n_dup: int, n_irrev: int) -> Mechanism:
+    """A seeded mechanism with the features of real combustion mechanisms.
+
+    Starts from ``make_mechanism`` (R - n_dup elementary reactions) and then:
+    every species gets a high-temperature NASA range of its own
+    (``_second_range``); n_third recombination / dissociation reactions (one
+    species on one side, two on the other) become three-body reactions and
+    n_lind + n_troe more become fall-off reactions (Lindemann, then Troe with
+    three and four parameters alternately), each with a few listed collision
+    efficiencies (one of them 0) and, for one reaction, a single bath species
+    (default efficiency 0); n_dup reactions get a duplicate with their own
+    Arrhenius triple; n_irrev elementary reactions become irreversible.
+    Three-body and low-pressure pre-exponentials are drawn 10^4..10^6.5 times
+    the bimolecular one, so that at 1 atm and flame temperatures the fall-off
+    reactions sit inside their fall-off range (reduced pressure about 0.1-100).
+    """
+    base = make_mechanism(seed, K, R - n_dup, E)
+    rng = np.random.default_rng(seed * 7919 + 17)
+    nasa = np.stack([_second_range(rng, base.nasa[k]) for k in range(K)])
+    reactions = list(base.reactions)
+    kin: List[Optional[RxnKinetics]] = [None] * len(reactions)
+    uni = [i for i, (r, p, *_) in enumerate(reactions)
+           if sum(nu for _, nu in r) + sum(nu for _, nu in p) == 3]
+    n_pd = n_third + n_lind + n_troe
+    if len(uni) < n_pd:
+        raise ValueError(f"only {len(uni)} reactions with one and two molecules on their sides")
+    pick = [uni[j] for j in rng.choice(len(uni), size=n_pd, replace=False)]
+    for j, i in enumerate(pick):
+        reac, prod, A, b, Ea = reactions[i]
+        neff = int(rng.integers(2, 4))
+        ks = rng.choice(K, size=neff, replace=False)
+        effs = [(int(k), 0.0 if t == 0 else float(np.round(rng.uniform(0.3, 12.0), 2)))
+                for t, k in enumerate(sorted(ks))]
+        x = RxnKinetics(effs=effs)
+        if j == 0:
+            x.default_eff = 0.0
+            x.effs = [(int(ks[0]), 1.0)]
+        if j < n_third:
+            x.kind = "third"
+            reactions[i] = (reac, prod, A * 10.0 ** rng.uniform(4.0, 6.5), b, Ea)
+        else:
+            x.low = (A * 10.0 ** rng.uniform(4.0, 6.5), float(rng.uniform(-2.0, 0.0)),
+                     float(rng.uniform(0.0, 0.5)) * Ea)
+            if j < n_third + n_lind:
+                x.kind = "lind"
+            else:
+                t = j - n_third - n_lind
+                x.kind = "troe3" if t % 2 == 0 else "troe4"
+                troe = (float(np.round(rng.uniform(0.3, 0.9), 3)), float(np.round(rng.uniform(50.0, 400.0), 1)),
+                        float(np.round(rng.uniform(800.0, 3000.0), 1)))
+                if x.kind == "troe4":
+                    troe += (float(np.round(rng.uniform(3000.0, 8000.0), 1)),)
+                x.troe = troe
+        kin[i] = x
+    rest = [i for i in range(len(reactions)) if kin[i] is None]
+    for i in rng.choice(rest, size=n_irrev, replace=False):
+        kin[int(i)] = RxnKinetics(reversible=False)
+    for i in rng.choice(len(reactions), size=n_dup, replace=False):
+        reac, prod, A, b, Ea = reactions[int(i)]
+        reactions.append((reac, prod, float(A * 10.0 ** rng.uniform(-1.5, 0.5)), float(rng.uniform(-1.0, 1.0)),
+                          float(rng.uniform(0.0, 200e3))))
+        src = kin[int(i)]
+        kin.append(dataclasses.replace(src, effs=list(src.effs)) if src is not None else None)
+    return Mechanism(base.element_names, base.element_weights, base.species_names, base.counts, nasa,
+                     reactions, seed, base.attempt, "chemgen-2", kin)
+
+
+#: The synthetic mechanisms of the workloads: 9 species / 21 reactions /
+#: 3 elements (stand-in for the H2 case) and 35 / 200 / 4 (larger than the CH4
+#: case), elementary reversible reactions with one NASA range; and two with the
+#: features of real mechanisms at the sizes of the paper's H2 and CH4 cases
+#: (9 species / 12 reactions, 20 species / 85 reactions): three-body and
+#: fall-off reactions, duplicates, irreversible reactions, two NASA ranges.
 MECH_SPECS = {"M9": dict(seed=1, K=9, R=21, E=3), "M35": dict(seed=2, K=35, R=200, E=4)}
+REAL_LIKE_SPECS = {
+    "H2R": dict(seed=3, K=9, R=12, E=3, n_third=2, n_lind=1, n_troe=2, n_dup=1, n_irrev=1),
+    "CH4R": dict(seed=4, K=20, R=85, E=4, n_third=8, n_lind=3, n_troe=4, n_dup=4, n_irrev=3),
+}
 
 
 def standard_mechanism(name: str) -> Mechanism:
+    if name in REAL_LIKE_SPECS:
+        return make_real_like_mechanism(**REAL_LIKE_SPECS[name])
     return make_mechanism(**MECH_SPECS[name])
 
 
 def custom_mechanism(counts, nasa_coeffs, reactions, element_weights=None,
-                     species_names=None) -> Mechanism:
+                     species_names=None, kinetics=None) -> Mechanism:
     """Build a mechanism from explicit data (test cases such as A <-> B isomers).
 
     ``nasa_coeffs[k]`` is a 7-vector used for both temperature ranges.
@@ -330,7 +509,7 @@ def custom_mechanism(counts, nasa_coeffs, reactions, element_weights=None,
     names = species_names or [f"S{k}" for k in range(K)]
     return Mechanism([f"E{e}" for e in range(E)], ew, names, counts, nasa,
                      [(list(r), list(p), float(A), float(b), float(Ea)) for r, p, A, b, Ea in reactions],
-                     seed=-1, attempt=0, generator="custom")
+                     seed=-1, attempt=0, generator="custom", kinetics=kinetics)
 
 
 def nasa_for(cp_over_R: Sequence[float], dhf: float, s0: float) -> List[float]:

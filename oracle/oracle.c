@@ -37,12 +37,20 @@
 #define OM_RU 8.31446261815324 /* J/(mol K), CODATA 2018 exact */
 #define OM_PSTD 101325.0       /* standard-state pressure, Pa (1 atm) */
 
+/* Pressure dependence of a reaction (file format version 2). */
+enum { OM_ELEM = 0, OM_THIRD = 1, OM_LIND = 2, OM_TROE3 = 3, OM_TROE4 = 4 };
+
 typedef struct {
     int nr, np;          /* number of reactant / product terms (1..2) */
     int rsp[2], rnu[2];  /* reactant species and integer coefficients */
     int psp[2], pnu[2];
     int dnu;             /* sum of product minus reactant coefficients */
     double A_si, b, Ea;  /* SI pre-exponential, temperature exponent, J/mol */
+    int kind;            /* OM_ELEM .. OM_TROE4 */
+    int rev;             /* 1: reverse rate from K_c; 0: irreversible */
+    double *eff;         /* third-body efficiency of every species (NULL for OM_ELEM) */
+    double A0_si, b0, Ea0;        /* low-pressure limit of a fall-off reaction */
+    double ta, tT3, tT1, tT2;     /* Troe parameters (tT2 used by OM_TROE4 only) */
 } om_rxn;
 
 typedef struct {
@@ -64,6 +72,50 @@ static int expect_word(FILE *fp, const char *w)
     return strcmp(buf, w) == 0 ? 0 : -1;
 }
 
+void om_free(void *h);
+
+/* Version 2 tail of a reaction line: reversibility flag, kind, then for a
+ * fall-off reaction the low-pressure Arrhenius triple (A0 in cm-mol-s units
+ * with the third body counted as a molecule), the Troe parameters a, T3, T1
+ * (and T2 for troe4: the temperatures usually written with three, one and
+ * two asterisks), and for every pressure-dependent kind the default
+ * efficiency and the listed (species, efficiency) pairs. */
+static int read_kinetics(FILE *fp, int K, om_rxn *r)
+{
+    char kind[16];
+    int n = 0;
+    if (fscanf(fp, "%d %15s", &r->rev, kind) != 2 || (r->rev != 0 && r->rev != 1)) return -1;
+    if (!strcmp(kind, "elem")) r->kind = OM_ELEM;
+    else if (!strcmp(kind, "third")) r->kind = OM_THIRD;
+    else if (!strcmp(kind, "lind")) r->kind = OM_LIND;
+    else if (!strcmp(kind, "troe3")) r->kind = OM_TROE3;
+    else if (!strcmp(kind, "troe4")) r->kind = OM_TROE4;
+    else return -1;
+    if (r->kind == OM_ELEM) return 0;
+    if (r->kind >= OM_LIND) {
+        double A0;
+        int order = 0;
+        if (fscanf(fp, "%lf %lf %lf", &A0, &r->b0, &r->Ea0) != 3) return -1;
+        for (int t = 0; t < r->nr; t++) order += r->rnu[t];
+        r->A0_si = A0 * pow(1e-6, order);
+    }
+    if (r->kind >= OM_TROE3 && fscanf(fp, "%lf %lf %lf", &r->ta, &r->tT3, &r->tT1) != 3) return -1;
+    if (r->kind >= OM_TROE3 && !(r->tT3 > 0.0 && r->tT1 > 0.0)) return -1;
+    if (r->kind == OM_TROE4 && fscanf(fp, "%lf", &r->tT2) != 1) return -1;
+    double def = 0.0;
+    if (fscanf(fp, "%lf %d", &def, &n) != 2 || n < 0 || n > K || !(def >= 0.0)) return -1;
+    r->eff = malloc((size_t)K * sizeof(double));
+    if (!r->eff) return -1;
+    for (int k = 0; k < K; k++) r->eff[k] = def;
+    for (int j = 0; j < n; j++) {
+        int k = -1;
+        double e = 0.0;
+        if (fscanf(fp, "%d %lf", &k, &e) != 2 || k < 0 || k >= K || !(e >= 0.0)) return -1;
+        r->eff[k] = e;
+    }
+    return 0;
+}
+
 void *om_load(const char *path)
 {
     FILE *fp = fopen(path, "r");
@@ -72,7 +124,7 @@ void *om_load(const char *path)
     char buf[128];
     int ver, seed, attempt;
     double aw[4] = {0, 0, 0, 0};
-    if (expect_word(fp, "CHEMMECH") || fscanf(fp, "%d", &ver) != 1 || ver != 1) goto fail;
+    if (expect_word(fp, "CHEMMECH") || fscanf(fp, "%d", &ver) != 1 || (ver != 1 && ver != 2)) goto fail;
     if (expect_word(fp, "generator") || fscanf(fp, "%127s", buf) != 1) goto fail;
     if (expect_word(fp, "seed") || fscanf(fp, "%d", &seed) != 1) goto fail;
     if (expect_word(fp, "attempt") || fscanf(fp, "%d", &attempt) != 1) goto fail;
@@ -87,15 +139,16 @@ void *om_load(const char *path)
         if (fscanf(fp, "%127s", buf) != 1) goto fail;
         double w = 0.0;
         for (int e = 0; e < m->E; e++) {
-            if (fscanf(fp, "%d", &m->counts[k][e]) != 1) goto fail;
+            if (fscanf(fp, "%d", &m->counts[k][e]) != 1 || m->counts[k][e] < 0) goto fail;
             w += m->counts[k][e] * aw[e];
         }
         m->W[k] = 1e-3 * w;
         for (int j = 0; j < 17; j++)
             if (fscanf(fp, "%lf", &m->nasa[k][j]) != 1) goto fail;
     }
-    if (expect_word(fp, "reactions") || fscanf(fp, "%d", &m->R) != 1 || m->R < 0) goto fail;
+    if (expect_word(fp, "reactions") || fscanf(fp, "%d", &m->R) != 1 || m->R < 0 || m->R > 1000000) goto fail;
     m->rxn = calloc(m->R > 0 ? m->R : 1, sizeof(om_rxn));
+    if (!m->rxn) goto fail;
     for (int i = 0; i < m->R; i++) {
         om_rxn *r = &m->rxn[i];
         double A;
@@ -103,27 +156,31 @@ void *om_load(const char *path)
         if (fscanf(fp, "%127s %d", buf, &r->nr) != 2 || r->nr < 1 || r->nr > 2) goto fail;
         for (int t = 0; t < r->nr; t++) {
             if (fscanf(fp, "%d %d", &r->rsp[t], &r->rnu[t]) != 2) goto fail;
-            if (r->rsp[t] < 0 || r->rsp[t] >= m->K) goto fail;
+            if (r->rsp[t] < 0 || r->rsp[t] >= m->K || r->rnu[t] < 1 || r->rnu[t] > 2) goto fail;
             order += r->rnu[t];
         }
         if (fscanf(fp, "%d", &r->np) != 1 || r->np < 1 || r->np > 2) goto fail;
         for (int t = 0; t < r->np; t++) {
             if (fscanf(fp, "%d %d", &r->psp[t], &r->pnu[t]) != 2) goto fail;
-            if (r->psp[t] < 0 || r->psp[t] >= m->K) goto fail;
+            if (r->psp[t] < 0 || r->psp[t] >= m->K || r->pnu[t] < 1 || r->pnu[t] > 2) goto fail;
             sum_p += r->pnu[t];
         }
+        if (order > 2 || sum_p > 2) goto fail; /* at most two molecules on a side */
         if (fscanf(fp, "%lf %lf %lf", &A, &r->b, &r->Ea) != 3) goto fail;
         r->dnu = sum_p - order;
-        /* A is given in cm-mol-s units: (cm^3/mol)^(order-1)/s -> SI */
-        r->A_si = A * pow(1e-6, order - 1);
+        r->kind = OM_ELEM;
+        r->rev = 1;
+        if (ver == 2 && read_kinetics(fp, m->K, r)) goto fail;
+        /* A is given in cm-mol-s units: (cm^3/mol)^(n-1)/s with n the number of
+         * colliding molecules, the third body included -> SI */
+        r->A_si = A * pow(1e-6, order - 1 + (r->kind == OM_THIRD));
     }
     if (expect_word(fp, "end")) goto fail;
     fclose(fp);
     return m;
 fail:
     fclose(fp);
-    free(m->rxn);
-    free(m);
+    om_free(m);
     return NULL;
 }
 
@@ -131,6 +188,8 @@ void om_free(void *h)
 {
     om_mech *m = h;
     if (!m) return;
+    if (m->rxn)
+        for (int i = 0; i < m->R; i++) free(m->rxn[i].eff);
     free(m->rxn);
     free(m);
 }
@@ -165,6 +224,31 @@ int om_thermo(void *h, double T, double *cp_R, double *h_RT, double *s_R)
     return 0;
 }
 
+#define RB_NAME rhs_real
+#define RB_KF kf_real
+#define RB_T double
+#define RB_EXP exp
+#define RB_LOG log
+#define RB_POW pow
+#define RB_RE(x) (x)
+#include "rhs_body.h"
+#undef RB_NAME
+#undef RB_KF
+#undef RB_T
+#undef RB_EXP
+#undef RB_LOG
+#undef RB_POW
+#undef RB_RE
+
+#define RB_NAME rhs_cplx
+#define RB_KF kf_cplx
+#define RB_T double complex
+#define RB_EXP cexp
+#define RB_LOG clog
+#define RB_POW cpow
+#define RB_RE(x) creal(x)
+#include "rhs_body.h"
+
 /* Rate constants, rates of progress and net production rates at (T, p, Y). */
 int om_rates(void *h, double T, double p, const double *Y, double *kf, double *kr, double *q,
              double *wdot)
@@ -181,12 +265,12 @@ int om_rates(void *h, double T, double p, const double *Y, double *kf, double *k
     }
     for (int i = 0; i < m->R; i++) {
         const om_rxn *r = &m->rxn[i];
-        kf[i] = r->A_si * pow(T, r->b) * exp(-r->Ea / (OM_RU * T));
+        kf[i] = kf_real(r, m->K, T, C);
         double sum_nu_g = 0.0;
         for (int t = 0; t < r->np; t++) sum_nu_g += r->pnu[t] * (h_RT[r->psp[t]] - s_R[r->psp[t]]);
         for (int t = 0; t < r->nr; t++) sum_nu_g -= r->rnu[t] * (h_RT[r->rsp[t]] - s_R[r->rsp[t]]);
         double Kc = exp(-sum_nu_g) * pow(OM_PSTD / (OM_RU * T), r->dnu);
-        kr[i] = kf[i] / Kc;
+        kr[i] = r->rev ? kf[i] / Kc : 0.0;
         double fwd = kf[i], rev = kr[i];
         for (int t = 0; t < r->nr; t++)
             for (int e = 0; e < r->rnu[t]; e++) fwd *= C[r->rsp[t]];
@@ -198,28 +282,6 @@ int om_rates(void *h, double T, double p, const double *Y, double *kf, double *k
     }
     return 0;
 }
-
-#define RB_NAME rhs_real
-#define RB_T double
-#define RB_EXP exp
-#define RB_LOG log
-#define RB_POW pow
-#define RB_RE(x) (x)
-#include "rhs_body.h"
-#undef RB_NAME
-#undef RB_T
-#undef RB_EXP
-#undef RB_LOG
-#undef RB_POW
-#undef RB_RE
-
-#define RB_NAME rhs_cplx
-#define RB_T double complex
-#define RB_EXP cexp
-#define RB_LOG clog
-#define RB_POW cpow
-#define RB_RE(x) creal(x)
-#include "rhs_body.h"
 
 int om_rhs(void *h, double p, const double *y, double *f)
 {
@@ -241,6 +303,61 @@ int om_jac_cs(void *h, double p, const double *y, double *J)
         for (int i = 0; i < N; i++) J[i * N + j] = cimag(fc[i]) / s;
     }
     return 0;
+}
+
+/* Forward rate constant with its partial derivatives: d(ln k_f)/dT at fixed
+ * concentrations and d k_f / d[M] at fixed T (0 for an elementary
+ * reaction).  For the fall-off forms, with x = log10 Pr, u = x + c,
+ * D = n - 0.14 u, f = u / D and Lc = log10 Fcent:
+ *   d ln k_f / dT = d ln k_inf/dT + (d ln Pr/dT) / (1 + Pr) + d ln F/dT,
+ *   d ln Pr / dT  = d ln k_0/dT - d ln k_inf/dT,
+ *   d log10 F / dx  = -Lc 2 f / (1 + f^2)^2 n / D^2,
+ *   d log10 F / dLc = 1 / (1 + f^2) - Lc 2 f / (1 + f^2)^2 (1.27 u - 0.67 n) / D^2,
+ *   d ln F / dT = (d log10 F/dx) d ln Pr/dT + (d log10 F/dLc) (dFcent/dT) / Fcent,
+ *   d k_f / d[M] = k_0 F / (1 + Pr) (1 / (1 + Pr) + d log10 F / dx). */
+static double kf_parts(const om_rxn *r, int K, double T, const double *C, double *dlnkf, double *dkfdM)
+{
+    const double ln10 = log(10.0), tiny = 1e-300;
+    const double k = kf_real(r, K, T, C);
+    const double dlnk_inf = r->b / T + r->Ea / (OM_RU * T * T);
+    *dlnkf = dlnk_inf;
+    *dkfdM = 0.0;
+    if (r->kind == OM_ELEM) return k;
+    const double kinf = r->A_si * pow(T, r->b) * exp(-r->Ea / (OM_RU * T));
+    if (r->kind == OM_THIRD) {
+        *dkfdM = kinf;
+        return k;
+    }
+    double M = 0.0;
+    for (int l = 0; l < K; l++) M += r->eff[l] * C[l];
+    const double k0 = r->A0_si * pow(T, r->b0) * exp(-r->Ea0 / (OM_RU * T));
+    const double Pr = k0 * M / kinf;
+    const double dlnPr = r->b0 / T + r->Ea0 / (OM_RU * T * T) - dlnk_inf;
+    double F = 1.0, dx = 0.0, dlnF = 0.0;
+    if (r->kind == OM_TROE3 || r->kind == OM_TROE4) {
+        double Fc = (1.0 - r->ta) * exp(-T / r->tT3) + r->ta * exp(-T / r->tT1);
+        double dFc = -(1.0 - r->ta) / r->tT3 * exp(-T / r->tT3) - r->ta / r->tT1 * exp(-T / r->tT1);
+        if (r->kind == OM_TROE4) {
+            Fc += exp(-r->tT2 / T);
+            dFc += r->tT2 / (T * T) * exp(-r->tT2 / T);
+        }
+        if (Fc < tiny) {
+            Fc = tiny;
+            dFc = 0.0;
+        }
+        const double Lc = log10(Fc);
+        const double x = log10(Pr < tiny ? tiny : Pr);
+        const double c = -0.4 - 0.67 * Lc, n = 0.75 - 1.27 * Lc;
+        const double u = x + c, D = n - 0.14 * u, f = u / D;
+        const double s = 1.0 + f * f;
+        F = pow(10.0, Lc / s);
+        dx = Pr < tiny ? 0.0 : -Lc * 2.0 * f / (s * s) * n / (D * D);
+        const double dLc = 1.0 / s - Lc * 2.0 * f / (s * s) * (1.27 * u - 0.67 * n) / (D * D);
+        dlnF = ln10 * (dx * dlnPr / ln10 + dLc * dFc / (Fc * ln10));
+    }
+    *dlnkf = dlnk_inf + dlnPr / (1.0 + Pr) + dlnF;
+    *dkfdM = k0 * F / (1.0 + Pr) * (1.0 / (1.0 + Pr) + dx);
+    return k;
 }
 
 /* Analytic Jacobian of the reactor right-hand side, row-major N x N.
@@ -272,7 +389,8 @@ int om_jac(void *h, double p, const double *y, double *J)
     }
     for (int i = 0; i < m->R; i++) {
         const om_rxn *r = &m->rxn[i];
-        double kf = r->A_si * pow(T, r->b) * exp(-r->Ea / (OM_RU * T));
+        double dlnkf, dkfdM;
+        double kf = kf_parts(r, K, T, C, &dlnkf, &dkfdM);
         double sum_nu_g = 0.0, sum_nu_h = 0.0;
         for (int t = 0; t < r->np; t++) {
             sum_nu_g += r->pnu[t] * (h_RT[r->psp[t]] - s_R[r->psp[t]]);
@@ -283,8 +401,7 @@ int om_jac(void *h, double p, const double *y, double *J)
             sum_nu_h -= r->rnu[t] * h_RT[r->rsp[t]];
         }
         double Kc = exp(-sum_nu_g) * pow(OM_PSTD / (OM_RU * T), r->dnu);
-        double kr = kf / Kc;
-        double dlnkf = r->b / T + r->Ea / (OM_RU * T * T);
+        double kr = r->rev ? kf / Kc : 0.0;
         double dlnKc = sum_nu_h / T - r->dnu / T;
         double dlnkr = dlnkf - dlnKc;
         /* forward and reverse concentration products and their partials */
@@ -311,6 +428,11 @@ int om_jac(void *h, double p, const double *y, double *J)
                 if (u != t)
                     for (int e = 0; e < r->pnu[u]; e++) d *= C[r->psp[u]];
             dqdC[r->psp[t]] -= kr * d;
+        }
+        /* through the third-body concentration: dq/dC_l += dkf/d[M] eff_l (Pf - Pr / Kc) */
+        if (r->kind != OM_ELEM) {
+            double g = dkfdM * (Pf - (r->rev ? Pr / Kc : 0.0));
+            for (int l = 0; l < K; l++) dqdC[l] += g * r->eff[l];
         }
         int sp[4], nu[4], ns = 0;
         for (int t = 0; t < r->nr; t++) { sp[ns] = r->rsp[t]; nu[ns] = -r->rnu[t]; ns++; }
