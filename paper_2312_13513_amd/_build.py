@@ -40,15 +40,17 @@ def sources():
 
 def specialised_mechanisms(outdir: str) -> dict:
     """Mechanisms that get compiled-in specialised kernels: the standard
-    9-species synthetic mechanism (one thread per cell holds its state), plus
-    any .mech files listed in CHEM_EXTRA_MECHS (colon-separated paths)."""
+    9-species synthetic mechanism and the 9-species stand-in with real
+    mechanism features (one thread per cell holds its state), plus any .mech
+    files listed in CHEM_EXTRA_MECHS (colon-separated paths)."""
     sys.path.insert(0, os.path.dirname(HERE))
     from chemgen.mechanism import standard_mechanism
     os.makedirs(outdir, exist_ok=True)
     paths = {}
-    p = os.path.join(outdir, "M9.mech")
-    standard_mechanism("M9").write(p)
-    paths["M9"] = p
+    for name in ("M9", "H2R"):
+        p = os.path.join(outdir, f"{name}.mech")
+        standard_mechanism(name).write(p)
+        paths[name] = p
     for i, extra in enumerate(filter(None, os.environ.get("CHEM_EXTRA_MECHS", "").split(":"))):
         paths[f"X{i}"] = extra
     return paths

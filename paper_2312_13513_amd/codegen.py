@@ -9,7 +9,8 @@ picks the specialised kernel when the loaded file's FNV-1a hash matches.
 
 The arithmetic is the same as the table-driven kernels (NASA-7 with
 pre-divided coefficients, ln k_f = ln A + b ln T - Ea/(R T), k_r = k_f / K_c
-via exp(ln k_f + dG/RT - dnu ln(p0/(R T)))).
+via exp(ln k_f + dG/RT - dnu ln(p0/(R T))), third-body and fall-off factors
+from kinetics.h with the efficiencies and low-pressure records as constants).
 """
 from __future__ import annotations
 
@@ -38,7 +39,9 @@ def _read(path: str):
         pos[0] += 1
         return tok[pos[0] - 1]
 
-    assert nxt() == "CHEMMECH" and nxt() == "1"
+    assert nxt() == "CHEMMECH"
+    version = nxt()
+    assert version in ("1", "2")
     for _ in range(6):
         nxt()
     assert nxt() == "units"
@@ -59,7 +62,7 @@ def _read(path: str):
         nasa.append([float(nxt()) for _ in range(17)])
     assert nxt() == "reactions"
     R = int(nxt())
-    rx = []
+    rx, kins = [], []
     for _ in range(R):
         nxt()
         nr = int(nxt())
@@ -68,9 +71,21 @@ def _read(path: str):
         prod = [(int(nxt()), int(nxt())) for _ in range(npr)]
         A, b, Ea = float(nxt()), float(nxt()), float(nxt())
         rx.append((reac, prod, A, b, Ea))
+        kin = {"rev": True, "kind": "elem"}
+        if version == "2":
+            kin["rev"] = nxt() == "1"
+            kin["kind"] = nxt()
+            if kin["kind"] in ("lind", "troe3", "troe4"):
+                kin["low"] = (float(nxt()), float(nxt()), float(nxt()))
+            if kin["kind"] in ("troe3", "troe4"):
+                kin["troe"] = [float(nxt()) for _ in range(3 if kin["kind"] == "troe3" else 4)]
+            if kin["kind"] != "elem":
+                kin["def"] = float(nxt())
+                kin["effs"] = [(int(nxt()), float(nxt())) for _ in range(int(nxt()))]
+        kins.append(kin)
     assert nxt() == "end"
     W = [1e-3 * sum(c * w for c, w in zip(cnt, aw)) for cnt in counts]
-    return K, R, W, nasa, rx
+    return K, R, W, nasa, rx, kins
 
 
 def _lit(x: float) -> str:
@@ -126,11 +141,42 @@ def _dprod(slots, s) -> str:
     return f"{cnt}.0 * {body}" if cnt > 1 else body
 
 
+def _pdep_lines(kin, K: int, order: int, i: int, deriv: bool) -> List[str]:
+    """Third-body concentration M and the pressure-dependence factor pd of a
+    pressure-dependent reaction (kinetics.h), efficiencies and the
+    low-pressure record as constants."""
+    eff = [kin["def"]] * K
+    for k, v in kin["effs"]:
+        eff[k] = v
+    terms = [(f"C{k}" if v == 1.0 else f"{_lit(v)} * C{k}") for k, v in enumerate(eff) if v != 0.0]
+    L = [f"const double M = {' + '.join(terms) if terms else '0.0'};"]
+    if kin["kind"] == "third":
+        L.append("const PdepRate pd{M, 0.0, 1.0};")
+        return L
+    A0, b0, Ea0 = kin["low"]
+    troe = kin.get("troe", [0.0, 1.0, 1.0])
+    head = [math.log(A0) + order * math.log(1e-6), b0, Ea0 / RU, troe[0],
+            1.0 / troe[1] if kin["kind"] != "lind" else 0.0, 1.0 / troe[2] if kin["kind"] != "lind" else 0.0,
+            troe[3] if kin["kind"] == "troe4" else 0.0, 1.0 if kin["kind"] == "troe4" else 0.0]
+    L.append(f"const double a{i}[{len(head)}] = {{{', '.join(_lit(v) for v in head)}}};")
+    kind = "kRxnLind" if kin["kind"] == "lind" else "kRxnTroe"
+    L.append(f"const PdepRate pd = pdep_rate<{'true' if deriv else 'false'}>({kind}, a{i}, M, T, lnT, invT, lnkf, "
+             f"{'dlnk' if deriv else '0.0'});")
+    return L
+
+
+def _eff_row(kin, K: int) -> List[float]:
+    eff = [kin["def"]] * K
+    for k, v in kin["effs"]:
+        eff[k] = v
+    return eff
+
+
 def generate(path: str, tag: str) -> Tuple[str, int, int]:
     """Return (source, K, hash) of the specialised functor and kernels for a file."""
     data = open(path, "rb").read()
     hsh = fnv1a64(data)
-    K, R, W, nasa, rx = _read(path)
+    K, R, W, nasa, rx, kins = _read(path)
     N = K + 1
     out = [f"// Generated from {os.path.basename(path)} (FNV-1a {hsh:016x}); do not edit.",
            '#include "bdf_driver.h"', "", "namespace chem {", "namespace {", "",
@@ -154,14 +200,21 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
         out.append(f"        double w{k} = 0.0;")
     for i, (reac, prod, A, b, Ea) in enumerate(rx):
         sr, sp, net = _rxn_terms(reac, prod)
+        kin = kins[i]
+        pdep = kin["kind"] != "elem"
         order = len(sr)
-        lnA = math.log(A) + (order - 1) * math.log(1e-6)
+        lnA = math.log(A) + (order - 1 + (kin["kind"] == "third")) * math.log(1e-6)
         dnu = len(sp) - len(sr)
         dg = " + ".join(f"g{k}" for k in sp) + " - " + " - ".join(f"g{k}" for k in sr)
         out.append(f"        {{   // reaction {i}")
         out.append(f"            const double lnkf = {_lit(lnA)} + {_lit(b)} * lnT - {_lit(Ea / RU)} * invT;")
         lnkr = f"lnkf + ({dg})" + (f" - {float(dnu)!r} * ln_c0" if dnu else "")
-        out.append(f"            const double q = exp(lnkf) * {_prod_expr(sr)} - exp({lnkr}) * {_prod_expr(sp)};")
+        q0 = f"exp(lnkf) * {_prod_expr(sr)}" + (f" - exp({lnkr}) * {_prod_expr(sp)}" if kin["rev"] else "")
+        if pdep:
+            out += ["            " + ln for ln in _pdep_lines(kin, K, order, i, False)]
+            out.append(f"            const double q = ({q0}) * pd.mult;")
+        else:
+            out.append(f"            const double q = {q0};")
         for k, nu in sorted(net.items()):
             if nu:
                 out.append(f"            w{k} += {float(nu)!r} * q;")
@@ -196,11 +249,14 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
         out.append(f"        const double C{k} = rho * y[{k}] * {_lit(1.0 / W[k])};")
     out.append(f"        const double ln_c0 = {_lit(ln_c0_const)} - lnT;")
     touched = set()
-    for reac, prod, *_ in rx:
+    for i, (reac, prod, *_ ) in enumerate(rx):
         sr, sp, net = _rxn_terms(reac, prod)
+        cols = set(sr) | set(sp)
+        if kins[i]["kind"] != "elem":
+            cols |= {l for l, v in enumerate(_eff_row(kins[i], K)) if v != 0.0}
         for k, nu in net.items():
             if nu:
-                for l in set(sr) | set(sp):
+                for l in cols:
                     touched.add((k, l))
     for k in range(K):
         out.append(f"        double v{k} = 0.0;")
@@ -212,8 +268,10 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
                 out.append(f"        J[{k * N + l}] = 0.0;")
     for i, (reac, prod, A, b, Ea) in enumerate(rx):
         sr, sp, net = _rxn_terms(reac, prod)
+        kin = kins[i]
+        pdep, rev_ = kin["kind"] != "elem", kin["rev"]
         order = len(sr)
-        lnA = math.log(A) + (order - 1) * math.log(1e-6)
+        lnA = math.log(A) + (order - 1 + (kin["kind"] == "third")) * math.log(1e-6)
         dnu = len(sp) - len(sr)
         dg = " + ".join(f"g{k}" for k in sp) + " - " + " - ".join(f"g{k}" for k in sr)
         dh = " + ".join(f"h{k}" for k in sp) + " - " + " - ".join(f"h{k}" for k in sr)
@@ -221,14 +279,28 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
         out.append(f"        {{   // reaction {i}")
         out.append(f"            const double lnkf = {_lit(lnA)} + {_lit(b)} * lnT - {_lit(Ea / RU)} * invT;")
         lnkr = f"lnkf + ({dg})" + (f" - {float(dnu)!r} * ln_c0" if dnu else "")
-        out.append("            const double kf = exp(lnkf);")
-        out.append(f"            const double kr = exp({lnkr});")
+        out.append(f"            const double dlnk = ({_lit(b)} + {_lit(Ea / RU)} * invT) * invT;")
+        if pdep:
+            out += ["            " + ln for ln in _pdep_lines(kin, K, order, i, True)]
+            out.append("            const double ekf = exp(lnkf);")
+            out.append("            const double kf = ekf * pd.mult;")
+            if rev_:
+                out.append(f"            const double ekr = exp({lnkr});")
+                out.append("            const double kr = ekr * pd.mult;")
+        else:
+            out.append("            const double kf = exp(lnkf);")
+            if rev_:
+                out.append(f"            const double kr = exp({lnkr});")
         out.append(f"            const double fwd = kf * {_prod_expr(sr)};")
-        out.append(f"            const double rev = kr * {_prod_expr(sp)};")
+        out.append(f"            const double rev = {'kr * ' + _prod_expr(sp) if rev_ else '0.0'};")
         out.append("            const double q = fwd - rev;")
-        out.append(f"            const double qh = {float(len(sr))!r} * fwd - {float(len(sp))!r} * rev;")
+        if pdep:
+            g0 = f"ekf * {_prod_expr(sr)}" + (f" - ekr * {_prod_expr(sp)}" if rev_ else "")
+            out.append(f"            const double G = pd.dM * ({g0});")
+        out.append(f"            const double qh = {float(len(sr))!r} * fwd - {float(len(sp))!r} * rev"
+                   + (" + G * M;" if pdep else ";"))
         out.append(f"            const double dh = {dh};")
-        out.append(f"            const double dlnkf = ({_lit(b)} + {_lit(Ea / RU)} * invT) * invT;")
+        out.append("            const double dlnkf = dlnk" + (" + pd.dlnT;" if pdep else ";"))
         out.append(f"            const double dlnkr = dlnkf - (dh - {float(dnu)!r}) * invT;")
         out.append("            const double dqT = fwd * dlnkf - rev * dlnkr;")
         out.append("            const double qv = q - qh;")
@@ -237,14 +309,15 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
         out.append("            shAC += qh * dh;")
         out.append("            shT += dh * (dqT - qh * invT);")
         out.append(f"            scp += q * ({dcp});")
-        species = sorted(set(sr) | set(sp))
+        species = sorted(set(sr) | (set(sp) if rev_ else set()))
         for sidx in species:
             terms = []
             if sidx in sr:
                 terms.append(f"kf * ({_dprod(sr, sidx)})")
-            if sidx in sp:
+            if sidx in sp and rev_:
                 terms.append(f"- kr * ({_dprod(sp, sidx)})")
             out.append(f"            const double dq{sidx} = {' '.join(terms)};")
+        effrow = _eff_row(kin, K) if pdep else None
         for k, nu in sorted(net.items()):
             if not nu:
                 continue
@@ -252,6 +325,10 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
             out.append(f"            J[{k * N + K}] += {float(nu)!r} * qa;")
             for sidx in species:
                 out.append(f"            J[{k * N + sidx}] += {_lit(nu * W[k] / W[sidx])} * dq{sidx};")
+            if pdep:   # through [M]: d q / d C_l += G eff_l
+                for l, e in enumerate(effrow):
+                    if e != 0.0:
+                        out.append(f"            J[{k * N + l}] += {_lit(nu * e * W[k] / W[l])} * G;")
         out.append("        }")
     out.append("        const double gq = wbar / rho;")
     out.append(f"        const double RT = {_lit(RU)} * T;")

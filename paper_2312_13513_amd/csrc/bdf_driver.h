@@ -17,6 +17,7 @@
 #include <utility>
 
 #include "chem_internal.h"
+#include "kinetics.h"
 
 namespace chem {
 

@@ -22,8 +22,18 @@
 #include "bdf_driver.h"
 #include "bdf_wave.h"
 
+// Built twice: as is, for mechanisms whose reactions are all elementary, and
+// with CHEM_WAVE_PDEP = 1 (bdf_wave_pdep.hip) for mechanisms with third-body
+// or fall-off reactions.  The pressure-dependent terms take registers that
+// would halve the occupancy of the elementary kernels.
+#ifndef CHEM_WAVE_PDEP
+#define CHEM_WAVE_PDEP 0
+#endif
+
 namespace chem {
 namespace {
+
+constexpr bool kPD = CHEM_WAVE_PDEP != 0;
 
 // Lanes that own one cell: Grp<64> is a whole wave (one cell per wave),
 // Grp<16> one DPP row of 16 lanes (four cells per wave, the tile schedule).
@@ -230,6 +240,8 @@ __device__ __forceinline__ double wave_rhs(const DevMechView &m, const WaveTable
         L.C[K] = 1.0;
         L.g[K] = 0.0;
     }
+    double ctot = 0.0;
+    if constexpr (kPD) ctot = Gp::sum(lane < K ? rho * yi * sp.invW : 0.0);
     Gp::sync();
     const double ln_c0 = log(kPstd / kRu) - lnT;
     for (int r = lane; r < m.R; r += G) {
@@ -237,7 +249,16 @@ __device__ __forceinline__ double wave_rhs(const DevMechView &m, const WaveTable
         const double lnkf = x.lnA + x.b * lnT - x.Ea_R * invT;
         const double dg = L.g[x.p0] + L.g[x.p1] - L.g[x.r0] - L.g[x.r1];
         const double lnkr = lnkf + dg - x.dnu * ln_c0;
-        qbuf[r] = exp(lnkf) * L.C[x.r0] * L.C[x.r1] - exp(lnkr) * L.C[x.p0] * L.C[x.p1];
+        const double fwd = exp(lnkf) * L.C[x.r0] * L.C[x.r1];
+        double q = (x.kind & kRxnIrrev) ? fwd : fwd - exp(lnkr) * L.C[x.p0] * L.C[x.p1];
+        if constexpr (kPD) {
+            const int kind = x.kind & 7;
+            if (kind != kRxnElem) {
+                const double M = third_body(x, m.aux, ctot, [&](int l) { return L.C[l]; });
+                q *= pdep_rate<false>(kind, m.aux + x.aux, M, T, lnT, invT, lnkf, 0.0).mult;
+            }
+        }
+        qbuf[r] = q;
     }
     Gp::sync();
     double wk = 0.0;
@@ -287,9 +308,13 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
     if (lane < N)
 #pragma unroll
         for (int c = 0; c < NP + 2; c++) L.row[lane][c] = (LT)0;
+    double ctot = 0.0;
+    if constexpr (kPD) ctot = Gp::sum(lane < K ? rho * yi * sp.invW : 0.0);
     Gp::sync();
     const int R = m.R;
-    double *qh = qbuf + R, *dqT = qbuf + 2 * R, *dq = qbuf + 3 * R;
+    // per reaction: q, sum_l C_l dq/dC_l, dq/dT, dq/dC at the four slots and
+    // (pressure-dependent mechanisms) G = d q / d[M]
+    double *qh = qbuf + R, *dqT = qbuf + 2 * R, *dq = qbuf + 3 * R, *gM = qbuf + 7 * R;
     const double ln_c0 = log(kPstd / kRu) - lnT;
     for (int r = lane; r < R; r += G) {
         const DevRxn x = m.rxn[r];
@@ -297,23 +322,40 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
         const double dg = L.g[x.p0] + L.g[x.p1] - L.g[x.r0] - L.g[x.r1];
         const double dh = L.h[x.p0] + L.h[x.p1] - L.h[x.r0] - L.h[x.r1];
         const double lnkr = lnkf + dg - x.dnu * ln_c0;
-        const double kf = exp(lnkf), kr = exp(lnkr);
+        const int kind = x.kind & 7;
+        const double dlnk = (x.b + x.Ea_R * invT) * invT;
         const double cr0 = L.C[x.r0], cr1 = L.C[x.r1], cp0 = L.C[x.p0], cp1 = L.C[x.p1];
+        const double k0f = exp(lnkf), k0r = (x.kind & kRxnIrrev) ? 0.0 : exp(lnkr);
+        PdepRate pd{1.0, 0.0, 0.0};
+        double M = 0.0;
+        if constexpr (kPD) {
+            if (kind != kRxnElem) {
+                M = third_body(x, m.aux, ctot, [&](int l) { return L.C[l]; });
+                pd = pdep_rate<true>(kind, m.aux + x.aux, M, T, lnT, invT, lnkf, dlnk);
+            }
+        }
+        const double kf = kPD ? k0f * pd.mult : k0f, kr = kPD ? k0r * pd.mult : k0r;
         const double fwd = kf * cr0 * cr1, rev = kr * cp0 * cp1;
         const double mf = (x.r1 != K) ? 2.0 : 1.0, mr = (x.p1 != K) ? 2.0 : 1.0;
-        const double dlnkf = (x.b + x.Ea_R * invT) * invT;
+        const double dlnkf = kPD ? dlnk + pd.dlnT : dlnk;
         const double dlnkr = dlnkf - (dh - x.dnu) * invT;
         qbuf[r] = fwd - rev;
-        qh[r] = mf * fwd - mr * rev;
         dqT[r] = fwd * dlnkf - rev * dlnkr;
         dq[4 * r + 0] = kf * cr1;
         dq[4 * r + 1] = kf * cr0;
         dq[4 * r + 2] = -kr * cp1;
         dq[4 * r + 3] = -kr * cp0;
+        if constexpr (kPD) {
+            const double g = pd.dM * (k0f * cr0 * cr1 - k0r * cp0 * cp1);
+            qh[r] = mf * fwd - mr * rev + g * M;
+            gM[r] = g;
+        } else {
+            qh[r] = mf * fwd - mr * rev;
+        }
     }
     Gp::sync();
     // species rows: owner lane k walks the reactions it takes part in
-    double wk = 0.0, wTk = 0.0, ACk = 0.0;
+    double wk = 0.0, wTk = 0.0, ACk = 0.0, uk = 0.0;
     if (lane < K) {
         const int b = wt.inc_off[lane], e = wt.inc_off[lane + 1];
         for (int j = b; j < e; j++) {
@@ -332,6 +374,17 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
                 const double f = sentinel ? 0.0 : nu * sp.W * L.invW[sl[s]];
                 L.row[lane][c] += (LT)(f * dq[4 * r + s]);
             }
+            if (kPD && (x.kind & 7) != kRxnElem) {
+                // through [M]: the default efficiency on every column (added
+                // with the rank-one term below), the listed ones here
+                const double gn = nu * gM[r];
+                uk += gn * x.def_eff;
+                const double *ef = m.aux + x.aux + kAuxHead;
+                for (int t = 0; t < x.neff; t++) {
+                    const int l = (int)ef[2 * t];
+                    L.row[lane][l] += (LT)(gn * ef[2 * t + 1] * sp.W * L.invW[l]);
+                }
+            }
         }
     }
     const double RT = kRu * T;
@@ -340,6 +393,8 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
     const double S = RT * Gp::sum(lane < K ? hk * wk : 0.0);
     const double hAC = Gp::sum(lane < K ? hk * ACk : 0.0);
     const double dST = Gp::sum(lane < K ? kRu * cpk * wk + RT * hk * (wTk - ACk * invT) : 0.0);
+    double hU = 0.0;
+    if constexpr (kPD) hU = Gp::sum(lane < K ? hk * uk : 0.0);
     Gp::sync();
     // temperature row: lane j sums column j over the species rows
     double JT = 0.0;
@@ -347,6 +402,7 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
         double col = 0.0;
 #pragma unroll 4
         for (int k = 0; k < K; k++) col += (double)L.row[k][lane] * (L.h[k] * L.invW[k]);
+        if constexpr (kPD) col += sp.invW * hU;
         const double dS = RT * rho * (col - (wbar / rho) * sp.invW * hAC);
         const double drcp = rho * sp.invW * (kRu * cpk - cpm * wbar);
         JT = (-dS + S * drcp * inv_rcp) * inv_rcp;
@@ -357,7 +413,7 @@ __device__ __forceinline__ void wave_newton_matrix(const DevMechView &m, const W
     Gp::sync();
     const double gq = wbar / rho;
     if (lane < K) {
-        const double u = sp.W * gq * (wk - ACk);
+        const double u = kPD ? sp.W * (gq * (wk - ACk) + uk) : sp.W * gq * (wk - ACk);
 #pragma unroll 4
         for (int c = 0; c < K; c++) L.row[lane][c] += (LT)(u * L.invW[c]);
         L.row[lane][K] = (LT)(sp.W / rho * (wTk + (wk - ACk) * invT));
@@ -938,7 +994,7 @@ __device__ __forceinline__ void run_block(const DevMechView &m, const WaveTables
 {
     const CellIO io = make_cell_io(T, p, Y, ldY, n, status, counters, prm);
     const int slot = Grp<G>::slot();
-    const size_t q7 = (size_t)7 * (m.R > 0 ? m.R : 1);
+    const size_t q7 = (size_t)m.qstride;
     double *qbuf;
     if constexpr (QLDS)
         qbuf = qlds + slot * q7;
@@ -990,6 +1046,7 @@ __global__ void __launch_bounds__(64) bdf_tile_kernel(DevMechView m, WaveTables 
         ml.W = (const double *)(lds + ((const char *)m.W - base));
         ml.invW = (const double *)(lds + ((const char *)m.invW - base));
         ml.rxn = (const DevRxn *)(lds + ((const char *)m.rxn - base));
+        ml.aux = (const double *)(lds + ((const char *)m.aux - base));
         WaveTables wl;
         wl.inc_off = (const int *)(lds + ((const char *)wt.inc_off - base));
         wl.inc = (const int2 *)(lds + ((const char *)wt.inc - base));
@@ -1003,7 +1060,9 @@ __global__ void __launch_bounds__(64) bdf_tile_kernel(DevMechView m, WaveTables 
 
 }  // namespace
 
+#if !CHEM_WAVE_PDEP
 int wave_kernel_rows(int N) { return N <= 16 ? 16 : (N <= 40 ? 40 : (N <= 64 ? 64 : 0)); }
+#endif
 
 // Persistent grid: as many one-wave blocks as fit on the device at once
 // (occupancy with `dyn` bytes of dynamic LDS), at most one per `cells_per_wave`
@@ -1039,12 +1098,14 @@ constexpr size_t kQbufLdsMax = 49152;     // reaction scratch of one wave kept i
 constexpr size_t kTileStageMax = 24576;   // tables + scratch of a tile block staged in LDS up to this size
 constexpr int64_t kDeferMinCells = 65536; // tile batches from this size defer Newton-matrix refreshes
 
+#if !CHEM_WAVE_PDEP
 bool wave_uses_global_scratch(const DevMechView &m, int lanes)
 {
-    const size_t q7 = (size_t)7 * (m.R > 0 ? m.R : 1) * sizeof(double);
+    const size_t q7 = (size_t)m.qstride * sizeof(double);
     if (lanes == 16) return (size_t)m.table_bytes + 4 * q7 > kTileStageMax;
     return q7 > kQbufLdsMax;
 }
+#endif
 
 template <int NP, typename LT>
 static hipError_t launch_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p, double *Y,
@@ -1052,7 +1113,7 @@ static hipError_t launch_wave(const DevMechView &m, const WaveTables &wt, double
                               int32_t *counters, unsigned long long *queue, double *qscratch, int max_groups,
                               hipStream_t s)
 {
-    const size_t qbytes = (size_t)7 * (m.R > 0 ? m.R : 1) * sizeof(double);
+    const size_t qbytes = (size_t)m.qstride * sizeof(double);
     if (qbytes <= kQbufLdsMax)
         return launch_groups(bdf_wave_kernel<NP, LT, true>, 1, qbytes, false, m, wt, T, p, Y, ldY, n, dt, prm,
                              status, counters, queue, qscratch, max_groups, s);
@@ -1066,7 +1127,7 @@ static hipError_t launch_tile(const DevMechView &m, const WaveTables &wt, double
                               int32_t *counters, unsigned long long *queue, double *qscratch, int max_groups,
                               hipStream_t s)
 {
-    const size_t lds = (size_t)m.table_bytes + (size_t)4 * 7 * (m.R > 0 ? m.R : 1) * sizeof(double);
+    const size_t lds = (size_t)m.table_bytes + (size_t)4 * m.qstride * sizeof(double);
     // refresh deferral pays when the queue holds many cells per group; a
     // small batch is latency bound and runs the plain loop.  A count that
     // lives on the device is taken as small.
@@ -1084,11 +1145,27 @@ static hipError_t launch_tile(const DevMechView &m, const WaveTables &wt, double
 #undef CHEM_TILE
 }
 
+#if CHEM_WAVE_PDEP
+hipError_t launch_bdf_wave_pdep(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
+                                double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
+                                int32_t *status, int32_t *counters, unsigned long long *queue,
+                                double *qscratch, int max_groups, bool fp32_lu, int lanes, hipStream_t s)
+{
+#else
+hipError_t launch_bdf_wave_pdep(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
+                                double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
+                                int32_t *status, int32_t *counters, unsigned long long *queue,
+                                double *qscratch, int max_groups, bool fp32_lu, int lanes, hipStream_t s);
+
 hipError_t launch_bdf_wave(const DevMechView &m, const WaveTables &wt, double *T, const double *p,
                            double *Y, int64_t ldY, int64_t n, double dt, const BdfParams &prm,
                            int32_t *status, int32_t *counters, unsigned long long *queue,
                            double *qscratch, int max_groups, bool fp32_lu, int lanes, hipStream_t s)
 {
+    if (m.n_pdep)
+        return launch_bdf_wave_pdep(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch,
+                                    max_groups, fp32_lu, lanes, s);
+#endif
 #define CHEM_LAUNCH(FN, NPV)                                                                                     \
     return fp32_lu ? FN<NPV, float>(m, wt, T, p, Y, ldY, n, dt, prm, status, counters, queue, qscratch,        \
                                     max_groups, s)                                                             \

@@ -23,13 +23,23 @@ constexpr int kSpeciesLen = 1 + 2 * kRangeLen;
 struct DevRxn {
     int32_t r0, r1, p0, p1;
     int32_t dnu;       // product molecules minus reactant molecules
-    int32_t pad[3];
-    double lnA;        // ln of the SI pre-exponential factor
+    int32_t kind;      // kRxn* pressure dependence, plus kRxnIrrev for no reverse rate
+    int32_t aux;       // pressure-dependent kinds: offset of the record in DevMechView::aux
+    int32_t neff;      // listed third-body efficiencies
+    double lnA;        // ln of the SI pre-exponential factor (high-pressure limit of a fall-off)
     double b;          // temperature exponent
     double Ea_R;       // activation temperature Ea / Ru, K
-    double pad2;
+    double def_eff;    // third-body efficiency of the species not listed
 };
 static_assert(sizeof(DevRxn) == 64, "reaction record is 64 bytes");
+
+// DevRxn::kind: third body, Lindemann fall-off, Troe fall-off (T2 term in
+// the record, 0 without one), plus a flag for an irreversible reaction.
+constexpr int32_t kRxnElem = 0, kRxnThird = 1, kRxnLind = 2, kRxnTroe = 3, kRxnIrrev = 8;
+// Record of a pressure-dependent reaction in DevMechView::aux: the header
+// (ln A0 in SI units, b0, Ea0/Ru, Troe a, 1/T3, 1/T1, T2, has-T2 flag), then
+// neff pairs (species index, efficiency minus the default efficiency).
+constexpr int kAuxHead = 8;
 
 struct DevMechView {
     int32_t K, R;
@@ -40,6 +50,9 @@ struct DevMechView {
     const double *W;            // K, kg/mol
     const double *invW;         // K
     const DevRxn *rxn;          // R
+    const double *aux;          // records of the pressure-dependent reactions (inside the table range)
+    int32_t n_pdep;             // pressure-dependent reactions (0: all elementary)
+    int32_t qstride;            // doubles of reaction scratch per cell of the lane-group kernels
 };
 
 struct BdfParams {

@@ -73,6 +73,11 @@ __device__ void reactor_rhs(const DevMechView &m, double p, const double *y, dou
     C[K] = 1.0;
     wdot[K] = 0.0;
     cpm *= kRu;
+    double ctot = 0.0;   // total concentration (third bodies)
+    if (m.n_pdep) {
+#pragma unroll
+        for (int k = 0; k < K; k++) ctot += C[k];
+    }
     const double ln_c0 = log(kPstd / kRu) - lnT;   // ln(p_std / (R T))
     for (int r = 0; r < m.R; r++) {
         const DevRxn x = m.rxn[r];
@@ -80,7 +85,13 @@ __device__ void reactor_rhs(const DevMechView &m, double p, const double *y, dou
         const double dg = gRT[x.p0] + gRT[x.p1] - gRT[x.r0] - gRT[x.r1];
         // k_r = k_f / K_c with ln K_c = -dg + dnu ln(p_std/(R T))
         const double lnkr = lnkf + dg - x.dnu * ln_c0;
-        const double q = exp(lnkf) * C[x.r0] * C[x.r1] - exp(lnkr) * C[x.p0] * C[x.p1];
+        const double fwd = exp(lnkf) * C[x.r0] * C[x.r1];
+        double q = (x.kind & kRxnIrrev) ? fwd : fwd - exp(lnkr) * C[x.p0] * C[x.p1];
+        const int kind = x.kind & 7;
+        if (kind != kRxnElem) {
+            const double M = third_body(x, m.aux, ctot, [&](int l) { return C[l]; });
+            q *= pdep_rate<false>(kind, m.aux + x.aux, M, T, lnT, invT, lnkf, 0.0).mult;
+        }
         wdot[x.r0] -= q;
         wdot[x.r1] -= q;
         wdot[x.p0] += q;
@@ -134,6 +145,13 @@ __device__ void reactor_jacobian(const DevMechView &m, double p, const double *y
     }
 #pragma unroll
     for (int k = 0; k < KP * KP; k++) A[k] = 0.0;
+    double ctot = 0.0, udef[KP];   // total concentration; dense third-body part of A per row
+    if (m.n_pdep) {
+#pragma unroll
+        for (int k = 0; k < K; k++) ctot += C[k];
+    }
+#pragma unroll
+    for (int k = 0; k < KP; k++) udef[k] = 0.0;
     const double ln_c0 = log(kPstd / kRu) - lnT;
     for (int r = 0; r < m.R; r++) {
         const DevRxn x = m.rxn[r];
@@ -141,11 +159,21 @@ __device__ void reactor_jacobian(const DevMechView &m, double p, const double *y
         const double dg = gRT[x.p0] + gRT[x.p1] - gRT[x.r0] - gRT[x.r1];
         const double dh = hRT[x.p0] + hRT[x.p1] - hRT[x.r0] - hRT[x.r1];
         const double lnkr = lnkf + dg - x.dnu * ln_c0;
-        const double kf = exp(lnkf), kr = exp(lnkr);
+        const int kind = x.kind & 7;
+        const double dlnk = (x.b + x.Ea_R * invT) * invT;
+        // k_f = exp(lnkf) mult; mult = 1 for an elementary reaction
+        PdepRate pd{1.0, 0.0, 0.0};
+        double M = 0.0;
+        if (kind != kRxnElem) {
+            M = third_body(x, m.aux, ctot, [&](int l) { return C[l]; });
+            pd = pdep_rate<true>(kind, m.aux + x.aux, M, T, lnT, invT, lnkf, dlnk);
+        }
+        const double kf = exp(lnkf) * pd.mult;
+        const double kr = (x.kind & kRxnIrrev) ? 0.0 : exp(lnkr) * pd.mult;
         const double fwd = kf * C[x.r0] * C[x.r1];
         const double rev = kr * C[x.p0] * C[x.p1];
         const double q = fwd - rev;
-        const double dlnkf = (x.b + x.Ea_R * invT) * invT;
+        const double dlnkf = dlnk + pd.dlnT;
         const double dlnkr = dlnkf - (dh - x.dnu) * invT;
         const double dqT = fwd * dlnkf - rev * dlnkr;
         // d q / d C at each slot (an empty slot's entry lands on the sentinel)
@@ -159,6 +187,23 @@ __device__ void reactor_jacobian(const DevMechView &m, double p, const double *y
 #pragma unroll
             for (int b = 0; b < 4; b++) A[sl[a] * KP + sl[b]] += nu[a] * dq[b];
         }
+        if (kind != kRxnElem) {
+            // through [M]: d q / d C_l += G eff_l with G = d mult/d[M] (q / mult)
+            const double G = pd.dM * (exp(lnkf) * C[x.r0] * C[x.r1] -
+                                      ((x.kind & kRxnIrrev) ? 0.0 : exp(lnkr) * C[x.p0] * C[x.p1]));
+            const double *e = m.aux + x.aux + kAuxHead;
+#pragma unroll
+            for (int a = 0; a < 4; a++) {
+                udef[sl[a]] += nu[a] * G * x.def_eff;
+                for (int j = 0; j < x.neff; j++) A[sl[a] * KP + (int)e[2 * j]] += nu[a] * G * e[2 * j + 1];
+            }
+        }
+    }
+    if (m.n_pdep) {
+#pragma unroll
+        for (int k = 0; k < K; k++)
+#pragma unroll
+            for (int l = 0; l < K; l++) A[k * KP + l] += udef[k];
     }
     double AC[K];
 #pragma unroll

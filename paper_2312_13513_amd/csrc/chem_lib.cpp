@@ -180,7 +180,7 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
         if (chem::wave_uses_global_scratch(m->view, lanes)) {
             // calls in flight on different streams take different partitions
             const unsigned part = __atomic_fetch_add(&m->next_part, 1u, __ATOMIC_RELAXED) % kScratchParts;
-            qs = m->wave_scratch + (size_t)part * m->wave_slots * 7 * (m->host.R > 0 ? m->host.R : 1);
+            qs = m->wave_scratch + (size_t)part * m->wave_slots * m->view.qstride;
         }
         e = chem::launch_bdf_wave(m->view, m->wave, T, p, Y, ldY, n, dt, prm, status, counters, queue, qs,
                                   m->wave_slots, o.precision == 1, lanes, stream);
@@ -275,6 +275,8 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
             if (h.nasa[k][3 + j] != h.nasa[k][10 + j]) two_range = true;
     }
     std::vector<chem::DevRxn> rx(R > 0 ? R : 1);
+    std::vector<double> aux;   // records of the pressure-dependent reactions
+    int n_pdep = 0;
     for (int i = 0; i < R; i++) {
         const HostRxn &r = h.rxn[i];
         int slots_r[2] = {K, K}, slots_p[2] = {K, K}, nr = 0, np = 0, order = 0;
@@ -290,11 +292,38 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
         d.p1 = slots_p[1];
         d.dnu = np - nr;
         // A in cm-mol-s: (cm^3/mol)^(order-1)/s; SI factor 1e-6 per extra order
-        d.lnA = std::log(r.A) + (order - 1) * std::log(1e-6);
+        // a third body counts as one more colliding molecule
+        d.lnA = std::log(r.A) + (order - 1 + (r.kind == chem_file::kThird ? 1 : 0)) * std::log(1e-6);
         d.b = r.b;
         d.Ea_R = r.Ea / chem::kRu;
+        d.kind = (r.kind == chem_file::kElem ? chem::kRxnElem
+                  : r.kind == chem_file::kThird ? chem::kRxnThird
+                  : r.kind == chem_file::kLind  ? chem::kRxnLind
+                                                : chem::kRxnTroe) |
+                 (r.reversible ? 0 : chem::kRxnIrrev);
+        d.def_eff = r.default_eff;
+        if (r.kind != chem_file::kElem) {
+            d.aux = (int32_t)aux.size();
+            d.neff = (int32_t)r.effs.size();
+            const double head[chem::kAuxHead] = {
+                r.kind >= chem_file::kLind ? std::log(r.A0) + order * std::log(1e-6) : 0.0,
+                r.b0,
+                r.Ea0 / chem::kRu,
+                r.troe[0],
+                r.kind >= chem_file::kTroe3 ? 1.0 / r.troe[1] : 0.0,
+                r.kind >= chem_file::kTroe3 ? 1.0 / r.troe[2] : 0.0,
+                r.kind == chem_file::kTroe4 ? r.troe[3] : 0.0,
+                r.kind == chem_file::kTroe4 ? 1.0 : 0.0};
+            aux.insert(aux.end(), head, head + chem::kAuxHead);
+            for (auto &e : r.effs) {
+                aux.push_back((double)e.first);
+                aux.push_back(e.second - r.default_eff);
+            }
+            n_pdep++;
+        }
         rx[i] = d;
     }
+    if (aux.empty()) aux.assign(2, 0.0);
     m->W = W;
     // one device block: the tables (species | W | invW | reactions | incidence
     // offsets | incidence entries, contiguous so that a kernel can copy them
@@ -326,7 +355,8 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     if (inc_flat.empty()) inc_flat.assign(2, 0);
     const size_t off_io = a16(off_rx + rx.size() * sizeof(chem::DevRxn));
     const size_t off_inc = a16(off_io + (K + 1) * sizeof(int));
-    const size_t table_bytes = a16(off_inc + inc_flat.size() * sizeof(int));
+    const size_t off_aux = a16(off_inc + inc_flat.size() * sizeof(int));
+    const size_t table_bytes = a16(off_aux + aux.size() * sizeof(double));
     const size_t off_q = (table_bytes + 255) & ~size_t(255);
     const size_t off_ws = off_q + kQueues * 256;
     // global reaction scratch, only when a wave or tile variant needs it:
@@ -335,7 +365,10 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     probe.K = K;
     probe.R = R;
     probe.table_bytes = (int32_t)table_bytes;
-    const size_t slice = (size_t)7 * (R > 0 ? R : 1) * sizeof(double);
+    // reaction scratch of the lane-group kernels: 7 R doubles, one R more
+    // for the third-body derivatives when a reaction is pressure dependent
+    probe.qstride = (n_pdep ? 8 : 7) * (R > 0 ? R : 1);
+    const size_t slice = (size_t)probe.qstride * sizeof(double);
     const bool need_ws = (chem::wave_kernel_rows(K + 1) > 0 && chem::wave_uses_global_scratch(probe, 64)) ||
                          (K + 1 <= 16 && chem::wave_uses_global_scratch(probe, 16));
     int wave_slots = 0;
@@ -367,6 +400,7 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     std::memcpy(staging.data() + off_rx, rx.data(), rx.size() * sizeof(chem::DevRxn));
     std::memcpy(staging.data() + off_io, inc_off.data(), inc_off.size() * sizeof(int));
     std::memcpy(staging.data() + off_inc, inc_flat.data(), inc_flat.size() * sizeof(int));
+    std::memcpy(staging.data() + off_aux, aux.data(), aux.size() * sizeof(double));
     rc = check_hip(hipMemcpy(blk, staging.data(), off_ws, hipMemcpyHostToDevice), "hipMemcpy");
     hipSetDevice(prev);
     if (rc != CHEM_OK) {
@@ -383,6 +417,9 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     m->view.invW = (const double *)(blk + off_iw);
     m->view.rxn = (const chem::DevRxn *)(blk + off_rx);
     m->view.table_bytes = (int32_t)table_bytes;
+    m->view.aux = (const double *)(blk + off_aux);
+    m->view.n_pdep = n_pdep;
+    m->view.qstride = probe.qstride;
     m->queues = (unsigned long long *)(blk + off_q);
     m->wave.inc_off = (const int *)(blk + off_io);
     m->wave.inc = (const int2 *)(blk + off_inc);

@@ -36,6 +36,50 @@ class Tokens {
     std::istream &in_;
 };
 
+// Version 2 tail of a reaction line: reversibility flag, kind, the
+// low-pressure triple and Troe parameters of the fall-off kinds, then the
+// default and listed third-body efficiencies of the pressure-dependent kinds.
+int parse_kinetics(Tokens &t, int K, int i, HostRxn &r, std::string &err)
+{
+    const std::string at = " of reaction " + std::to_string(i);
+    auto fail = [&](const std::string &msg) {
+        err = msg + at;
+        return CHEM_EMECH;
+    };
+    int rev = -1;
+    std::string kind;
+    if (!t.num(rev) || (rev != 0 && rev != 1) || !t.word(kind)) return fail("bad kinetics tail");
+    r.reversible = rev == 1;
+    static const char *const names[] = {"elem", "third", "lind", "troe3", "troe4"};
+    r.kind = -1;
+    for (int k = 0; k < 5; k++)
+        if (kind == names[k]) r.kind = k;
+    if (r.kind < 0) return fail("unknown reaction kind '" + kind + "'");
+    if (r.kind == kElem) return CHEM_OK;
+    if (r.kind >= kLind &&
+        (!t.num(r.A0) || !t.num(r.b0) || !t.num(r.Ea0) || !(r.A0 > 0) || !std::isfinite(r.A0) ||
+         !std::isfinite(r.b0) || !std::isfinite(r.Ea0)))
+        return fail("bad low-pressure Arrhenius data");
+    const int ntroe = r.kind == kTroe3 ? 3 : (r.kind == kTroe4 ? 4 : 0);
+    for (int j = 0; j < ntroe; j++)
+        if (!t.num(r.troe[j]) || !std::isfinite(r.troe[j])) return fail("bad Troe parameters");
+    if (ntroe && !(r.troe[1] > 0 && r.troe[2] > 0)) return fail("Troe temperatures T3 and T1 must be > 0");
+    int n = -1;
+    if (!t.num(r.default_eff) || !(r.default_eff >= 0) || !std::isfinite(r.default_eff) || !t.num(n) || n < 0 ||
+        n > K)
+        return fail("bad third-body efficiencies");
+    std::vector<char> seen((size_t)K, 0);
+    for (int j = 0; j < n; j++) {
+        int k = -1;
+        double e = -1;
+        if (!t.num(k) || !t.num(e) || k < 0 || k >= K || !(e >= 0) || !std::isfinite(e) || seen[(size_t)k])
+            return fail("bad third-body efficiency");
+        seen[(size_t)k] = 1;
+        r.effs.push_back({k, e});
+    }
+    return CHEM_OK;
+}
+
 }  // namespace
 
 int parse_mech(std::istream &in, HostMech &m, std::string &err)
@@ -47,8 +91,8 @@ int parse_mech(std::istream &in, HostMech &m, std::string &err)
     Tokens t(in);
     int ver = 0, seed = 0, attempt = 0;
     std::string gen, u;
-    if (!t.expect("CHEMMECH") || !t.num(ver) || ver != 1)
-        return fail(CHEM_EMECH, "not a CHEMMECH 1 file");
+    if (!t.expect("CHEMMECH") || !t.num(ver) || (ver != 1 && ver != 2))
+        return fail(CHEM_EMECH, "not a CHEMMECH 1 or 2 file");
     if (!t.expect("generator") || !t.word(gen) || !t.expect("seed") || !t.num(seed) ||
         !t.expect("attempt") || !t.num(attempt) || !t.expect("units"))
         return fail(CHEM_EMECH, "bad header");
@@ -113,6 +157,10 @@ int parse_mech(std::istream &in, HostMech &m, std::string &err)
         for (auto &s : r.prod) mp += s.second;
         if (mr > 2 || mp > 2)
             return fail(CHEM_EMECH, "reaction " + std::to_string(i) + " has more than two molecules on a side");
+        if (ver == 2) {
+            const int rc = parse_kinetics(t, m.K, i, r, err);
+            if (rc != CHEM_OK) return rc;
+        }
         for (int e = 0; e < m.E; e++) {
             int bal = 0;
             for (auto &s : r.reac) bal -= s.second * m.counts[s.first][e];

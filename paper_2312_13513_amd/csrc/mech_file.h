@@ -1,5 +1,7 @@
 // Reader of the text mechanism format (.mech): species with element counts
-// and NASA-7 polynomials, reactions with mass-action Arrhenius rates.  Plain
+// and NASA-7 polynomials, reactions with mass-action Arrhenius rates and (in
+// format version 2) third-body, Lindemann or Troe fall-off pressure
+// dependence and irreversible reactions.  Plain
 // C++17 with no HIP dependency, so it can also be built for the host alone
 // (the sanitizer build of the tests does so).
 #pragma once
@@ -11,9 +13,19 @@
 
 namespace chem_file {
 
+// Pressure dependence of a reaction (format version 2; version 1 files hold
+// elementary reversible reactions only).
+enum RxnKind { kElem = 0, kThird = 1, kLind = 2, kTroe3 = 3, kTroe4 = 4 };
+
 struct HostRxn {
     std::vector<std::pair<int, int>> reac, prod;   // (species, coefficient)
-    double A = 0, b = 0, Ea = 0;
+    double A = 0, b = 0, Ea = 0;                   // A in cm-mol-s, Ea in J/mol
+    int kind = kElem;
+    bool reversible = true;
+    double default_eff = 1.0;                      // third-body efficiency of unlisted species
+    std::vector<std::pair<int, double>> effs;      // (species, efficiency), species distinct
+    double A0 = 0, b0 = 0, Ea0 = 0;                // low-pressure limit (fall-off kinds)
+    double troe[4] = {0, 0, 0, 0};                 // a, T3, T1, T2 (T2: kTroe4 only)
 };
 
 struct HostMech {

@@ -14,10 +14,11 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def mech_dir(tmp_path_factory):
-    """The two standard synthetic mechanisms written as .mech files."""
+    """The standard synthetic mechanisms written as .mech files (M9, M35, and
+    the stand-ins with real-mechanism features H2R and CH4R)."""
     from chemgen.mechanism import standard_mechanism
     d = tmp_path_factory.mktemp("mech")
-    for name in ("M9", "M35"):
+    for name in ("M9", "M35", "H2R", "CH4R"):
         standard_mechanism(name).write(str(d / f"{name}.mech"))
     return d
 

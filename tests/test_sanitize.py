@@ -42,6 +42,7 @@ def run(*cmd):
 
 def damaged_mechs(text: str, d):
     """(path, must_reject) for damaged copies of a mechanism file."""
+    d.mkdir(exist_ok=True)
     toks = text.split()
     out = []
 
@@ -71,11 +72,13 @@ def damaged_mechs(text: str, d):
 
 def test_mechanism_readers_under_sanitizers(bins, mech_dir, tmp_path):
     host, orc = bins
-    good = [mech_dir / "M9.mech", mech_dir / "M35.mech"]
-    assert run(host, "mech", *good) == ["ok 9 21 3", "ok 35 200 4"]
+    good = [mech_dir / f"{n}.mech" for n in ("M9", "M35", "H2R", "CH4R")]
+    want = ["ok 9 21 3", "ok 35 200 4", "ok 9 12 3", "ok 20 85 4"]
+    assert run(host, "mech", *good) == want
     lines = run(orc, *good)
-    assert lines[0].startswith("ok 9 21 3 ") and lines[1].startswith("ok 35 200 4 ")
-    cases = damaged_mechs((mech_dir / "M9.mech").read_text(), tmp_path)
+    assert all(ln.startswith(w + " ") for ln, w in zip(lines, want))
+    cases = damaged_mechs((mech_dir / "M9.mech").read_text(), tmp_path / "m9")
+    cases += damaged_mechs((mech_dir / "H2R.mech").read_text(), tmp_path / "h2r")
     got_lib = run(host, "mech", *[p for p, _ in cases])
     got_orc = run(orc, *[p for p, _ in cases])
     assert len(got_lib) == len(got_orc) == len(cases)
