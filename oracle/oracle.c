@@ -34,6 +34,7 @@
 
 #define OM_KMAX 64
 #define OM_NMAX (OM_KMAX + 1)
+#define OM_EMAX 16
 #define OM_RU 8.31446261815324 /* J/(mol K), CODATA 2018 exact */
 #define OM_PSTD 101325.0       /* standard-state pressure, Pa (1 atm) */
 
@@ -56,7 +57,7 @@ typedef struct {
 typedef struct {
     int K, R, E;
     double W[OM_KMAX];          /* kg/mol */
-    int counts[OM_KMAX][4];
+    int counts[OM_KMAX][OM_EMAX];
     double nasa[OM_KMAX][17];   /* Tlo Tmid Thi, 7 low, 7 high */
     om_rxn *rxn;
 } om_mech;
@@ -123,7 +124,7 @@ void *om_load(const char *path)
     om_mech *m = calloc(1, sizeof(om_mech));
     char buf[128];
     int ver, seed, attempt;
-    double aw[4] = {0, 0, 0, 0};
+    double aw[OM_EMAX] = {0};
     if (expect_word(fp, "CHEMMECH") || fscanf(fp, "%d", &ver) != 1 || (ver != 1 && ver != 2)) goto fail;
     if (expect_word(fp, "generator") || fscanf(fp, "%127s", buf) != 1) goto fail;
     if (expect_word(fp, "seed") || fscanf(fp, "%d", &seed) != 1) goto fail;
@@ -131,7 +132,7 @@ void *om_load(const char *path)
     if (expect_word(fp, "units")) goto fail;
     for (int i = 0; i < 6; i++)
         if (fscanf(fp, "%127s", buf) != 1) goto fail;
-    if (expect_word(fp, "elements") || fscanf(fp, "%d", &m->E) != 1 || m->E < 1 || m->E > 4) goto fail;
+    if (expect_word(fp, "elements") || fscanf(fp, "%d", &m->E) != 1 || m->E < 1 || m->E > OM_EMAX) goto fail;
     for (int e = 0; e < m->E; e++)
         if (fscanf(fp, "%127s %lf", buf, &aw[e]) != 2) goto fail;
     if (expect_word(fp, "species") || fscanf(fp, "%d", &m->K) != 1 || m->K < 1 || m->K > OM_KMAX) goto fail;
