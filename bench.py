@@ -2,8 +2,10 @@
 
 Default workload (``--workload flame64``): the plain FP64 GPU integrator on
 the 64^3 flame field (262,144 cells, 9-species / 21-reaction synthetic
-mechanism, dt = 1e-6 s, rtol 1e-8, atol 1e-12), in the library's choice of
-schedule (the 16-lane tile for this mechanism; --schedule picks another).  One step = one call of
+mechanism, dt = 1e-6 s, rtol 1e-8, atol 1e-12), in the autotuned launch
+configuration (schedule -2 after chem_autotune on the field, outside the
+timed region; the line reports the tuner's whole measured table; --schedule
+fixes one instead).  One step = one call of
 chem_integrate over all cells, starting from the same pristine field
 (restored by a device-to-device copy inside the step, so the copy is timed
 too).  Prints ONE JSON line: the metric, the roofline of the integrator
@@ -188,7 +190,7 @@ def run_integrator(args, workload: str):
     from paper_2312_13513_amd import chem
 
     if workload == "flame64":
-        mname, make, precision, schedule = "M9", F.flame64, 0, -1
+        mname, make, precision, schedule = "M9", F.flame64, 0, -2
         desc = "flame64: 262,144 cells (64^3 smooth flame field), synthetic 9-species/21-reaction mechanism"
     elif workload == "cells4096":
         mname, make, precision, schedule = "M9", F.cells4096, 0, -1
@@ -220,6 +222,20 @@ def run_integrator(args, workload: str):
     T0 = torch.tensor(field.T, dtype=torch.float64, device=dev)
     p0 = torch.tensor(field.p, dtype=torch.float64, device=dev)
     Y0 = torch.tensor(field.Y, dtype=torch.float64, device=dev)
+    tune = None
+    if schedule == -2:
+        # launch configuration measured on this field (not timed); the steps
+        # below then run the tuned choice
+        t_tune = time.perf_counter()
+        best, use_lpt, best_ms = mech.autotune(T0, p0, Y0, field.dt, opts=opts)
+        table = mech.autotune_results()
+        schedule = best.schedule
+        tune = {"chosen": {"schedule": best.schedule, "jac_batch": best.jac_batch,
+                           "waves_per_simd": best.waves_per_simd, "lpt": int(use_lpt), "ms": best_ms},
+                "sample_cells": min(n, 262144), "tuning_s": time.perf_counter() - t_tune,
+                "table": [{k: (round(v, 4) if k == "ms" else v) for k, v in e.items()} for e in table]}
+        progress(f"autotune: schedule {best.schedule} jac_batch {best.jac_batch} waves/SIMD "
+                 f"{best.waves_per_simd} lpt {int(use_lpt)} {best_ms:.3f} ms")
     T, Y = T0.clone(), Y0.clone()
     status = torch.zeros(n, dtype=torch.int32, device=dev)
     counters = torch.zeros(6 * n, dtype=torch.int32, device=dev)
@@ -279,6 +295,8 @@ def run_integrator(args, workload: str):
                      "rhs_per_cell": float(cnt[1].mean()), "jac_per_cell": float(cnt[2].mean())},
         "status_ok_frac": float(np.mean(st == 0)),
     }
+    if tune is not None:
+        result["autotune"] = tune
     if field.zone is not None:
         result["substeps"]["per_zone_mean"] = {name: float(cnt[0][field.zone == z].mean())
                                                for z, name in enumerate(("cold", "front", "burnt"))}
@@ -575,8 +593,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="flame64", choices=("flame64", "cells4096", "zones128", "surrogate"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedule", type=int, default=None, choices=(-1, 0, 1, 2),
-                    help="integrator workloads: -1 library choice, 0 thread, 1 wave, 2 tile per cell")
+    ap.add_argument("--schedule", type=int, default=None, choices=(-2, -1, 0, 1, 2),
+                    help="integrator workloads: -2 autotuned (flame64 default), -1 library choice, 0 thread, "
+                         "1 wave, 2 tile per cell")
     ap.add_argument("--cpu-sample", type=int, default=0, help="cells for the oracle timing (0 = workload default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="repeat the oracle sample until this long")
     ap.add_argument("--train-samples", type=int, default=2 * 1024 * 1024)

@@ -76,8 +76,10 @@ typedef struct {
                            -1 = library choice (one thread per cell for a
                            compiled-in mechanism in FP64, else the tile schedule
                            when K <= 15, else one wave per cell), 0 = one thread per cell
-                           (FP64 only; K <= 9 table kernel or
-                           a compiled-in mechanism), 1 = one 64-lane wave per
+                           (FP64 only; a compiled-in mechanism: its straight-line
+                           kernels keep a cell's state in registers and LDS,
+                           which table-driven kernels cannot do without
+                           spilling), 1 = one 64-lane wave per
                            cell (any K <= 63), 2 = tile: 16 lanes per cell, four
                            cells per wave (K <= 15; the same operations per
                            cell as 1).  CHEM_EUNSUP when the chosen schedule
@@ -89,7 +91,10 @@ typedef struct {
                            do not depend on it. */
     int32_t qmax;       /* highest BDF order the step selection may raise to,
                            1..5 (0 = 5, the default method) */
-    int32_t reserved[6];
+    int32_t waves_per_simd; /* at most this many waves of the integrator per
+                           SIMD (a cap on the persistent grid; 0 = as many as
+                           fit).  Scheduling only: results do not depend on it. */
+    int32_t reserved[5];
 } chem_opts;
 
 /* Fill opts with the defaults above (rtol, atol and the BDF limits of the
@@ -202,18 +207,33 @@ int chem_lpt_order(const int32_t *cost, int64_t n, int32_t *order, void *hip_str
 
 /* Launch configuration chosen by measurement (Section 3.2: optimisations of
  * the kernels and of their launch).
- * Autotuner: times every schedule that can serve the mechanism at
- * opts->precision (one thread per cell with jac_batch 4, 16, 64; one wave
- * per cell; the 16-lane tile when K <= 15), each in natural and in LPT
- * order, on a strided sample of at
- * most max_sample cells (0 = 65,536) of the given states (not modified),
- * and returns the fastest as *best (schedule, jac_batch filled in),
- * *use_lpt (1 if the LPT order was faster) and *best_ms.  The choice is also
- * kept in the handle: opts.schedule = -2 then selects it.  Allocates and
- * synchronises (a planning call). */
+ * Autotuner: times every configuration that can serve the mechanism at
+ * opts->precision -- one thread per cell (compiled-in mechanisms, FP64) with
+ * jac_batch 4, 16, 64; one wave per cell and the 16-lane tile (K <= 15),
+ * each at the most waves per SIMD that fit and at one, in natural and in
+ * LPT order -- twice each on a strided sample of at most max_sample cells
+ * (0 = 262,144, four cells per lane of a full device for the thread
+ * schedule; the whole field when it is smaller) of the given states (not
+ * modified), and returns the fastest as *best (schedule, jac_batch,
+ * waves_per_simd filled in), *use_lpt (1 if the LPT order was faster) and
+ * *best_ms.  The choice is kept in the handle per precision and per
+ * size class floor(log2(ncells)); opts.schedule = -2 selects the choice of
+ * the call's size class (else of the nearest tuned one).  With the
+ * environment variable CHEM_TUNE_CACHE naming a file, every result is also
+ * appended there as a text line (GPU architecture, mechanism file hash,
+ * species count, precision, size class, choice, time) and loading the same
+ * mechanism file on the same architecture restores it.  chem_autotune_results
+ * copies the measured table of the handle's last chem_autotune (at most
+ * capacity entries, host memory; *count = the number measured).  Allocates
+ * and synchronises: a planning call, not for a capture. */
+typedef struct {
+    int32_t schedule, jac_batch, lpt, waves_per_simd;
+    double ms;          /* fastest of the two timed runs, HIP events */
+} chem_tune_entry;
 int chem_autotune(chem_mech mech, const double *T, const double *p, const double *Y, int64_t ldY,
-                  int64_t ncells, double dt, const chem_opts *opts, int32_t max_sample,
-                  chem_opts *best, int32_t *use_lpt, double *best_ms, void *hip_stream);
+                  int64_t ncells, double dt, const chem_opts *base, int32_t max_sample, chem_opts *best,
+                  int32_t *use_lpt, double *best_ms, void *hip_stream);
+int chem_autotune_results(chem_mech mech, chem_tune_entry *out, int32_t capacity, int32_t *count);
 
 /* Right-hand side of the reactor ODE at the given states (Section 2's
  * species and temperature equations; diagnostics and parity tests of the

@@ -28,7 +28,13 @@ class ChemError(RuntimeError):
 class chem_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
                 ("precision", C.c_int32), ("schedule", C.c_int32), ("block", C.c_int32),
-                ("jac_batch", C.c_int32), ("qmax", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("jac_batch", C.c_int32), ("qmax", C.c_int32), ("waves_per_simd", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
+class chem_tune_entry(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("jac_batch", C.c_int32), ("lpt", C.c_int32),
+                ("waves_per_simd", C.c_int32), ("ms", C.c_double)]
 
 
 class chem_stats(C.Structure):
@@ -68,6 +74,7 @@ def _load():
     L.chem_get_stats.argtypes = [vp, vp, i64, vp, C.POINTER(chem_stats), vp]
     L.chem_autotune.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), C.c_int32,
                                 C.POINTER(chem_opts), i32p, C.POINTER(C.c_double), vp]
+    L.chem_autotune_results.argtypes = [vp, C.POINTER(chem_tune_entry), C.c_int32, i32p]
     fp, dblp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int64)
     ckp = C.POINTER(chem_surr_checks)
     L.chem_surrogate_default_checks.argtypes = [ckp]
@@ -118,7 +125,8 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_get_grads", "chem_surrogate_set_grads", "chem_surrogate_adam",
             "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_reserve",
             "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace", "chem_integrate_noalloc",
-            "chem_surrogate_train_part", "chem_surrogate_save_checkpoint", "chem_surrogate_checkpoint_user")
+            "chem_surrogate_train_part", "chem_surrogate_save_checkpoint", "chem_surrogate_checkpoint_user",
+            "chem_autotune_results")
 
 
 def lib():
@@ -247,6 +255,15 @@ class Mechanism:
                                   float(dt), C.byref(opts) if opts is not None else None, int(max_sample),
                                   C.byref(best), C.byref(lpt), C.byref(ms), _stream(stream)))
         return best, bool(lpt.value), ms.value
+
+    def autotune_results(self) -> list:
+        """Measured table of the last autotune: dicts of schedule, jac_batch,
+        lpt, waves_per_simd, ms."""
+        n = C.c_int32()
+        _check(_lib.chem_autotune_results(C.c_void_p(self.handle), None, 0, C.byref(n)))
+        buf = (chem_tune_entry * max(1, n.value))()
+        _check(_lib.chem_autotune_results(C.c_void_p(self.handle), buf, n.value, C.byref(n)))
+        return [{k: getattr(e, k) for k, _ in chem_tune_entry._fields_} for e in buf[:n.value]]
 
     def rhs(self, T, p, Y, F, stream=None):
         chem_eval_rhs(self.handle, T, p, Y, F, stream)

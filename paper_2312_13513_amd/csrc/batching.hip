@@ -182,7 +182,7 @@ int chem_autotune(chem_mech m, const double *T, const double *p, const double *Y
     chem_default_opts(&o0);
     if (base) o0 = *base;
     const int K = m->host.K;
-    const int64_t ns = std::min<int64_t>(n, max_sample > 0 ? max_sample : 65536);
+    const int64_t ns = std::min<int64_t>(n, max_sample > 0 ? max_sample : 262144);
     hipStream_t st = (hipStream_t)stream;
     // strided sample of the field, copied into work arrays
     std::vector<int32_t> hidx((size_t)ns);
@@ -227,23 +227,27 @@ int chem_autotune(chem_mech m, const double *T, const double *p, const double *Y
         }
         return CHEM_OK;
     };
-    const bool thread_ok = (m->gen != nullptr || chem::thread_kernel_supports(K)) && o0.precision == 0;
+    const bool thread_ok = m->gen != nullptr && o0.precision == 0;
     const bool wave_ok = chem::wave_kernel_rows(K + 1) > 0;
     const bool tile_ok = K + 1 <= 16;
     struct Cand {
-        int schedule, jac_batch, lpt;
+        int schedule, jac_batch, lpt, waves;
     };
     std::vector<Cand> cands;
-    for (int l = 0; l < 2; l++) {
-        if (thread_ok)
-            for (int jb : {4, 16, 64}) cands.push_back({0, jb, l});
-        if (wave_ok) cands.push_back({1, 0, l});
-        if (tile_ok) cands.push_back({2, 0, l});
-    }
+    // the thread schedule orders its cells itself (start pass): no LPT variant
+    if (thread_ok)
+        for (int jb : {4, 16, 64}) cands.push_back({0, jb, 0, 0});
+    for (int l = 0; l < 2; l++)
+        for (int w : {0, 1}) {
+            if (wave_ok) cands.push_back({1, 0, l, w});
+            if (tile_ok) cands.push_back({2, 0, l, w});
+        }
+    const bool any_lpt = wave_ok || tile_ok;
     // a first run in natural order gives the per-cell step counts for LPT
     float best_t = 1e30f;
-    Cand bc{-1, 0, 0};
-    if (rc == CHEM_OK) {
+    Cand bc{-1, 0, 0, 0};
+    std::vector<chem_tune_entry> table;
+    if (rc == CHEM_OK && any_lpt) {
         chem_opts o = o0;
         o.schedule = -1;
         float t = 0.0f;
@@ -256,9 +260,12 @@ int chem_autotune(chem_mech m, const double *T, const double *p, const double *Y
         chem_opts o = o0;
         o.schedule = cands[c].schedule;
         o.jac_batch = cands[c].jac_batch;
+        o.waves_per_simd = cands[c].waves;
         float t = 0.0f;
         rc = run(o, cands[c].lpt ? lpt : nullptr, t);
-        if (rc == CHEM_OK && t < best_t) {
+        if (rc != CHEM_OK) break;
+        table.push_back({cands[c].schedule, cands[c].jac_batch, cands[c].lpt, cands[c].waves, (double)t});
+        if (t < best_t) {
             best_t = t;
             bc = cands[c];
         }
@@ -271,12 +278,34 @@ int chem_autotune(chem_mech m, const double *T, const double *p, const double *Y
     *best = o0;
     best->schedule = bc.schedule;
     best->jac_batch = bc.jac_batch;
-    auto &tu = m->tuned[o0.precision == 1 ? 1 : 0];
-    tu.valid = true;
+    best->waves_per_simd = bc.waves;
+    const int prec = o0.precision == 1 ? 1 : 0;
+    // kept for the size class of the calls this sample stands for
+    const int cls = size_class(n);
+    Tuned tu;
     tu.schedule = bc.schedule;
     tu.jac_batch = bc.jac_batch;
+    tu.waves_per_simd = bc.waves;
+    tu.lpt = bc.lpt;
+    tu.ms = best_t;
+    {
+        std::lock_guard<std::mutex> lk(m->ws_mu);
+        m->tuned[{prec, cls}] = tu;
+        m->tune_results = table;
+    }
+    chem_host::tune_cache_append(m, prec, cls, tu);
     if (use_lpt) *use_lpt = bc.lpt;
     if (best_ms) *best_ms = best_t;
+    return CHEM_OK;
+}
+
+int chem_autotune_results(chem_mech m, chem_tune_entry *out, int32_t capacity, int32_t *count)
+{
+    if (!m || !count || capacity < 0 || (capacity > 0 && !out))
+        return fail(CHEM_EINVAL, "mech and count must not be NULL, capacity >= 0");
+    std::lock_guard<std::mutex> lk(m->ws_mu);
+    *count = (int32_t)m->tune_results.size();
+    for (int32_t i = 0; i < capacity && i < *count; i++) out[i] = m->tune_results[(size_t)i];
     return CHEM_OK;
 }
 

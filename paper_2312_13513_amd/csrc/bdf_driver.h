@@ -970,7 +970,7 @@ __global__ void reset_queue_kernel(unsigned long long *queue);
 
 // Grid of the queue kernel: enough one-wave blocks to fill every CU at the
 // kernel's occupancy, never more lanes than cells.
-int queue_grid(const void *kernel, int64_t n);
+int queue_grid(const void *kernel, int64_t n, int waves_per_simd);
 
 // Bytes of the start-pass workspace for `items` work items of an N-component
 // cell, and its layout in such a buffer (256-byte aligned pieces).
@@ -1014,7 +1014,7 @@ hipError_t launch_thread_integrate(const Mech &mech, double *T, const double *p,
     hipLaunchKernelGGL(bdf_start_kernel<Mech>, dim3(gb), dim3(256), 0, s, mech, T, p, Y, ldY, n, dt, prm, sp);
     hipLaunchKernelGGL(start_scan_kernel, dim3(1), dim3(64), 0, s, sp.cnt);
     hipLaunchKernelGGL(start_scatter_kernel, dim3(gb), dim3(256), 0, s, sp.key, sp.cnt, sp.ord, n, prm);
-    const int blocks = queue_grid((const void *)bdf_queue_kernel<Mech>, items);
+    const int blocks = queue_grid((const void *)bdf_queue_kernel<Mech>, items, prm.waves_per_simd);
     hipLaunchKernelGGL(bdf_queue_kernel<Mech>, dim3(blocks), dim3(64), 0, s, mech, T, p, Y, ldY, n, dt, prm,
                        status, counters, queue, sp);
     return hipGetLastError();

@@ -1083,6 +1083,8 @@ static hipError_t launch_groups(Kern kern, int cells_per_wave, size_t dyn, bool 
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 64, dyn) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
+        // one-wave blocks: four SIMDs per compute unit
+        if (prm.waves_per_simd > 0 && per_cu > 4 * prm.waves_per_simd) per_cu = 4 * prm.waves_per_simd;
         blocks = cus * per_cu;
     }
     if (qglobal && blocks > max_groups / cells_per_wave) blocks = max_groups / cells_per_wave;

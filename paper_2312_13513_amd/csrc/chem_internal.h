@@ -63,6 +63,7 @@ struct BdfParams {
     const int32_t *idx;     // if not NULL: integrate cells idx[0 .. n_idx) in this order
     int64_t n_idx;
     int32_t qmax;           // highest order the step selection may raise to (1..kQmax)
+    int32_t waves_per_simd; // cap on the persistent grid (0: as many waves as fit)
 };
 
 // Launchers of the table-driven kernels.  Return hipError_t of the launch.
@@ -71,10 +72,9 @@ hipError_t launch_rhs(const DevMechView &m, const double *T, const double *p, co
 hipError_t launch_jacobian(const DevMechView &m, const double *T, const double *p, const double *Y,
                            int64_t ldY, int64_t n, double *J, int64_t ldJ, hipStream_t s);
 struct StartPass;
-hipError_t launch_bdf_thread(const DevMechView &m, double *T, const double *p, double *Y,
-                             int64_t ldY, int64_t n, double dt, const BdfParams &prm,
-                             int32_t *status, int32_t *counters, unsigned long long *queue,
-                             const StartPass &sp, int64_t items, hipStream_t s);
-bool thread_kernel_supports(int K);
+// Species counts with table-driven right-hand-side and Jacobian evaluation
+// kernels (chem_eval_rhs / chem_eval_jacobian of a mechanism that is not
+// compiled in).
+bool table_eval_supports(int K);
 
 }  // namespace chem

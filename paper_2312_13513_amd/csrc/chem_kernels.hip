@@ -295,13 +295,15 @@ __global__ void __launch_bounds__(256) start_scatter_kernel(const int32_t *key, 
     if (in) ord[base[k] + rank] = (int32_t)it;
 }
 
-int queue_grid(const void *kernel, int64_t n)
+int queue_grid(const void *kernel, int64_t n, int waves_per_simd)
 {
     int dev = 0, cus = 0, per_cu = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
+    // one-wave blocks: four SIMDs per compute unit
+    if (waves_per_simd > 0 && per_cu > 4 * waves_per_simd) per_cu = 4 * waves_per_simd;
     int64_t blocks = (int64_t)cus * per_cu;
     const int64_t need = (n + 63) / 64;
     if (blocks > need) blocks = need;
@@ -310,7 +312,7 @@ int queue_grid(const void *kernel, int64_t n)
 
 #define CHEM_FOR_EACH_K(X) X(9)
 
-bool thread_kernel_supports(int K)
+bool table_eval_supports(int K)
 {
 #define CHEM_CASE(KK) if (K == KK) return true;
     CHEM_FOR_EACH_K(CHEM_CASE)
@@ -341,20 +343,6 @@ hipError_t launch_jacobian(const DevMechView &m, const double *T, const double *
                            dim3(64), 0, s, TableMech<KK>{m}, T, p, Y, ldY, n, J, ldJ);           \
         return hipGetLastError();                                                                \
     }
-    CHEM_FOR_EACH_K(CHEM_CASE)
-#undef CHEM_CASE
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_bdf_thread(const DevMechView &m, double *T, const double *p, double *Y,
-                             int64_t ldY, int64_t n, double dt, const BdfParams &prm,
-                             int32_t *status, int32_t *counters, unsigned long long *queue,
-                             const StartPass &sp, int64_t items, hipStream_t s)
-{
-#define CHEM_CASE(KK)                                                                             \
-    if (m.K == KK)                                                                                \
-        return launch_thread_integrate(TableMech<KK>{m}, T, p, Y, ldY, n, dt, prm, status, counters, \
-                                       queue, sp, items, s);
     CHEM_FOR_EACH_K(CHEM_CASE)
 #undef CHEM_CASE
     return hipErrorInvalidValue;

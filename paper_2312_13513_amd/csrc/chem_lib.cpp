@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <iterator>
@@ -113,6 +114,43 @@ int check_hip(hipError_t e, const char *what)
     return fail(CHEM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+void tune_cache_append(const chem_mech_s *m, int precision, int cls, const Tuned &t)
+{
+    const char *path = std::getenv("CHEM_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;
+    char line[256];
+    std::snprintf(line, sizeof(line), "chemtune1 %s %016llx %d %d %d %d %d %d %d %.6g\n", m->arch.c_str(),
+                  m->file_hash, m->host.K, precision, cls, t.schedule, t.jac_batch, t.waves_per_simd, t.lpt, t.ms);
+    f << line;
+}
+
+void tune_cache_restore(chem_mech_s *m)
+{
+    const char *path = std::getenv("CHEM_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string tag, arch, hash;
+        int K = 0, prec = 0, cls = 0;
+        Tuned t;
+        if (!(is >> tag >> arch >> hash >> K >> prec >> cls >> t.schedule >> t.jac_batch >> t.waves_per_simd >>
+              t.lpt >> t.ms))
+            continue;
+        char want[32];
+        std::snprintf(want, sizeof(want), "%016llx", m->file_hash);
+        // later lines win; values outside the option ranges are ignored
+        if (tag != "chemtune1" || arch != m->arch || hash != want || K != m->host.K || prec < 0 || prec > 1 ||
+            cls < 0 || cls > 62 || t.schedule < 0 || t.schedule > 2 || t.jac_batch < 0 || t.jac_batch > 64 ||
+            t.waves_per_simd < 0)
+            continue;
+        m->tuned[{prec, cls}] = t;
+    }
+}
+
 bool is_device_ptr(const void *p)
 {
     if (!p) return false;
@@ -142,24 +180,38 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
     if (o.max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
     if (o.precision != 0 && o.precision != 1) return fail(CHEM_EINVAL, "precision must be 0 or 1");
     if (o.schedule < -2 || o.schedule > 2) return fail(CHEM_EINVAL, "unknown schedule");
+    if (o.waves_per_simd < 0) return fail(CHEM_EINVAL, "waves_per_simd must be >= 0");
     if (o.schedule == -2) {
-        const auto &tu = m->tuned[o.precision == 1 ? 1 : 0];
-        o.schedule = tu.valid ? tu.schedule : -1;
-        if (tu.valid && o.jac_batch == 0) o.jac_batch = tu.jac_batch;
+        // the tuned choice of this call's size class, else of the nearest tuned one
+        const int64_t items = idx ? n_idx : n;
+        Tuned t;
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(m->ws_mu);
+            const Tuned *tu = m->find_tuned(o.precision == 1 ? 1 : 0, size_class(items));
+            if (tu) {
+                t = *tu;
+                have = true;
+            }
+        }
+        o.schedule = have ? t.schedule : -1;
+        if (have && o.jac_batch == 0) o.jac_batch = t.jac_batch;
+        if (have && o.waves_per_simd == 0) o.waves_per_simd = t.waves_per_simd;
     }
     if (o.block != 0 && o.block != 64) return fail(CHEM_EUNSUP, "block must be 0 or 64");
     if (n == 0) return CHEM_OK;
     if ((status && !is_device_ptr(status)) || (counters && !is_device_ptr(counters)))
         return fail(CHEM_EINVAL, "status and counters must be device pointers or NULL");
     const int K = m->host.K;
-    const bool thread_ok = m->gen != nullptr || chem::thread_kernel_supports(K);
+    const bool thread_ok = m->gen != nullptr;
     const bool wave_ok = chem::wave_kernel_rows(K + 1) > 0;
     // automatic choice: one thread per cell for a compiled-in mechanism
     // (state in registers and LDS, no spill), else the 16-lane tile when a
     // cell fits in it (N <= 16), else one wave per cell
     const int sched = o.schedule >= 0 ? o.schedule : (m->gen && o.precision == 0 ? 0 : (K + 1 <= 16 ? 2 : 1));
     if (sched == 0 && !thread_ok)
-        return fail(CHEM_EUNSUP, "no one-thread-per-cell kernel is built for K = " + std::to_string(K));
+        return fail(CHEM_EUNSUP, "the one-thread-per-cell schedule needs a compiled-in mechanism (list the "
+                                 ".mech file in CHEM_EXTRA_MECHS when building)");
     if (sched == 0 && o.precision != 0)
         return fail(CHEM_EUNSUP, "the one-thread-per-cell schedule computes in FP64 only");
     if (sched == 1 && !wave_ok)
@@ -169,7 +221,8 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
     if (o.jac_batch < 0 || o.jac_batch > 64) return fail(CHEM_EINVAL, "jac_batch must be in 0..64");
     if (o.qmax < 0 || o.qmax > chem::kQmax) return fail(CHEM_EINVAL, "qmax must be in 0..5");
     chem::BdfParams prm{o.rtol,  o.atol, o.max_steps, o.jac_batch > 0 ? o.jac_batch : 16,
-                        n_dev,   idx,    n_idx,       o.qmax > 0 ? o.qmax : chem::kQmax};
+                        n_dev,   idx,    n_idx,       o.qmax > 0 ? o.qmax : chem::kQmax,
+                        o.waves_per_simd};
     // each call takes its own queue counter (64 rotate), so that calls in
     // flight on different streams do not share one
     unsigned long long *queue = m->queues + 32 * (__atomic_fetch_add(&m->next_queue, 1u, __ATOMIC_RELAXED) % kQueues);
@@ -204,11 +257,7 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
             wp = wb.p;
         }
         const chem::StartPass sp = chem::start_pass_carve(wp, K + 1, items);
-        if (m->gen)
-            e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, sp, items, stream);
-        else
-            e = chem::launch_bdf_thread(m->view, T, p, Y, ldY, n, dt, prm, status, counters, queue, sp, items,
-                                        stream);
+        e = m->gen->integrate(T, p, Y, ldY, n, dt, prm, status, counters, queue, sp, items, stream);
     }
     return check_hip(e, "integrator launch");
 }
@@ -244,6 +293,7 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
         std::ifstream fb(path, std::ios::binary);
         std::string bytes((std::istreambuf_iterator<char>(fb)), std::istreambuf_iterator<char>());
         const unsigned long long h = fnv1a64(bytes);
+        m->file_hash = h;
         int ng = 0;
         const chem::GenEntry *reg = chem::gen_registry(&ng);
         for (int i = 0; i < ng; i++)
@@ -425,6 +475,14 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
     m->wave.inc = (const int2 *)(blk + off_inc);
     m->wave_scratch = wave_slots > 0 ? (double *)(blk + off_ws) : nullptr;
     m->wave_slots = wave_slots;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->arch = prop.gcnArchName;
+        const std::string::size_type colon = m->arch.find(':');
+        if (colon != std::string::npos) m->arch.resize(colon);
+        if (m->arch.empty()) m->arch = "unknown";
+        chem_host::tune_cache_restore(m);
+    }
     // set-up of the fixed workspace of this device (chem_integrate_noalloc)
     void *fixed = nullptr;
     if ((rc = noalloc_scratch(device, &fixed)) != CHEM_OK) {
@@ -510,7 +568,7 @@ int chem_eval_rhs(chem_mech m, const double *T, const double *p, const double *Y
     if (rc != CHEM_OK || n == 0) return rc;
     if (ldF < n || !is_device_ptr(F)) return fail(CHEM_EINVAL, "F must be a device array with ldF >= ncells");
     if (m->gen) return check_hip(m->gen->rhs(T, p, Y, ldY, n, F, ldF, (hipStream_t)stream), "rhs launch");
-    if (!chem::thread_kernel_supports(m->host.K))
+    if (!chem::table_eval_supports(m->host.K))
         return fail(CHEM_EUNSUP, "no kernel is built for K = " + std::to_string(m->host.K));
     return check_hip(chem::launch_rhs(m->view, T, p, Y, ldY, n, F, ldF, (hipStream_t)stream), "rhs launch");
 }
@@ -522,7 +580,7 @@ int chem_eval_jacobian(chem_mech m, const double *T, const double *p, const doub
     if (rc != CHEM_OK || n == 0) return rc;
     if (ldJ < n || !is_device_ptr(J)) return fail(CHEM_EINVAL, "J must be a device array with ldJ >= ncells");
     if (m->gen) return check_hip(m->gen->jac(T, p, Y, ldY, n, J, ldJ, (hipStream_t)stream), "jacobian launch");
-    if (!chem::thread_kernel_supports(m->host.K))
+    if (!chem::table_eval_supports(m->host.K))
         return fail(CHEM_EUNSUP, "no kernel is built for K = " + std::to_string(m->host.K));
     return check_hip(chem::launch_jacobian(m->view, T, p, Y, ldY, n, J, ldJ, (hipStream_t)stream),
                      "jacobian launch");

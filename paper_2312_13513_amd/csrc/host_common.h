@@ -63,6 +63,12 @@ struct DevBuf {
 
 }  // namespace chem_host
 
+// One autotuned launch configuration.
+struct Tuned {
+    int schedule = -1, jac_batch = 0, waves_per_simd = 0, lpt = 0;
+    double ms = 0.0;
+};
+
 struct chem_mech_s {
     int device = 0;
     chem_file::HostMech host;
@@ -85,12 +91,35 @@ struct chem_mech_s {
     // grows to the largest call made on its stream outside graph capture
     std::map<void *, chem_host::DevBuf> start_ws;
     std::mutex ws_mu;
-    // autotuned schedule per precision (used when opts.schedule == -2)
-    struct Tuned {
-        bool valid = false;
-        int schedule = -1, jac_batch = 0;
-    } tuned[2];
+    // autotuned choices per (precision, size class floor(log2 ncells)), used
+    // when opts.schedule == -2; guarded by ws_mu
+    std::map<std::pair<int, int>, Tuned> tuned;
+    std::vector<chem_tune_entry> tune_results;   // measured table of the last chem_autotune
+    unsigned long long file_hash = 0;            // FNV-1a of the mechanism file
+    std::string arch;                            // GPU architecture name of the device
+    const Tuned *find_tuned(int precision, int cls) const
+    {
+        const Tuned *best = nullptr;
+        int dist = 1 << 30;
+        for (const auto &t : tuned) {
+            if (t.first.first != precision) continue;
+            const int d = t.first.second > cls ? t.first.second - cls : cls - t.first.second;
+            if (d < dist) {
+                dist = d;
+                best = &t.second;
+            }
+        }
+        return best;
+    }
 };
+
+// Size class of a call of n cells (the autotuner's key).
+inline int size_class(int64_t n)
+{
+    int c = 0;
+    while (c < 62 && (int64_t(2) << c) <= n) c++;
+    return c;
+}
 
 namespace chem_host {
 
@@ -105,5 +134,10 @@ int integrate_cells(chem_mech m, double *T, const double *p, double *Y, int64_t 
                     double dt, const chem_opts *opts, int32_t *status, int32_t *counters,
                     hipStream_t stream, const int64_t *n_dev, const int32_t *idx = nullptr,
                     int64_t n_idx = 0, void *fixed_ws = nullptr, size_t fixed_bytes = 0);
+
+// Tuning cache file (CHEM_TUNE_CACHE): append one result, and restore the
+// lines of this mechanism file and architecture into the handle.
+void tune_cache_append(const chem_mech_s *m, int precision, int cls, const Tuned &t);
+void tune_cache_restore(chem_mech_s *m);
 
 }  // namespace chem_host

@@ -111,6 +111,86 @@ def test_autotune_choice_meets_parity(torch, m9, field, om9):
     assert dT < DT_TOL and dY < DY_TOL
 
 
+def _time_opts(torch, mech, T0, p, Y0, dt, o, reps=3):
+    """Best of reps HIP-event timings of one call (state restored each time)."""
+    import torch as t
+    best = 1e30
+    for _ in range(reps):
+        T, Y = T0.clone(), Y0.clone()
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        a.record()
+        mech.integrate(T, p, Y, dt, opts=o)
+        b.record()
+        t.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def test_autotune_picks_the_fastest_at_full_size(torch, m9, mech_dir):
+    """On a 131,072-cell flame field (the default sample is then the whole
+    field) the tuned choice is, within 10 %, the fastest of every candidate
+    configuration timed again at full size; the measured table lists every
+    candidate once."""
+    from chemgen.fields import flame_field
+    from chemgen.mechanism import read_mechanism
+    from paper_2312_13513_amd import chem
+    m = read_mechanism(str(mech_dir / "M9.mech"))
+    f = flame_field(m, (64, 64, 32), seed=44, dt=1e-6, name="flame64x32", mech_name="M9")
+    T, Y, p = _dev(torch, f.T), _dev(torch, f.Y), _dev(torch, f.p)
+    best, lpt, ms = m9.autotune(T, p, Y, f.dt)
+    table = m9.autotune_results()
+    _say(f"[autotune-full] chose schedule {best.schedule} jac_batch {best.jac_batch} waves/SIMD "
+         f"{best.waves_per_simd} lpt {lpt}: {ms:.3f} ms; table {[(e['schedule'], e['jac_batch'], e['lpt'], e['waves_per_simd'], round(e['ms'], 3)) for e in table]}")
+    keys = [(e["schedule"], e["jac_batch"], e["lpt"], e["waves_per_simd"]) for e in table]
+    assert len(keys) == len(set(keys)) and len(keys) == 3 + 8
+    assert min(e["ms"] for e in table) == pytest.approx(ms)
+    times = {}
+    order = torch.empty(f.n, dtype=torch.int32, device="cuda:0")
+    for sched, jb, l, w in keys:
+        if l:
+            continue    # LPT runs need the order of a previous step; natural order suffices here
+        o = chem.chem_default_opts()
+        o.schedule, o.jac_batch, o.waves_per_simd = sched, jb, w
+        times[(sched, jb, w)] = _time_opts(torch, m9, T, p, Y, f.dt, o)
+    _say(f"[autotune-full] full-size times {times}")
+    chosen = times.get((best.schedule, best.jac_batch, best.waves_per_simd))
+    if chosen is not None:
+        assert chosen <= 1.10 * min(times.values())
+
+
+def test_tuned_choice_per_size_class_and_cache_file(torch, mech_dir, field, tmp_path, monkeypatch):
+    """Choices are kept per size class; with CHEM_TUNE_CACHE set they are
+    written to that file and a new handle of the same mechanism file restores
+    them: schedule -2 then runs the tuned schedule (bitwise equal to asking
+    for it explicitly)."""
+    from paper_2312_13513_amd import chem
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("CHEM_TUNE_CACHE", str(cache))
+    f = field
+    a = chem.Mechanism(str(mech_dir / "M9.mech"), 0)
+    n1, n2 = 1000, 3000
+    T, Y, p = _dev(torch, f.T[:n2]), _dev(torch, f.Y[:, :n2]), _dev(torch, f.p[:n2])
+    b1 = a.autotune(T[:n1].contiguous(), p[:n1].contiguous(), Y[:, :n1].contiguous(), f.dt)[0]
+    b2 = a.autotune(T, p, Y, f.dt)[0]
+    a.close()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and all(ln.startswith("chemtune1 gfx") for ln in lines)
+    assert [int(ln.split()[5]) for ln in lines] == [9, 11]
+    b = chem.Mechanism(str(mech_dir / "M9.mech"), 0)
+    for n, bst in ((n1, b1), (n2, b2)):
+        o = chem.chem_default_opts()
+        o.schedule = -2
+        T1, Y1 = _dev(torch, f.T[:n]), _dev(torch, f.Y[:, :n])
+        b.integrate(T1, p[:n].contiguous(), Y1, f.dt, opts=o)
+        o2 = chem.chem_default_opts()
+        o2.schedule = bst.schedule
+        T2, Y2 = _dev(torch, f.T[:n]), _dev(torch, f.Y[:, :n])
+        b.integrate(T2, p[:n].contiguous(), Y2, f.dt, opts=o2)
+        torch.cuda.synchronize()
+        assert torch.equal(T1, T2) and torch.equal(Y1, Y2)
+    b.close()
+
+
 def test_stats_totals_match_the_per_cell_outputs(torch, m9, field):
     """chem_get_stats against numpy sums of the same per-cell arrays, with
     failed cells (a NaN state, a step cap) among them."""

@@ -338,21 +338,19 @@ def test_parity_flame64_sampled(torch, gm9, om9, mech_dir):
 
 
 def test_thread_kernels_match_oracle(torch, gm9, gm9_table, cells4096_run):
-    """The one-thread-per-cell schedule, with the compiled-in mechanism and
-    with the table-driven kernel, on the same cells: parity with the oracle,
-    and the same per-cell step counts from both."""
+    """The one-thread-per-cell schedule of the compiled-in mechanism on a
+    slice of the cells: parity with the oracle.  A table-driven mechanism
+    (byte-different file) has no such kernel: CHEM_EUNSUP, no launch."""
     from paper_2312_13513_amd import chem
     f, g, o = cells4096_run
     sel = np.arange(0, 1024)
     opts = chem.chem_default_opts()
     opts.schedule = 0
-    counts = []
-    for mech, tag in ((gm9, "thread-specialised"), (gm9_table, "thread-table")):
-        Tg, Yg, sg, cg = run_gpu(torch, mech, f.T[sel], f.p[sel], f.Y[:, sel], f.dt, opts=opts)
-        flips = compare(tag, Tg, Yg, sg, cg, o[0][sel], o[1][:, sel], o[2][sel], o[3][sel])
-        assert flips.size <= 2
-        counts.append(cg[:, 0])
-    assert np.mean(counts[0] == counts[1]) >= 0.998
+    Tg, Yg, sg, cg = run_gpu(torch, gm9, f.T[sel], f.p[sel], f.Y[:, sel], f.dt, opts=opts)
+    flips = compare("thread-specialised", Tg, Yg, sg, cg, o[0][sel], o[1][:, sel], o[2][sel], o[3][sel])
+    assert flips.size <= 2
+    with pytest.raises(chem.ChemError, match="compiled-in mechanism"):
+        run_gpu(torch, gm9_table, f.T[sel], f.p[sel], f.Y[:, sel], f.dt, opts=opts)
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 257])

@@ -3,8 +3,8 @@ Lindemann and Troe fall-off, irreversible and duplicate reactions, two NASA-7
 ranges) against the FP64 oracle, through the C ABI: right-hand side and
 Jacobian of the 9-species stand-in of the paper's H2 case (Section 4.1) with
 its compiled-in kernels and with the table-driven ones, its integration on
-every schedule (one thread per cell, compiled-in and table-driven; 16-lane
-tile; 64-lane wave; FP64 and FP32 Jacobian/LU), and the 20-species stand-in
+every schedule (one thread per cell, compiled in; 16-lane tile; 64-lane
+wave; FP64 and FP32 Jacobian/LU), and the 20-species stand-in
 of the CH4 case (Section 4.2) on the wave schedule.  Bars as in the other
 integrator tests: 1e-6 K and 1e-10 in Y for FP64 (cells whose step counts
 flip on round-off held to the oracle's own runs on ulp-perturbed inputs);
@@ -120,7 +120,7 @@ def h2r_cells(h2r):
     return (T, p, Y, dt), om.integrate(T, p, Y, dt)[:4]
 
 
-@pytest.mark.parametrize("which,schedule", [("gen", 0), ("table", 0), ("gen", 2), ("gen", 1), ("gen", -1)])
+@pytest.mark.parametrize("which,schedule", [("gen", 0), ("table", 2), ("table", 1), ("gen", -1)])
 def test_integrate_fp64_every_schedule(torch, h2r, h2r_cells, which, schedule):
     (T, p, Y, dt), o = h2r_cells
     tag = f"H2R-{which}-schedule{schedule}"
