@@ -36,6 +36,35 @@ __device__ __forceinline__ double reg_value(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Reciprocal of a finite nonzero x: the hardware estimate refined by two
+// Newton steps (within an ulp or two of 1/x; the step-control quantities it
+// serves are continuous, and a division costs several times more here).
+__device__ __forceinline__ double rcp_d(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
+// x^(1/k) for x >= 0, k = 1..7, as exp(ln x / k).
+__device__ __forceinline__ double root_k(double x, int k)
+{
+    const double inv = k == 1 ? 1.0 : k == 2 ? 0.5 : k == 3 ? 1.0 / 3.0 : k == 4 ? 0.25
+                     : k == 5 ? 0.2 : k == 6 ? 1.0 / 6.0 : 1.0 / 7.0;
+    return exp(log(x) * inv);
+}
+
+// x^k for k = 1..7 by products.
+__device__ __forceinline__ double pow_k(double x, int k)
+{
+    double r = x;
+#pragma unroll
+    for (int j = 2; j <= 7; j++)
+        if (j <= k) r *= x;
+    return r;
+}
+
 // Compile-time loops: f(std::integral_constant<int, i>) for i in [B, E).  The
 // index is a constant expression in the body, so every array access it makes
 // is static whatever the loop unroller decides (a dynamic index would push
@@ -54,8 +83,10 @@ __device__ __forceinline__ void static_for(F &&f)
 // Factor in place; ties keep the upper row (the pivot is the first row of
 // largest magnitude).  Rows are exchanged by selects on the pivot index; the
 // pivot row of column k is kept in bits 4k..4k+3 of one 64-bit word (N <= 16).
-// Operation order per element as a textbook LU: l = m_rk / m_kk, then
-// m_rc -= l m_kc for c = k+1..N-1.
+// Operation order per element as a textbook LU: l = m_rk (1 / m_kk), then
+// m_rc -= l m_kc for c = k+1..N-1; the diagonal keeps 1 / m_kk for the
+// solve (multiplications in place of divisions, with a reciprocal within an
+// ulp or two).
 template <int N>
 __device__ __forceinline__ bool lu_factor(double *M, unsigned long long &piv)
 {
@@ -93,15 +124,17 @@ __device__ __forceinline__ bool lu_factor(double *M, unsigned long long &piv)
                 });
             }
         }
+        const double rp = rcp_d(M[k * N + k]);
         static_for<k + 1, N>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
-            const double l = M[r * N + k] / M[k * N + k];
+            const double l = M[r * N + k] * rp;
             M[r * N + k] = l;
             static_for<k + 1, N>([&](auto cc) {
                 constexpr int c = decltype(cc)::value;
                 M[r * N + c] -= l * M[k * N + c];
             });
         });
+        M[k * N + k] = rp;
     });
     return ok;
 }
@@ -136,7 +169,7 @@ __device__ __forceinline__ void lu_solve(const double *M, unsigned long long piv
             constexpr int c = decltype(cc)::value;
             b[r] -= M[r * N + c] * b[c];
         });
-        b[r] /= M[r * N + r];
+        b[r] *= M[r * N + r];
     });
 }
 
@@ -282,17 +315,20 @@ __device__ __forceinline__ void nord_rescale(LaneState<N> &S, double eta)
     }
 }
 
-// Step coefficients from the history: xi_i = (h + tau_1 + ... + tau_{i-1}) / h,
-// l = coefficients of prod_{i=1..q} (1 + x / xi_i).
+// Step coefficients from the history: xi_i = (h + tau_1 + ... + tau_{i-1}) / h
+// and its reciprocal rxi_i, l = coefficients of prod_{i=1..q} (1 + x / xi_i).
 template <int N>
-__device__ __forceinline__ void step_coeffs(const LaneState<N> &S, double *xi, double *l)
+__device__ __forceinline__ void step_coeffs(const LaneState<N> &S, double *xi, double *rxi, double *l)
 {
+    const double invh = rcp_d(S.h);
     double s = S.h;
     xi[1] = 1.0;
+    rxi[1] = 1.0;
 #pragma unroll
     for (int i = 2; i <= kQmax + 1; i++) {
         s += S.tau[i - 1];
-        xi[i] = s / S.h;
+        xi[i] = s * invh;
+        rxi[i] = S.h * rcp_d(s);
     }
     l[0] = 1.0;
 #pragma unroll
@@ -301,7 +337,7 @@ __device__ __forceinline__ void step_coeffs(const LaneState<N> &S, double *xi, d
     for (int i = 1; i <= kQmax; i++)
         if (i <= S.q)
 #pragma unroll
-            for (int j = i; j >= 1; j--) l[j] += l[j - 1] / xi[i];
+            for (int j = i; j >= 1; j--) l[j] += l[j - 1] * rxi[i];
 }
 
 // xi_{q+1} = (h + tau_1 + ... + tau_q) / h, summed with the order as a guard
@@ -313,7 +349,7 @@ __device__ __forceinline__ double xi_q1(const LaneState<N> &S)
 #pragma unroll
     for (int i = 1; i <= kQmax; i++)
         if (i <= S.q) s += S.tau[i];
-    return s / S.h;
+    return s * rcp_d(S.h);
 }
 
 struct CellIO {
@@ -394,11 +430,11 @@ __device__ __forceinline__ void begin_attempt(LaneState<N> &S, const CellIO &io)
         return;
     }
     nord_predict(S);
-    double xi[kQmax + 2], l[kQmax + 1];
-    step_coeffs(S, xi, l);
-    S.gamma = S.h / l[1];
-    S.inv_l1 = 1.0 / l[1];
-    S.Cq = 1.0 / (1.0 + l[1] * xi_q1(S));
+    double xi[kQmax + 2], rxi[kQmax + 2], l[kQmax + 1];
+    step_coeffs(S, xi, rxi, l);
+    S.inv_l1 = rcp_d(l[1]);
+    S.gamma = S.h * S.inv_l1;
+    S.Cq = rcp_d(1.0 + l[1] * xi_q1(S));
     S.jcur = false;
     S.need_J = !S.have_M || S.force_M || S.nst >= S.nst_M + bdf::kMsbp ||
                fabs(S.gamma / S.gamma_M - 1.0) > bdf::kDgmax;
@@ -421,7 +457,7 @@ __device__ __forceinline__ void begin_step(LaneState<N> &S, const CellIO &io)
         S.last = true;
     }
 #pragma unroll
-    for (int i = 0; i < N; i++) S.z(kWeightRow, i) = 1.0 / (io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
+    for (int i = 0; i < N; i++) S.z(kWeightRow, i) = rcp_d(io.prm->rtol * fabs(S.z(0, i)) + io.prm->atol);
     S.nef = 0;
     S.ncf = 0;
     S.force_M = false;
@@ -472,23 +508,23 @@ __device__ __forceinline__ void select_next(LaneState<N> &S, int qmax)
     using namespace bdf;
     const int q = S.q;
     const double h_done = S.h;
-    double xi[kQmax + 2], l[kQmax + 1];
-    step_coeffs(S, xi, l);
+    double xi[kQmax + 2], rxi[kQmax + 2], l[kQmax + 1];
+    step_coeffs(S, xi, rxi, l);
     double prod_q = 1.0;
 #pragma unroll
     for (int i = 1; i <= kQmax; i++)
         if (i <= q) prod_q *= xi[i];
     const double x1 = xi_q1(S);
-    const double gfac = prod_q * (1.0 / l[1] + x1) / factorial_d(q + 1);
+    const double rgfac = factorial_d(q + 1) * rcp_d(prod_q * (S.inv_l1 + x1));
     double ehat_new[N];
 #pragma unroll
-    for (int i = 0; i < N; i++) ehat_new[i] = S.e[i] / gfac;
+    for (int i = 0; i < N; i++) ehat_new[i] = S.e[i] * rgfac;
     if (S.qwait > 0) S.qwait--;
     const double etamax = (S.nef > 0 || S.ncf > 0) ? 1.0 : (S.nst == 1 ? kEtaMaxFirst : kEtaMax);
     double eta = 1.0;
     int qnew = q;
     if (etamax > 1.0) {
-        eta = 1.0 / (pow(kBiasQ * S.dsm, 1.0 / (q + 1)) + kAddon);
+        eta = rcp_d(root_k(kBiasQ * S.dsm, q + 1) + kAddon);
         if (S.qwait == 0) {
             double eta_m = 0.0, eta_p = 0.0;
             if (q > 1) {
@@ -504,13 +540,13 @@ __device__ __forceinline__ void select_next(LaneState<N> &S, int qmax)
                 for (int i = 1; i < kQmax; i++)
                     if (i <= q - 1) {
                         prod *= xi[i];
-                        l1 += 1.0 / xi[i];
+                        l1 += rxi[i];
                     }
-                const double Em = wrms_norm<N>(zq, S.z) * prod / l1;
-                eta_m = 1.0 / (pow(kBiasQm1 * Em, 1.0 / q) + kAddon);
+                const double Em = wrms_norm<N>(zq, S.z) * prod * rcp_d(l1);
+                eta_m = rcp_d(root_k(kBiasQm1 * Em, q) + kAddon);
             }
             if (q < qmax && S.ehat_ok) {
-                const double rr = pow(h_done / S.ehat_h, q + 1);
+                const double rr = pow_k(h_done * rcp_d(S.ehat_h), q + 1);
                 double dv[N];
 #pragma unroll
                 for (int i = 0; i < N; i++) dv[i] = ehat_new[i] - S.z(kEhatRow, i) * rr;
@@ -519,10 +555,10 @@ __device__ __forceinline__ void select_next(LaneState<N> &S, int qmax)
                 for (int i = 1; i <= kQmax; i++)
                     if (i <= q + 1) {
                         prod *= xi[i];
-                        l1 += 1.0 / xi[i];
+                        l1 += rxi[i];
                     }
-                const double Ep = wrms_norm<N>(dv, S.z) * prod / (factorial_d(q + 2) * l1);
-                eta_p = 1.0 / (pow(kBiasQp1 * Ep, 1.0 / (q + 2)) + kAddon);
+                const double Ep = wrms_norm<N>(dv, S.z) * prod * rcp_d(factorial_d(q + 2) * l1);
+                eta_p = rcp_d(root_k(kBiasQp1 * Ep, q + 2) + kAddon);
             }
             if (eta_m > eta && eta_m >= eta_p) {
                 eta = eta_m;
@@ -569,7 +605,7 @@ __device__ __forceinline__ void select_next(LaneState<N> &S, int qmax)
         S.ehat_ok = false;
     } else if (qnew == q + 1) {
         // add e * (x / xi_{q+1}) * Lambda_q(x)
-        const double inv = 1.0 / x1;
+        const double inv = rcp_d(x1);
 #pragma unroll
         for (int j = 2; j <= kQmax; j++)
             if (j == q + 1)
@@ -618,7 +654,7 @@ __device__ __forceinline__ void error_test(LaneState<N> &S, const CellIO &io)
             S.phase = RESTART;   // needs f(z0)
             return;
         }
-        double eta = 1.0 / (pow(kBiasQ * S.dsm, 1.0 / (S.q + 1)) + kAddon);
+        double eta = rcp_d(root_k(kBiasQ * S.dsm, S.q + 1) + kAddon);
         eta = fmin(fmax(eta, kEtaMinEf), kEtaMaxEf);
         if (S.nef >= 2) eta = fmin(eta, kEtaNef2);
         nord_rescale(S, eta);
@@ -627,8 +663,8 @@ __device__ __forceinline__ void error_test(LaneState<N> &S, const CellIO &io)
         return;
     }
     {
-        double xi[kQmax + 2], l[kQmax + 1];
-        step_coeffs(S, xi, l);
+        double xi[kQmax + 2], rxi[kQmax + 2], l[kQmax + 1];
+        step_coeffs(S, xi, rxi, l);
 #pragma unroll
         for (int j = 0; j <= kQmax; j++)
             if (j <= S.q)
@@ -873,7 +909,7 @@ __device__ void run_lanes(const Mech &mech, const CellIO &io, double t_end,
                     d[i] = -((first ? 0.0 : S.e[i]) - S.gamma * S.fy[i] + S.z(1, i) * inv_l1);
                 lu_solve<N>(S.M, S.piv, d);
                 if (S.gamma != S.gamma_M) {
-                    const double s = 2.0 / (1.0 + S.gamma / S.gamma_M);
+                    const double s = 2.0 * rcp_d(1.0 + S.gamma * rcp_d(S.gamma_M));
 #pragma unroll
                     for (int i = 0; i < N; i++) d[i] *= s;
                 }
