@@ -170,14 +170,20 @@ constexpr int kMlpRB = kMlpRows / 16;
 constexpr int kMlpPad = 8;   // bf16 pad per LDS row: spreads the 16 rows of an A fragment over banks
 constexpr int kMlpDepth = 2; // K steps of weight fragments loaded ahead
 
-template <int J>
+// KS > 0: the layer has KS K steps, known at compile time, and the step
+// loop is unrolled completely (one straight block, so the waits on the
+// weight loads count the loads in flight instead of draining them at a loop
+// head); KS = 0: any K.
+template <int J, int KS = 0>
 __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, const bf16_t *__restrict__ Wf, int N,
                                           const float *__restrict__ bias, bf16_t *outs, int lds_out,
                                           float *outg, int64_t ldg, int64_t r0, int64_t rows)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wave index is uniform: as a scalar, the block guards below are
+    // scalar branches
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int kk = (lane >> 4) * 8;
-    const int nblk = N >> 4, ksteps = K >> 5;
+    const int nblk = N >> 4, ksteps = KS > 0 ? KS : K >> 5;
     floatx4 acc[J][kMlpRB];
 #pragma unroll
     for (int j = 0; j < J; j++)
@@ -190,20 +196,28 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
         wfr[j] = Wf + (int64_t)(jb < nblk ? jb : 0) * ksteps * 512 + lane * 8;
     }
     const bf16_t *arow = in + (lane & 15) * ldi + kk;
-    // weight fragments of the next kMlpDepth K steps are in flight while the
-    // current step's products run (one register slot per step, the loop
-    // unrolled by the depth so that every slot index is static)
-    bf16x8 bq[kMlpDepth][J];
+    // weight fragments of the next D K steps are in flight while the current
+    // step's products run (one register slot per step, the loop unrolled by
+    // the depth so that every slot index is static; four steps ahead when the
+    // step count is known, else kMlpDepth).  A wave whose column block j lies
+    // past the layer (only when N is not a multiple of 64) loads and
+    // multiplies block 0 in its place and drops the result: no branch around
+    // the loads, so the loop body is one block and each step waits only for
+    // its own fragments.
+    constexpr int D = KS > 0 ? (KS < 4 ? KS : 4) : kMlpDepth;
+    bf16x8 bq[D][J];
 #pragma unroll
-    for (int d = 0; d < kMlpDepth; d++)
+    for (int d = 0; d < D; d++)
 #pragma unroll
         for (int j = 0; j < J; j++)
-            if (d < ksteps && w + kMlpWaves * j < nblk) __builtin_memcpy(&bq[d][j], wfr[j] + d * 512, 16);
-    for (int s0 = 0; s0 < ksteps; s0 += kMlpDepth) {
+            if (d < ksteps) __builtin_memcpy(&bq[d][j], wfr[j] + d * 512, 16);
+    // ksteps is a multiple of D (KS: by the shapes of mlp_layer_any; else
+    // mlp_fused_supported)
+#pragma unroll(KS > 0 ? KS / D : 1)
+    for (int s0 = 0; s0 < ksteps; s0 += D) {
 #pragma unroll
-        for (int d = 0; d < kMlpDepth; d++) {
+        for (int d = 0; d < D; d++) {
             const int ks = s0 + d;
-            if (ks >= ksteps) break;
             bf16x8 a[kMlpRB];
 #pragma unroll
             for (int i = 0; i < kMlpRB; i++) __builtin_memcpy(&a[i], arow + i * 16 * ldi + ks * 32, 16);
@@ -212,14 +226,14 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
             // each lane's four results are adjacent in a row of the output
 #pragma unroll
             for (int j = 0; j < J; j++)
-                if (w + kMlpWaves * j < nblk)
 #pragma unroll
-                    for (int i = 0; i < kMlpRB; i++)
-                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[d][j], a[i], acc[j][i], 0, 0, 0);
-            const int kn = ks + kMlpDepth;
+                for (int i = 0; i < kMlpRB; i++)
+                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[d][j], a[i], acc[j][i], 0, 0, 0);
+            // the last steps reload the last fragment (unused) instead of
+            // branching around the load
+            const int kn = ks + D < ksteps ? ks + D : ksteps - 1;
 #pragma unroll
-            for (int j = 0; j < J; j++)
-                if (kn < ksteps && w + kMlpWaves * j < nblk) __builtin_memcpy(&bq[d][j], wfr[j] + kn * 512, 16);
+            for (int j = 0; j < J; j++) __builtin_memcpy(&bq[d][j], wfr[j] + kn * 512, 16);
         }
     }
 #pragma unroll
@@ -249,19 +263,32 @@ __device__ __forceinline__ void mlp_layer(const bf16_t *in, int ldi, int K, cons
     }
 }
 
-// one layer with the register budget of its width
+// one layer with the register budget of its width; the shapes of the
+// default network (64 -> 512 -> 256 -> 128 -> 48 padded) with their K steps
+// fixed at compile time
 __device__ __forceinline__ void mlp_layer_any(const bf16_t *in, int ldi, int K, const bf16_t *Wf, int N,
                                               const float *bias, bf16_t *outs, int lds_out, float *outg,
                                               int64_t ldg, int64_t r0, int64_t rows)
 {
-    if (N <= 64)
+#define CHEM_MLP_LAYER(JJ, KK)                                                                     \
+    if (K == KK) {                                                                                 \
+        mlp_layer<JJ, KK / 32>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);       \
+        return;                                                                                    \
+    }
+    if (N <= 64) {
+        CHEM_MLP_LAYER(1, 128)
         mlp_layer<1>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
-    else if (N <= 128)
+    } else if (N <= 128) {
+        CHEM_MLP_LAYER(2, 256)
         mlp_layer<2>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
-    else if (N <= 256)
+    } else if (N <= 256) {
+        CHEM_MLP_LAYER(4, 512)
         mlp_layer<4>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
-    else
+    } else {
+        CHEM_MLP_LAYER(kMlpJ, 64)
         mlp_layer<kMlpJ>(in, ldi, K, Wf, N, bias, outs, lds_out, outg, ldg, r0, rows);
+    }
+#undef CHEM_MLP_LAYER
 }
 
 // Weights [N][K] -> fragment order (see above), 8 values per thread.
@@ -753,6 +780,9 @@ bool mlp_fused_supported(const int out_l[4])
 {
     for (int l = 0; l < 4; l++)
         if (out_l[l] > kMlpMaxN || out_l[l] % 16 != 0) return false;
+    // every layer's K (64, then the hidden widths) in whole prefetch groups
+    for (int l = 0; l < 3; l++)
+        if (out_l[l] % (32 * kMlpDepth) != 0) return false;
     int dev = 0, max_lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
