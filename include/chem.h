@@ -424,6 +424,57 @@ int chem_surrogate_save_checkpoint(chem_surr surr, const char *path, const void 
 int chem_surrogate_load(chem_mech mech, const char *path, chem_surr *out);
 int chem_surrogate_checkpoint_user(const char *path, void *user, int64_t capacity, int64_t *user_bytes);
 
+/* ------------------------------------------------------------------------ */
+/* Implicit finite-volume Laplacian: ldu assembly and CSR conversion          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct chem_ldu_s *chem_ldu;
+
+/* A mesh in owner/neighbour (ldu) addressing (Section 3.1, the ldu/CSR
+ * figure), copied to `device` from host arrays the caller keeps:
+ * internal faces in upper-triangular order (0 <= owner[f] < neighbour[f] <
+ * ncells; sorted by owner, then neighbour), with the owner weight of linear
+ * interpolation, the inverse distance of the two cell centres delta and the
+ * face area mag_sf; boundary faces grouped by patch, patch p holding faces
+ * patch_start[p] .. patch_start[p+1]-1 (patch_start[0] = 0) of type
+ * patch_type[p] (0 fixed value, 1 zero gradient), with the cell next to each
+ * face, the inverse centre-to-face distance bdelta and the area bmag_sf.
+ * The CSR pattern is built here: row i holds the columns of the faces
+ * whose neighbour is i (increasing), i itself, then the faces whose owner
+ * is i (increasing); ncells + 2 nfaces < 2^31.  CHEM_EINVAL on arrays that
+ * break these rules.  Allocates; synchronous. */
+int chem_ldu_create(int64_t ncells, int64_t nfaces, const int32_t *owner, const int32_t *neighbour,
+                    const double *weight, const double *delta, const double *mag_sf, int32_t npatches,
+                    const int64_t *patch_start, const int32_t *patch_type, const int32_t *face_cells,
+                    const double *bdelta, const double *bmag_sf, int device, chem_ldu *out);
+void chem_free_ldu(chem_ldu mesh);
+/* dims[0..3] = ncells, nfaces, boundary faces, CSR entries. */
+int chem_ldu_info(chem_ldu mesh, int64_t *dims);
+/* Algorithm 1 of Section 3.1, the implicit discretisation of
+ * div(gamma grad psi): per internal face gamma_f = w gamma_c[owner] +
+ * (1 - w) gamma_c[neighbour], upper[f] = lower[f] = gamma_f delta_f |S_f|,
+ * diag (ncells) = -(sum of the coefficients of the cell's faces), accumulated
+ * with atomics (so its last bits depend on the order of the additions);
+ * then one launch per boundary patch: fixed value internal[b] =
+ * -gamma_b[b] |S_b| delta_b, boundary[b] = gamma_b[b] |S_b| delta_b psi_b[b];
+ * zero gradient 0 and 0.  The operator is L(psi) = A psi + r with A the ldu
+ * matrix with the internal coefficients added to the diagonal and r the
+ * boundary coefficients summed per cell.  All arrays device memory; enqueued
+ * on the stream; allocates nothing. */
+int chem_ldu_laplacian(chem_ldu mesh, const double *gamma_c, const double *gamma_b, const double *psi_b,
+                       double *lower, double *upper, double *diag, double *internal, double *boundary,
+                       void *hip_stream);
+/* The ldu matrix in CSR (the ldu/CSR figure): csr_val (CSR entries, in the
+ * pattern of chem_ldu_create) and rhs (ncells) = r, the boundary's internal
+ * coefficients added to the diagonal entries in boundary-face order
+ * (deterministic).  Device arrays; enqueued on the stream; allocates
+ * nothing. */
+int chem_ldu_to_csr(chem_ldu mesh, const double *lower, const double *upper, const double *diag,
+                    const double *internal, const double *boundary, double *csr_val, double *rhs,
+                    void *hip_stream);
+/* Copies the CSR pattern: row_ptr (ncells + 1) and col (CSR entries), device. */
+int chem_ldu_csr_pattern(chem_ldu mesh, int32_t *row_ptr, int32_t *col, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,14 @@ def _load():
     L.chem_autotune.argtypes = [vp, dp, dp, dp, i64, i64, C.c_double, C.POINTER(chem_opts), C.c_int32,
                                 C.POINTER(chem_opts), i32p, C.POINTER(C.c_double), vp]
     L.chem_autotune_results.argtypes = [vp, C.POINTER(chem_tune_entry), C.c_int32, i32p]
+    L.chem_ldu_create.argtypes = [i64, i64, vp, vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, vp, C.c_int,
+                                  C.POINTER(vp)]
+    L.chem_free_ldu.argtypes = [vp]
+    L.chem_free_ldu.restype = None
+    L.chem_ldu_info.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.chem_ldu_laplacian.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
+    L.chem_ldu_to_csr.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
+    L.chem_ldu_csr_pattern.argtypes = [vp, dp, dp, vp]
     fp, dblp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int64)
     ckp = C.POINTER(chem_surr_checks)
     L.chem_surrogate_default_checks.argtypes = [ckp]
@@ -126,7 +134,8 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_reserve",
             "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace", "chem_integrate_noalloc",
             "chem_surrogate_train_part", "chem_surrogate_save_checkpoint", "chem_surrogate_checkpoint_user",
-            "chem_autotune_results")
+            "chem_autotune_results", "chem_ldu_create", "chem_free_ldu", "chem_ldu_info", "chem_ldu_laplacian",
+            "chem_ldu_to_csr", "chem_ldu_csr_pattern")
 
 
 def lib():
@@ -460,3 +469,51 @@ class Surrogate:
                                               float(lr0), float(lr1), losses.ctypes.data_as(C.POINTER(C.c_double)),
                                               _stream(stream)))
         return losses
+
+
+# --------------------------------------------------------------------------- finite-volume Laplacian
+
+class LduMesh:
+    """Owning wrapper of a chem_ldu mesh (built from host numpy arrays, e.g.
+    chemgen.mesh.BoxMesh)."""
+
+    def __init__(self, mesh, device: int = 0):
+        import numpy as np
+        a = {k: np.ascontiguousarray(getattr(mesh, k), dtype=t) for k, t in
+             (("owner", np.int32), ("neighbour", np.int32), ("weight", np.float64), ("delta", np.float64),
+              ("mag_sf", np.float64), ("patch_start", np.int64), ("patch_type", np.int32),
+              ("face_cells", np.int32), ("bdelta", np.float64), ("bmag_sf", np.float64))}
+        self._keep = a
+        h = C.c_void_p()
+        _check(_lib.chem_ldu_create(int(mesh.ncells), int(a["owner"].size), *(a[k].ctypes.data for k in
+                                    ("owner", "neighbour", "weight", "delta", "mag_sf")),
+                                    int(a["patch_type"].size), a["patch_start"].ctypes.data,
+                                    a["patch_type"].ctypes.data, a["face_cells"].ctypes.data, a["bdelta"].ctypes.data,
+                                    a["bmag_sf"].ctypes.data, int(device), C.byref(h)))
+        self.handle = h.value
+        dims = (C.c_int64 * 4)()
+        _check(_lib.chem_ldu_info(C.c_void_p(self.handle), dims))
+        self.ncells, self.nfaces, self.nbfaces, self.nnz = (int(v) for v in dims)
+
+    def close(self):
+        if self.handle:
+            _lib.chem_free_ldu(C.c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def laplacian(self, gamma_c, gamma_b, psi_b, lower, upper, diag, internal, boundary, stream=None):
+        _check(_lib.chem_ldu_laplacian(C.c_void_p(self.handle), _ptr(gamma_c), _ptr(gamma_b), _ptr(psi_b),
+                                       _ptr(lower), _ptr(upper), _ptr(diag), _ptr(internal), _ptr(boundary),
+                                       _stream(stream)))
+
+    def to_csr(self, lower, upper, diag, internal, boundary, csr_val, rhs, stream=None):
+        _check(_lib.chem_ldu_to_csr(C.c_void_p(self.handle), _ptr(lower), _ptr(upper), _ptr(diag), _ptr(internal),
+                                    _ptr(boundary), _ptr(csr_val), _ptr(rhs), _stream(stream)))
+
+    def csr_pattern(self, row_ptr, col, stream=None):
+        _check(_lib.chem_ldu_csr_pattern(C.c_void_p(self.handle), _ptr(row_ptr), _ptr(col), _stream(stream)))
