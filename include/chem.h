@@ -472,6 +472,15 @@ int chem_ldu_laplacian(chem_ldu mesh, const double *gamma_c, const double *gamma
 int chem_ldu_to_csr(chem_ldu mesh, const double *lower, const double *upper, const double *diag,
                     const double *internal, const double *boundary, double *csr_val, double *rhs,
                     void *hip_stream);
+/* The same matrix and right-hand side assembled straight into CSR, with no
+ * ldu arrays and no atomics: each internal face writes gamma_f delta_f
+ * |S_f| to its two off-diagonal places, then each cell's diagonal is minus
+ * the sum of its row's off-diagonal entries (in column order) plus its
+ * boundary faces' internal coefficients, and rhs its boundary coefficients
+ * (deterministic: the same bits every call).  Device arrays; enqueued on the
+ * stream; allocates nothing. */
+int chem_ldu_laplacian_csr(chem_ldu mesh, const double *gamma_c, const double *gamma_b, const double *psi_b,
+                           double *csr_val, double *rhs, void *hip_stream);
 /* Copies the CSR pattern: row_ptr (ncells + 1) and col (CSR entries), device. */
 int chem_ldu_csr_pattern(chem_ldu mesh, int32_t *row_ptr, int32_t *col, void *hip_stream);
 

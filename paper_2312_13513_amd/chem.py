@@ -83,6 +83,7 @@ def _load():
     L.chem_ldu_laplacian.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
     L.chem_ldu_to_csr.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
     L.chem_ldu_csr_pattern.argtypes = [vp, dp, dp, vp]
+    L.chem_ldu_laplacian_csr.argtypes = [vp, dp, dp, dp, dp, dp, vp]
     fp, dblp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int64)
     ckp = C.POINTER(chem_surr_checks)
     L.chem_surrogate_default_checks.argtypes = [ckp]
@@ -135,7 +136,7 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace", "chem_integrate_noalloc",
             "chem_surrogate_train_part", "chem_surrogate_save_checkpoint", "chem_surrogate_checkpoint_user",
             "chem_autotune_results", "chem_ldu_create", "chem_free_ldu", "chem_ldu_info", "chem_ldu_laplacian",
-            "chem_ldu_to_csr", "chem_ldu_csr_pattern")
+            "chem_ldu_to_csr", "chem_ldu_csr_pattern", "chem_ldu_laplacian_csr")
 
 
 def lib():
@@ -514,6 +515,10 @@ class LduMesh:
     def to_csr(self, lower, upper, diag, internal, boundary, csr_val, rhs, stream=None):
         _check(_lib.chem_ldu_to_csr(C.c_void_p(self.handle), _ptr(lower), _ptr(upper), _ptr(diag), _ptr(internal),
                                     _ptr(boundary), _ptr(csr_val), _ptr(rhs), _stream(stream)))
+
+    def laplacian_csr(self, gamma_c, gamma_b, psi_b, csr_val, rhs, stream=None):
+        _check(_lib.chem_ldu_laplacian_csr(C.c_void_p(self.handle), _ptr(gamma_c), _ptr(gamma_b), _ptr(psi_b),
+                                           _ptr(csr_val), _ptr(rhs), _stream(stream)))
 
     def csr_pattern(self, row_ptr, col, stream=None):
         _check(_lib.chem_ldu_csr_pattern(C.c_void_p(self.handle), _ptr(row_ptr), _ptr(col), _stream(stream)))

@@ -1,7 +1,10 @@
 // Implicit finite-volume Laplacian on the GPU: assembly of the ldu matrix
 // with atomic accumulation of the diagonal (paper Section 3.1, Algorithm 1)
 // and its conversion to CSR (the ldu/CSR figure), for meshes in
-// owner/neighbour addressing.  Both are HBM-bound: one thread per face or
+// owner/neighbour addressing; and the same matrix assembled straight into
+// CSR without atomics (each face writes its two entries, each cell sums its
+// row), which on a GPU of several dies with their own L2 avoids the atomic
+// traffic between them.  Both are HBM-bound: one thread per face or
 // per cell, face arrays read once in face order (coalesced), the diagonal
 // accumulated with FP64 atomics that stay in L2.  The CSR pattern and the
 // position of every ldu coefficient in it are built once per mesh on the
@@ -30,6 +33,7 @@ struct chem_ldu_s {
     const double *weight = nullptr, *delta = nullptr, *mag_sf = nullptr, *bdelta = nullptr, *bmag_sf = nullptr;
     const int32_t *upper_pos = nullptr, *lower_pos = nullptr, *diag_pos = nullptr;
     const int32_t *bnd_ptr = nullptr, *bnd_face = nullptr, *row_ptr = nullptr, *col = nullptr;
+    const int32_t *btype = nullptr;   // patch type of every boundary face
 };
 
 namespace chem {
@@ -45,6 +49,18 @@ __global__ void __launch_bounds__(kLduBlock) ldu_zero_kernel(double *__restrict_
     if (i < n) v[i] = 0.0;
 }
 
+// The coefficient of an internal face: gamma_f by linear interpolation,
+// times delta_f |S_f|.
+__device__ __forceinline__ double face_coeff(int64_t f, const int32_t *__restrict__ owner,
+                                             const int32_t *__restrict__ neighbour, const double *__restrict__ weight,
+                                             const double *__restrict__ delta, const double *__restrict__ mag_sf,
+                                             const double *__restrict__ gamma_c)
+{
+    const double w = weight[f];
+    const double gf = w * gamma_c[owner[f]] + (1.0 - w) * gamma_c[neighbour[f]];
+    return gf * delta[f] * mag_sf[f];
+}
+
 // Internal faces (Algorithm 1, internal field): gamma_f by linear
 // interpolation, upper = lower = gamma_f delta_f |S_f|, and the diagonal of
 // both cells of the face accumulated by atomics.
@@ -56,14 +72,55 @@ __global__ void __launch_bounds__(kLduBlock) ldu_internal_kernel(
 {
     const int64_t f = (int64_t)blockIdx.x * kLduBlock + threadIdx.x;
     if (f >= nfaces) return;
-    const int o = owner[f], n = neighbour[f];
-    const double w = weight[f];
-    const double gf = w * gamma_c[o] + (1.0 - w) * gamma_c[n];
-    const double c = gf * delta[f] * mag_sf[f];
+    const double c = face_coeff(f, owner, neighbour, weight, delta, mag_sf, gamma_c);
     upper[f] = c;
     lower[f] = c;
-    atomicAdd(&diag[o], -c);
-    atomicAdd(&diag[n], -c);
+    atomicAdd(&diag[owner[f]], -c);
+    atomicAdd(&diag[neighbour[f]], -c);
+}
+
+// Assembly straight into CSR, without atomics: each face writes its
+// coefficient to both places it has in the rows ...
+__global__ void __launch_bounds__(kLduBlock) csr_assemble_faces_kernel(
+    int64_t nfaces, const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
+    const double *__restrict__ weight, const double *__restrict__ delta, const double *__restrict__ mag_sf,
+    const double *__restrict__ gamma_c, const int32_t *__restrict__ upper_pos, const int32_t *__restrict__ lower_pos,
+    double *__restrict__ val)
+{
+    const int64_t f = (int64_t)blockIdx.x * kLduBlock + threadIdx.x;
+    if (f >= nfaces) return;
+    const double c = face_coeff(f, owner, neighbour, weight, delta, mag_sf, gamma_c);
+    val[upper_pos[f]] = c;
+    val[lower_pos[f]] = c;
+}
+
+// ... then each cell sums its row's off-diagonal entries (contiguous, in
+// column order: the same sum every call) into the diagonal and adds its
+// boundary faces (fixed value: -gamma_b |S_b| delta_b to the diagonal,
+// gamma_b |S_b| delta_b psi_b to the right-hand side; zero gradient nothing).
+__global__ void __launch_bounds__(kLduBlock) csr_assemble_cells_kernel(
+    int64_t ncells, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ diag_pos,
+    const int32_t *__restrict__ bnd_ptr, const int32_t *__restrict__ bnd_face, const int32_t *__restrict__ btype,
+    const double *__restrict__ bdelta, const double *__restrict__ bmag_sf, const double *__restrict__ gamma_b,
+    const double *__restrict__ psi_b, double *__restrict__ val, double *__restrict__ rhs)
+{
+    const int64_t i = (int64_t)blockIdx.x * kLduBlock + threadIdx.x;
+    if (i >= ncells) return;
+    const int dp = diag_pos[i];
+    double s = 0.0;
+    for (int j = row_ptr[i]; j < row_ptr[i + 1]; j++)
+        if (j != dp) s += val[j];
+    double d = -s, r = 0.0;
+    for (int j = bnd_ptr[i]; j < bnd_ptr[i + 1]; j++) {
+        const int b = bnd_face[j];
+        if (btype[b] == 0) {
+            const double c = gamma_b[b] * bmag_sf[b] * bdelta[b];
+            d += -c;
+            r += c * psi_b[b];
+        }
+    }
+    val[dp] = d;
+    rhs[i] = r;
 }
 
 // One boundary patch (Algorithm 1, boundary loop: a launch per patch, the
@@ -207,6 +264,9 @@ int chem_ldu_create(int64_t ncells, int64_t nfaces, const int32_t *owner, const 
         upos[f] = row_ptr[o] + nlo[o] + 1 + ufill[o]++;
         col[upos[f]] = neighbour[f];
     }
+    std::vector<int32_t> btype(nb);
+    for (int32_t p = 0; p < npatches; p++)
+        for (int64_t b = patch_start[p]; b < patch_start[p + 1]; b++) btype[b] = patch_type[p];
     // boundary faces grouped by cell, faces increasing
     std::vector<int32_t> bptr(ncells + 1, 0), bface(nb);
     for (int64_t b = 0; b < nb; b++) bptr[face_cells[b] + 1]++;
@@ -235,7 +295,8 @@ int chem_ldu_create(int64_t ncells, int64_t nfaces, const int32_t *owner, const 
         {bdelta, (size_t)nb * 8, 0},          {bmag_sf, (size_t)nb * 8, 0},       {upos.data(), (size_t)nfaces * 4, 0},
         {lpos.data(), (size_t)nfaces * 4, 0}, {dpos.data(), (size_t)ncells * 4, 0},
         {bptr.data(), (size_t)(ncells + 1) * 4, 0}, {bface.data(), (size_t)nb * 4, 0},
-        {row_ptr.data(), (size_t)(ncells + 1) * 4, 0}, {col.data(), (size_t)nnz * 4, 0}};
+        {row_ptr.data(), (size_t)(ncells + 1) * 4, 0}, {col.data(), (size_t)nnz * 4, 0},
+        {btype.data(), (size_t)nb * 4, 0}};
     size_t total = 0;
     for (auto &p : parts) {
         p.off = total;
@@ -274,6 +335,7 @@ int chem_ldu_create(int64_t ncells, int64_t nfaces, const int32_t *owner, const 
     m->bnd_face = (const int32_t *)(base + parts[k++].off);
     m->row_ptr = (const int32_t *)(base + parts[k++].off);
     m->col = (const int32_t *)(base + parts[k++].off);
+    m->btype = (const int32_t *)(base + parts[k++].off);
     *out = m;
     return CHEM_OK;
 }
@@ -344,6 +406,24 @@ int chem_ldu_to_csr(chem_ldu m, const double *lower, const double *upper, const 
     hipLaunchKernelGGL(chem::csr_cells_kernel, dim3(chem::ldu_blocks(m->ncells)), dim3(chem::kLduBlock), 0, st,
                        m->ncells, m->diag_pos, m->bnd_ptr, m->bnd_face, diag, internal, boundary, csr_val, rhs);
     return check_hip(hipGetLastError(), "csr launch");
+}
+
+int chem_ldu_laplacian_csr(chem_ldu m, const double *gamma_c, const double *gamma_b, const double *psi_b,
+                           double *csr_val, double *rhs, void *stream)
+{
+    int rc = check_ldu(m);
+    if (rc != CHEM_OK) return rc;
+    if (!all_dev({gamma_c, csr_val, rhs}) || (m->nbfaces && !all_dev({gamma_b, psi_b})))
+        return fail(CHEM_EINVAL, "arrays must be device pointers");
+    hipStream_t st = (hipStream_t)stream;
+    if (m->nfaces)
+        hipLaunchKernelGGL(chem::csr_assemble_faces_kernel, dim3(chem::ldu_blocks(m->nfaces)), dim3(chem::kLduBlock),
+                           0, st, m->nfaces, m->owner, m->neighbour, m->weight, m->delta, m->mag_sf, gamma_c,
+                           m->upper_pos, m->lower_pos, csr_val);
+    hipLaunchKernelGGL(chem::csr_assemble_cells_kernel, dim3(chem::ldu_blocks(m->ncells)), dim3(chem::kLduBlock), 0,
+                       st, m->ncells, m->row_ptr, m->diag_pos, m->bnd_ptr, m->bnd_face, m->btype, m->bdelta,
+                       m->bmag_sf, gamma_b, psi_b, csr_val, rhs);
+    return check_hip(hipGetLastError(), "csr assembly launch");
 }
 
 int chem_ldu_csr_pattern(chem_ldu m, int32_t *row_ptr, int32_t *col, void *stream)

@@ -1,6 +1,7 @@
 """GPU parity of the implicit Laplacian assembly (Section 3.1, Algorithm 1)
-and of the ldu -> CSR conversion, through the C ABI, against the numpy
-oracle on the same seeded meshes and fields.
+and of the ldu -> CSR conversion, and of the direct CSR assembly (no
+atomics, deterministic), through the C ABI, against the numpy oracle on the
+same seeded meshes and fields.
 
 Bars: the CSR pattern is integer data and must be equal.  upper and lower
 are five or six roundings (u = 2^-53) on each side, fused differently
@@ -40,10 +41,15 @@ def _run(torch, m, seed):
     rp = torch.zeros(m.ncells + 1, dtype=torch.int32, device=dev)
     col = torch.zeros(g.nnz, dtype=torch.int32, device=dev)
     g.csr_pattern(rp, col)
+    # the direct CSR assembly, twice (no atomics: the same bits both times)
+    val2, rhs2, val3, rhs3 = z(g.nnz), z(m.ncells), z(g.nnz), z(m.ncells)
+    g.laplacian_csr(t(gc), t(gb), t(pb), val2, rhs2)
+    g.laplacian_csr(t(gc), t(gb), t(pb), val3, rhs3)
     torch.cuda.synchronize()
+    assert torch.equal(val2, val3) and torch.equal(rhs2, rhs3)
     out = {k: v.cpu().numpy() for k, v in (("lower", lo), ("upper", up), ("diag", dg), ("internal", ic),
                                             ("boundary", bc), ("val", val), ("rhs", rhs), ("row_ptr", rp),
-                                            ("col", col))}
+                                            ("col", col), ("val_direct", val2), ("rhs_direct", rhs2))}
     out["lower"], out["upper"] = out["lower"][:m.nfaces], out["upper"][:m.nfaces]
     out["internal"], out["boundary"] = out["internal"][:m.nbfaces], out["boundary"][:m.nbfaces]
     g.close()
@@ -77,7 +83,17 @@ def _compare(tag, m, fields, out):
                   np.maximum(np.abs(val[~diag_entry]), 1e-300), initial=0.0) <= 1.5e-15
     dscale = gross + np.abs(val[diag_entry])
     assert np.max(np.abs(out["val"][diag_entry] - val[diag_entry]) / np.maximum(dscale, 1e-300)) <= 2.5e-15
-    assert np.max(np.abs(out["rhs"] - rhs) / np.maximum(np.abs(rhs), 1e-300)) <= 2.5e-15
+    # rhs: a sum of up to three boundary terms of either sign, measured
+    # against the sum of their magnitudes
+    rgross = np.zeros(m.ncells)
+    np.add.at(rgross, m.face_cells.astype(np.int64), np.abs(bc))
+    assert np.max(np.abs(out["rhs"] - rhs) / np.maximum(rgross, 1e-300)) <= 2.5e-15
+    # direct CSR assembly: off-diagonals are the same face coefficients as
+    # the ldu path (bitwise), diagonal and rhs within the same bars
+    vd = out["val_direct"]
+    assert np.array_equal(vd[~diag_entry], out["val"][~diag_entry])
+    assert np.max(np.abs(vd[diag_entry] - val[diag_entry]) / np.maximum(dscale, 1e-300)) <= 2.5e-15
+    assert np.max(np.abs(out["rhs_direct"] - rhs) / np.maximum(rgross, 1e-300)) <= 2.5e-15
 
 
 @pytest.mark.parametrize("shape,grading", [((13, 9, 7), (2.0, 0.5, 1.3)), ((1, 1, 1), (1.0, 1.0, 1.0)),
