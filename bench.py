@@ -28,6 +28,10 @@ Other workloads (``--workload``):
              FP64 residuals and state, wave-per-cell schedule;
   laplacian128  implicit Laplacian assembly (Algorithm 1) + ldu -> CSR
              conversion on a graded 128^3 box (HBM roofline);
+  props_tgv  the Thermo field kernels on one GPU's share of the 256^3 TGV
+             mesh (256x128x128 = 4,194,304 cells, 9 species): T from h by
+             Newton from the previous step's T, then mixture-averaged
+             viscosity, conductivity and diffusion coefficients;
   surrogate  the learned surrogate with per-cell fallback on the 256x128x128
              flame field (4,194,304 cells, 35 species, dt = 1e-5): training
              states labelled by the GPU integrator, training on the GPU, then
@@ -694,13 +698,146 @@ def run_laplacian(args):
     return result
 
 
+def props_flops(K: int) -> dict:
+    """Algorithmic FP64 flops per cell of the property kernels (add, mul,
+    div = 1, fused multiply-add = 2, log and sqrt = 20), from the
+    definitions:
+      transport  composition 5K + 2; per species the two ln T quartics
+                 (8 each), T^(1/4) |P|, 1/s_k, T^(1/2) Q, X/lam and the two
+                 sums (25 K); Wilke 7 K^2 (t = 1 + s_k c1 / s_j, t^2 c2,
+                 X_j times it) plus 5 K; the K(K-1)/2 diffusion pairs
+                 13 each (quartic, reciprocal, two products into the sums)
+                 plus 8 K; log T and two square roots 60
+      T from h   per Newton step 22 K + 10 (cp and h quartics, a6/T, the
+                 sums, the step and the clamp), plus K for Y R / W."""
+    pairs = K * (K - 1) // 2
+    return {"transport": 7 * K * K + 13 * pairs + 38 * K + 62, "newton_step": 22 * K + 10, "newton_setup": K}
+
+
+def run_props(args):
+    """The Thermo field kernels on the TGV share: one step = restore the
+    previous step's temperature (a device copy, timed), T from h by Newton
+    (chem_T_from_h, cp out), then the transport properties at the new T
+    (chem_transport_field: mu, lam and D).  h is the mixture enthalpy at the
+    field's T (chem_mixture_h_cp, outside the timed region)."""
+    import torch
+
+    from chemgen.fields import newton_guess, seeded_sample, tgv_share
+    from chemgen.transport import transport_fits
+    from paper_2312_13513_amd import chem
+
+    mech_obj, path = mech_file("M9")
+    f = tgv_share(mech_obj)
+    n, K = f.n, mech_obj.K
+    fits = transport_fits(mech_obj, 9)
+    guess = newton_guess(f.T, 12)
+    m = chem.Mechanism(path)
+    m.set_transport(*fits)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    Td, pd, Yd, Tg = t(f.T), t(f.p), t(f.Y), t(guess)
+    h = torch.empty(n, dtype=torch.float64, device=dev)
+    m.mixture_h_cp(Td, Yd, h, None)
+    T = torch.empty_like(h)
+    cp, mu, lam = torch.empty_like(h), torch.empty_like(h), torch.empty_like(h)
+    D = torch.empty((K, n), dtype=torch.float64, device=dev)
+    its = torch.empty(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        T.copy_(Tg)
+        if ev is not None:
+            ev[0].record(stream)
+        m.T_from_h(h, Yd, T, cp, None, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        m.transport(T, pd, Yd, mu, lam, D, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    progress(f"props_tgv: {n} cells, K = {K}")
+    for _ in range(args.warmup):
+        step()
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    newton_s = float(np.mean([a.elapsed_time(b) for a, b, _ in evs])) * 1e-3
+    trans_s = float(np.mean([b.elapsed_time(c) for _, b, c in evs])) * 1e-3
+    # Newton steps taken (a separate call with the counts, outside the timing)
+    T.copy_(Tg)
+    m.T_from_h(h, Yd, T, None, its, stream=stream)
+    torch.cuda.synchronize()
+    steps_mean = float(its.double().mean().item())
+    fl = props_flops(K)
+    flops_tr = fl["transport"] * n
+    flops_nw = (fl["newton_step"] * steps_mean + fl["newton_setup"]) * n
+    bytes_tr = n * 8 * (K + 2) * 2            # T, p, Y in; mu, lam, D out
+    bytes_nw = n * 8 * (K + 4)                # h, T, Y in; T, cp out
+    peak_f = FP64_PEAK_TFLOPS * 1e12
+
+    def roof(flops, nbytes, secs, kernel):
+        t_hbm, t_alu = nbytes / 8e12, flops / peak_f
+        if t_hbm >= t_alu:
+            return {"bound": "hbm", "achieved": nbytes / secs / 1e9, "peak": 8000.0, "unit": "GB/s",
+                    "frac": nbytes / secs / 8e12, "traffic": traffic_for("props_tgv", kernel), "kernel": kernel,
+                    "kernel_ms": secs * 1e3, "bytes_per_launch": nbytes, "flops_per_launch": flops,
+                    "fp64_frac": flops / secs / peak_f}
+        return {"bound": "alu", "achieved": flops / secs / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": flops / secs / peak_f, "traffic": traffic_for("props_tgv", kernel), "kernel": kernel,
+                "kernel_ms": secs * 1e3, "bytes_per_launch": nbytes, "flops_per_launch": flops,
+                "hbm_frac": nbytes / secs / 8e12}
+
+    km = 12 if K <= 12 else 16
+    r_tr = roof(flops_tr, bytes_tr, trans_s, f"transport_kernel<{km}, true, 3>")
+    r_nw = roof(flops_nw, bytes_nw, newton_s, f"t_from_h_kernel<{km}>")
+    dominant = r_tr if trans_s >= newton_s else r_nw
+    result = {
+        "metric": "thermo/transport field properties (T from h, mu, lambda, D), cells/s",
+        "value": n * args.steps / wall, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "props_tgv: 256x128x128 = 4,194,304-cell flame field (one GPU's share of the "
+                               "256^3 TGV mesh on four GPUs), 9 species, Newton from T + U(-20, 20) K, seeded "
+                               "Lennard-Jones transport fits", "ncells": n, "species": K},
+        "roofline": dominant,
+        "kernels": {"t_from_h": r_nw, "transport": r_tr},
+        "newton_steps_mean": steps_mean,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import OracleMech
+        from oracle import transport as TR
+        om = OracleMech(path)
+        ns = args.cpu_sample or 1000000
+        idx = seeded_sample(n, ns, 17)
+        Ys, Ts, ps = f.Y[:, idx], f.T[idx], f.p[idx]
+        h_s = h.cpu().numpy()[idx]
+        t1 = time.perf_counter()
+        T_o, cp_o, _ = TR.thermo_field(om, h_s, Ys, guess[idx])
+        mu_o, lam_o, D_o = TR.transport(*fits, mech_obj.molar_masses(), T_o, ps, Ys)
+        cpu = time.perf_counter() - t1
+        result["cpu_baseline"] = {"value": idx.size / cpu, "unit": "cells/s", "cores": 1, "kind": "oracle",
+                                  "cpu": cpu_model(), "sample": f"{idx.size} seeded cells of the field, one pass, "
+                                                                f"{cpu:.2f} s (C Newton per cell, numpy transport, "
+                                                                "one thread)"}
+        Tgpu = T.cpu().numpy()[idx]
+        result["max_abs_dT_vs_oracle"] = float(np.max(np.abs(Tgpu - T_o)))
+        result["max_rel_dmu_vs_oracle"] = float(np.max(np.abs(mu.cpu().numpy()[idx] / mu_o - 1)))
+        result["max_rel_dD_vs_oracle"] = float(np.max(np.abs(D.cpu().numpy()[:, idx] / D_o - 1)))
+    m.close()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="flame64",
-                    choices=("flame64", "cells4096", "zones128", "surrogate", "laplacian128"))
+                    choices=("flame64", "cells4096", "zones128", "surrogate", "laplacian128", "props_tgv"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", type=int, default=None, choices=(-2, -1, 0, 1, 2),
                     help="integrator workloads: -2 autotuned (flame64 default), -1 library choice, 0 thread, "
@@ -755,6 +892,8 @@ def main():
         result = run_surrogate(args)
     elif args.workload == "laplacian128":
         result = run_laplacian(args)
+    elif args.workload == "props_tgv":
+        result = run_props(args)
     else:
         result = run_integrator(args, args.workload)
         if args.workload == "flame64" and not args.no_surrogate:

@@ -10,6 +10,10 @@ Each workload is a batch of CFD cells advanced over one flow step dt:
   thin flame front, 30 % burnt (uneven stiffness), dt = 1e-5 s.
 * ``flame256x128x128`` / ``flame256`` - 35-species flame fields of 4.2M and
   16.8M cells (the TGV mesh of Section 4.1 is 256^3), dt = 1e-5 s.
+* ``tgv_share``   - 256 x 128 x 128 = 4,194,304 cells of the 9-species
+  mechanism: one GPU's quarter of the 256^3 TGV mesh run on four GPUs
+  (Section 4.1), a smooth flame field; the workload of the property
+  kernels, with ``newton_guess`` standing in for the previous step's T.
 
 Arrays use the structure-of-arrays layout of the library: ``Y`` has shape
 (K, n), one contiguous row per species.  Nothing here evaluates a rate.
@@ -136,6 +140,16 @@ def flame256x128x128(mech: Optional[Mechanism] = None, seed: int = 104) -> Field
 def flame256(mech: Optional[Mechanism] = None, seed: int = 105) -> Field:
     return flame_field(mech or standard_mechanism("M35"), (256, 256, 256), seed, 1e-5, "flame256", "M35",
                        mix_seed=7)
+
+
+def tgv_share(mech: Optional[Mechanism] = None, seed: int = 106) -> Field:
+    return flame_field(mech or standard_mechanism("M9"), (256, 128, 128), seed, 1e-6, "tgv_share", "M9")
+
+
+def newton_guess(T: np.ndarray, seed: int, spread: float = 20.0) -> np.ndarray:
+    """T plus a seeded uniform offset in [-spread, spread] K: the previous
+    flow step's temperature as the start of the enthalpy Newton."""
+    return T + np.random.default_rng(seed).uniform(-spread, spread, T.shape[0])
 
 
 def subset(field: Field, idx: np.ndarray, name_suffix: str = "_sub") -> Field:

@@ -484,6 +484,47 @@ int chem_ldu_laplacian_csr(chem_ldu mesh, const double *gamma_c, const double *g
 /* Copies the CSR pattern: row_ptr (ncells + 1) and col (CSR entries), device. */
 int chem_ldu_csr_pattern(chem_ldu mesh, int32_t *row_ptr, int32_t *col, void *hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Thermophysical and transport properties over a field                     */
+/* ------------------------------------------------------------------------ */
+
+/* The thermo part of the Thermo class of Section 3.1: mass-specific
+ * enthalpy h (J/kg) and cp (J/(kg K)) of every cell's mixture from the
+ * NASA-7 polynomials at its temperature T (K); Y[k*ldY + i] as in
+ * chem_integrate.  h or cp may be NULL.  Device arrays; enqueued on the
+ * stream; allocates nothing.  K <= 64 (CHEM_EUNSUP otherwise). */
+int chem_mixture_h_cp(chem_mech mech, const double *T, const double *Y, int64_t ldY, int64_t ncells,
+                      double *h, double *cp, void *hip_stream);
+/* Temperature from mass-specific enthalpy by Newton's method on the
+ * temperature polynomials (Section 3.1): from the guess in T, every step
+ * T <- min(max(T - (h(T) - h) / cp(T), 200), 3500) K until a step is below
+ * tol (K); T then holds the result, cp (if not NULL) the mixture cp there
+ * and iters (if not NULL) the steps taken.  A cell that has not converged
+ * after max_iter steps (1 .. 1000) gets T = cp = NaN and iters = max_iter + 1
+ * (a per-cell result, not a call error).  Y is used as given (no clipping).
+ * Device arrays; enqueued on the stream; allocates nothing. */
+int chem_T_from_h(chem_mech mech, const double *h, const double *Y, int64_t ldY, int64_t ncells, double *T,
+                  double *cp, int32_t *iters, int32_t max_iter, double tol, void *hip_stream);
+/* Transport data of the mechanism's species (host arrays, copied; lowest
+ * power first): visc (K x 5) with mu_k = (T^(1/4) P_k(ln T))^2 in Pa s,
+ * cond (K x 5) with lam_k = T^(1/2) Q_k(ln T) in W/(m K), and diff
+ * (K x K x 5, symmetric in the species pair, diagonal = self-diffusion)
+ * with D_jk = T^(3/2) B_jk(ln T) / p in m^2/s.  CHEM_EINVAL on non-finite or
+ * asymmetric fits.  Allocates and synchronises; replaces earlier data, so it
+ * must not run while transport calls on this mechanism are in flight. */
+int chem_set_transport(chem_mech mech, const double *visc, const double *cond, const double *diff);
+/* Mixture-averaged transport properties (the molecular transport model of
+ * Section 2; compute-bound kernels of Section 3.2) of every cell at T (K),
+ * p (Pa) and mass fractions Y, after y_k = max(Y_k, 0) / sum_j max(Y_j, 0):
+ * mu (Pa s) by Wilke's rule, lam (W/(m K)) as the mean of the mole-fraction
+ * weighted arithmetic and harmonic means of the species values, and
+ * D[k*ldD + i] (m^2/s) = (1 - y_k) / sum_{j != k} X_j / D_jk (D_kk for a
+ * pure species).  mu and lam are given together or both NULL; D may be NULL
+ * (then p may be NULL too); not all NULL.  Needs chem_set_transport.  Device
+ * arrays; enqueued on the stream; allocates nothing; K <= 64. */
+int chem_transport_field(chem_mech mech, const double *T, const double *p, const double *Y, int64_t ldY,
+                         int64_t ncells, double *mu, double *lam, double *D, int64_t ldD, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

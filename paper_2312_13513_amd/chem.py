@@ -84,6 +84,10 @@ def _load():
     L.chem_ldu_to_csr.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
     L.chem_ldu_csr_pattern.argtypes = [vp, dp, dp, vp]
     L.chem_ldu_laplacian_csr.argtypes = [vp, dp, dp, dp, dp, dp, vp]
+    L.chem_mixture_h_cp.argtypes = [vp, dp, dp, i64, i64, dp, dp, vp]
+    L.chem_T_from_h.argtypes = [vp, dp, dp, i64, i64, dp, dp, dp, C.c_int32, C.c_double, vp]
+    L.chem_set_transport.argtypes = [vp, dp, dp, dp]
+    L.chem_transport_field.argtypes = [vp, dp, dp, dp, i64, i64, dp, dp, dp, i64, vp]
     fp, dblp, i64p = C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int64)
     ckp = C.POINTER(chem_surr_checks)
     L.chem_surrogate_default_checks.argtypes = [ckp]
@@ -136,7 +140,8 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace", "chem_integrate_noalloc",
             "chem_surrogate_train_part", "chem_surrogate_save_checkpoint", "chem_surrogate_checkpoint_user",
             "chem_autotune_results", "chem_ldu_create", "chem_free_ldu", "chem_ldu_info", "chem_ldu_laplacian",
-            "chem_ldu_to_csr", "chem_ldu_csr_pattern", "chem_ldu_laplacian_csr")
+            "chem_ldu_to_csr", "chem_ldu_csr_pattern", "chem_ldu_laplacian_csr", "chem_mixture_h_cp",
+            "chem_T_from_h", "chem_set_transport", "chem_transport_field")
 
 
 def lib():
@@ -280,6 +285,36 @@ class Mechanism:
 
     def jacobian(self, T, p, Y, J, stream=None):
         chem_eval_jacobian(self.handle, T, p, Y, J, stream)
+
+    # -- field properties (the Thermo class) --------------------------------
+    def mixture_h_cp(self, T, Y, h=None, cp=None, stream=None, ncells=None):
+        """h, cp (n,) float64 GPU tensors (either may be None) of the mixtures Y at T."""
+        n = T.shape[0] if ncells is None else int(ncells)
+        _check(_lib.chem_mixture_h_cp(C.c_void_p(self.handle), _ptr(T), _ptr(Y), Y.shape[1], n, _ptr(h),
+                                      _ptr(cp), _stream(stream)))
+
+    def T_from_h(self, h, Y, T, cp=None, iters=None, max_iter: int = 20, tol: float = 1e-10, stream=None,
+                 ncells=None):
+        """T (n,) in: Newton guess, out: temperature with mixture enthalpy h."""
+        n = h.shape[0] if ncells is None else int(ncells)
+        _check(_lib.chem_T_from_h(C.c_void_p(self.handle), _ptr(h), _ptr(Y), Y.shape[1], n, _ptr(T), _ptr(cp),
+                                  _ptr(iters), int(max_iter), float(tol), _stream(stream)))
+
+    def set_transport(self, visc, cond, diff):
+        """Species transport fits (numpy, lowest power first): visc (K, 5),
+        cond (K, 5), diff (K, K, 5)."""
+        import numpy as np
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in (visc, cond, diff)]
+        if a[0].shape != (self.K, 5) or a[1].shape != (self.K, 5) or a[2].shape != (self.K, self.K, 5):
+            raise ValueError("transport fits must be (K, 5), (K, 5) and (K, K, 5)")
+        _check(_lib.chem_set_transport(C.c_void_p(self.handle), *(x.ctypes.data for x in a)))
+
+    def transport(self, T, p, Y, mu=None, lam=None, D=None, stream=None, ncells=None):
+        """Mixture viscosity, conductivity (n,) and diffusion coefficients D (K, ldD)."""
+        n = T.shape[0] if ncells is None else int(ncells)
+        _check(_lib.chem_transport_field(C.c_void_p(self.handle), _ptr(T), _ptr(p), _ptr(Y), Y.shape[1], n,
+                                         _ptr(mu), _ptr(lam), _ptr(D), D.shape[1] if D is not None else 0,
+                                         _stream(stream)))
 
 
 def chem_lpt_order(cost, order, stream=None) -> None:

@@ -496,11 +496,12 @@ int chem_load_mechanism(const char *path, int device, chem_mech *out)
 void chem_free_mechanism(chem_mech m)
 {
     if (!m) return;
-    if (m->dev_block) {
+    if (m->dev_block || m->transport_block) {
         int prev = 0;
         hipGetDevice(&prev);
         hipSetDevice(m->device);
-        hipFree(m->dev_block);
+        if (m->dev_block) hipFree(m->dev_block);
+        if (m->transport_block) hipFree(m->transport_block);
         for (auto &w : m->start_ws) w.second.release();
         hipSetDevice(prev);
     }

@@ -97,6 +97,7 @@ struct chem_mech_s {
     std::vector<chem_tune_entry> tune_results;   // measured table of the last chem_autotune
     unsigned long long file_hash = 0;            // FNV-1a of the mechanism file
     std::string arch;                            // GPU architecture name of the device
+    void *transport_block = nullptr;             // mixture-averaged transport tables (chem_set_transport)
     const Tuned *find_tuned(int precision, int cls) const
     {
         const Tuned *best = nullptr;

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "chem.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(chem_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(chem_[A-Za-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_path():
