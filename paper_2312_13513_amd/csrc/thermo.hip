@@ -68,9 +68,29 @@ __device__ __forceinline__ double rcp_t(double x)
     return r;
 }
 
-__device__ __forceinline__ double poly5(const double *c, double x)
+// Powers of ln T shared by every fit of a cell.
+struct LnPow {
+    double x, x2, x3, x4;
+};
+
+__device__ __forceinline__ LnPow ln_powers(double x)
 {
-    return fma(fma(fma(fma(c[4], x, c[3]), x, c[2]), x, c[1]), x, c[0]);
+    const double x2 = x * x;
+    return {x, x2, x2 * x, x2 * x2};
+}
+
+// c0 + c1 x + c2 x^2 + c3 x^3 + c4 x^4 with uniform (scalar) coefficients:
+// every step multiplies a scalar by a per-cell power into a vector
+// accumulator, one instruction each.  (Horner's rule would add a scalar to
+// a product and costs a register move per step on this target, which takes
+// one scalar operand per instruction.)
+__device__ __forceinline__ double poly5(const double *c, const LnPow &p)
+{
+    double q = c[1] * p.x;
+    q = fma(c[2], p.x2, q);
+    q = fma(c[3], p.x3, q);
+    q = fma(c[4], p.x4, q);
+    return q + c[0];
 }
 
 // Call f(k) for k = 0 .. K-1: unrolled over KM when UO, else a run-time loop.
@@ -100,6 +120,8 @@ __device__ __forceinline__ void load_rows(const double *__restrict__ Y, int64_t 
         if (k >= K) y[k] = 0.0;
 }
 
+// yr_k = Y_k / W_k: the mixture sums below are in units of R (mass-specific
+// h / R and cp / R); R enters once per cell, not once per species.
 template <int KM>
 __device__ __forceinline__ void load_yr(const double *__restrict__ Y, int64_t ldY, int64_t i, int K,
                                         const double *__restrict__ invW, double (&yr)[KM])
@@ -107,7 +129,7 @@ __device__ __forceinline__ void load_yr(const double *__restrict__ Y, int64_t ld
     load_rows<KM>(Y, ldY, i, K, yr);
 #pragma unroll
     for (int k = 0; k < KM; k++)
-        if (k < K) yr[k] *= kRu * invW[k];
+        if (k < K) yr[k] *= invW[k];
 }
 
 // MODE bit 1: viscosity and conductivity; bit 2: diffusion coefficients.
@@ -127,7 +149,7 @@ __global__ void __launch_bounds__(kThermoBlock) transport_kernel(TrView v, const
     if (i >= n) return;
     const int K = v.K;
     const double Tc = T[i];
-    const double lnT = log(Tc);
+    const LnPow lnT = ln_powers(log(Tc));
     const double sT = sqrt(Tc);
 
     // composition: y_k = max(Y_k, 0) / sum, X_k = (y_k / W_k) / sum_j (y_j / W_j);
@@ -272,7 +294,7 @@ __device__ __forceinline__ unsigned mid_pattern(const MidSet &ms, double T)
 }
 
 // Mixture polynomial coefficients at T (computation consolidation): with
-// yr_k = Y_k R / W_k and each species' range at T,
+// yr_k = Y_k / W_k and each species' range at T, in units of R,
 //   cp  = sum_c M[c] T^c                                 (c = 0..4)
 //   h   = T (M[0] + sum_c M[4+c] T^c) + M[9]             (c = 1..4)
 // where M[0..4] = sum_k yr_k a1..a5, M[5..8] = sum_k yr_k a2/2..a5/5 and
@@ -295,16 +317,16 @@ __device__ __forceinline__ void mix_coeffs(const double *species, int K, const d
             const double *s = species + k * kSpeciesLen;
             const double *lo = s + 1, *hi = s + 1 + kRangeLen;
             const bool low = T < s[0];
-            if (__all(low)) {
+            // each lane's weight is zero in the other range; a range no lane
+            // of the wave is in is skipped (a uniform branch)
+            const double wl = low ? yr[k] : 0.0, wh = low ? 0.0 : yr[k];
+            if (__any(low)) {
 #pragma unroll
-                for (int c = 0; c < 10; c++) M[c] = fma(yr[k], lo[src[c]], M[c]);
-            } else if (!__any(low)) {
+                for (int c = 0; c < 10; c++) M[c] = fma(wl, lo[src[c]], M[c]);
+            }
+            if (!__all(low)) {
 #pragma unroll
-                for (int c = 0; c < 10; c++) M[c] = fma(yr[k], hi[src[c]], M[c]);
-            } else {
-                const double wl = low ? yr[k] : 0.0, wh = low ? 0.0 : yr[k];
-#pragma unroll
-                for (int c = 0; c < 10; c++) M[c] = fma(wl, lo[src[c]], fma(wh, hi[src[c]], M[c]));
+                for (int c = 0; c < 10; c++) M[c] = fma(wh, hi[src[c]], M[c]);
             }
         }
 }
@@ -333,8 +355,8 @@ __global__ void __launch_bounds__(kThermoBlock) h_cp_kernel(const double *__rest
     load_yr<KM>(Y, ldY, i, K, invW, yr);
     const double Tc = T[i];
     mix_coeffs<KM>(species, K, yr, Tc, M);
-    if (h) h[i] = mix_h(M, Tc);
-    if (cp) cp[i] = mix_cp(M, Tc);
+    if (h) h[i] = kRu * mix_h(M, Tc);
+    if (cp) cp[i] = kRu * mix_cp(M, Tc);
 }
 
 // Temperature from mixture enthalpy: Newton from the guess in T, each step
@@ -356,7 +378,7 @@ __global__ void __launch_bounds__(kThermoBlock) t_from_h_kernel(const double *__
     if (i >= n) return;
     double yr[KM], M[10];
     load_yr<KM>(Y, ldY, i, K, invW, yr);
-    const double h0 = h[i];
+    const double h0 = h[i] * (1.0 / kRu);
     double Tc = T[i];
     unsigned pat = mid_pattern(ms, Tc);
     int it = 0;
@@ -375,7 +397,7 @@ __global__ void __launch_bounds__(kThermoBlock) t_from_h_kernel(const double *__
         done = fabs(dT) < tol;
     }
     T[i] = done ? Tc : __builtin_nan("");
-    if (cp) cp[i] = done ? mix_cp(M, Tc) : __builtin_nan("");
+    if (cp) cp[i] = done ? kRu * mix_cp(M, Tc) : __builtin_nan("");
     if (iters) iters[i] = done ? it : max_iter + 1;
 }
 
