@@ -71,6 +71,25 @@ def network_dims(K: int, h1: int = 512, h2: int = 256, h3: int = 128):
     return [(K + 2, h1), (h1, h2), (h2, h3), (h3, K)]
 
 
+def species_network_dims(K: int, h1: int = 1600, h2: int = 800, h3: int = 400):
+    """Layer shapes of one network of the per-species variant (a single output)."""
+    return [(K + 2, h1), (h1, h2), (h2, h3), (h3, 1)]
+
+
+def init_species_params(K: int, h, seed: int) -> np.ndarray:
+    """Initial weights of K per-species networks (each as init_params, seeds
+    seed, seed + 1, ...), concatenated network by network."""
+    dims = species_network_dims(K, *h)
+    return np.concatenate([init_params(dims, seed + g) for g in range(K)])
+
+
+def split_species_params(flat: np.ndarray, K: int, h):
+    """The (W, b) lists of the K per-species networks of a flat vector."""
+    dims = species_network_dims(K, *h)
+    per = sum(a * b + b for a, b in dims)
+    return [split_params(flat[g * per:(g + 1) * per], dims) for g in range(K)]
+
+
 def epoch_orders(n: int, epochs: int, seed: int) -> np.ndarray:
     """A seeded permutation of 0..n-1 per epoch, concatenated (int32)."""
     rng = np.random.default_rng(seed)

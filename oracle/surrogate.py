@@ -14,7 +14,9 @@ the flow step):
 * MLP: h1 = gelu(x W1^T + b1), h2 = gelu(h1 W2^T + b2), h3 = gelu(h2 W3^T + b3),
   out = h3 W4^T + b4, gelu(u) = u (1 + erf(u/sqrt 2)) / 2 (exact form);
 * decode: dY = mu_y + sigma_y * out, Y_new = Y + dY;
-* loss: mean squared error on the z-scored outputs; Adam with bias correction.
+* loss: mean squared error on the z-scored outputs; Adam with bias correction;
+* the per-species variant: one such network per species with a single
+  output each, all fed the same input (forward_species, backward_species).
 
 Weights use the (out, in) layout.
 """
@@ -71,6 +73,31 @@ def forward(params: List[Tuple[np.ndarray, np.ndarray]], x):
         h = gelu(u) if li < len(params) - 1 else u
         acts.append(h)
     return h, (acts, pres)
+
+
+def forward_species(nets, x):
+    """The paper's per-species variant (Section 2: one network per species,
+    each with its own hidden layers and a single output): nets[g] is species
+    g's (W, b) list; output column g is its prediction.  Returns (out,
+    caches)."""
+    outs, caches = [], []
+    for params in nets:
+        o, c = forward(params, x)
+        outs.append(o)
+        caches.append(c)
+    return np.concatenate(outs, axis=1), caches
+
+
+def backward_species(nets, caches, out, target):
+    """Gradients of mse_loss over all n x G outputs of forward_species: each
+    network's own single-output gradient, divided by G (the mean runs over G
+    times as many values)."""
+    G = len(nets)
+    res = []
+    for g, params in enumerate(nets):
+        gr = backward(params, caches[g], out[:, g:g + 1], target[:, g:g + 1])
+        res.append([(gW / G, gb / G) for gW, gb in gr])
+    return res
 
 
 def mse_loss(out, target):

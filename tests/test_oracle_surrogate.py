@@ -232,3 +232,80 @@ def test_apply_checks_fail_and_keep_input(om35, m35, bad):
         checks = {"dT_gate": 1e-6}
     ok, Tn, Yn = S.apply_cell(om35, m35.counts, W, T, Y, dY, np.zeros(K), np.ones(K), checks)
     assert not ok and Tn == T and np.array_equal(Yn, Y)
+
+
+def _species_nets(rng, nin, h, G):
+    return [_net(rng, [nin, *h, 1]) for _ in range(G)]
+
+
+def test_species_networks_are_one_block_diagonal_network():
+    """G single-output networks on a shared input equal one dense network
+    whose first layer stacks their first layers and whose later layers are
+    block diagonal (each species' block, zeros between): a structural pin of
+    forward_species and backward_species through the single-network oracle,
+    itself pinned against torch above."""
+    rng = np.random.default_rng(71)
+    nin, h, G, n = 7, (5, 4, 3), 4, 11
+    nets = _species_nets(rng, nin, h, G)
+    dense = []
+    for li in range(4):
+        Ws = [net[li][0] for net in nets]
+        bs = [net[li][1] for net in nets]
+        if li == 0:
+            W = np.vstack(Ws)
+        else:
+            W = np.zeros((sum(w.shape[0] for w in Ws), sum(w.shape[1] for w in Ws)))
+            r = c = 0
+            for w in Ws:
+                W[r:r + w.shape[0], c:c + w.shape[1]] = w
+                r += w.shape[0]
+                c += w.shape[1]
+        dense.append((W, np.concatenate(bs)))
+    x = rng.normal(0, 1, (n, nin))
+    tgt = rng.normal(0, 1, (n, G))
+    out_s, caches = S.forward_species(nets, x)
+    out_d, cache_d = S.forward(dense, x)
+    assert np.allclose(out_s, out_d, rtol=1e-13, atol=1e-14)
+    gs = S.backward_species(nets, caches, out_s, tgt)
+    gd = S.backward(dense, cache_d, out_d, tgt)
+    for g in range(G):
+        # the dense gradient's diagonal blocks are the species networks' gradients
+        r0 = [g * hh for hh in (*h, 1)]
+        c0 = [0] + [g * hh for hh in h]
+        for li, size_o in enumerate((*h, 1)):
+            size_i = nin if li == 0 else h[li - 1]
+            blk = gd[li][0][r0[li]:r0[li] + size_o, c0[li]:c0[li] + size_i]
+            assert np.allclose(gs[g][li][0], blk, rtol=1e-12, atol=1e-15)
+            assert np.allclose(gs[g][li][1], gd[li][1][r0[li]:r0[li] + size_o], rtol=1e-12, atol=1e-15)
+
+
+def test_species_backward_finite_differences():
+    """Central differences of the mean squared error over all n x G outputs
+    against backward_species, on weights and biases of every layer of two of
+    the networks (the 1/G factor of the mean included)."""
+    rng = np.random.default_rng(72)
+    nin, h, G, n = 5, (4, 3, 3), 3, 6
+    nets = _species_nets(rng, nin, h, G)
+    x = rng.normal(0, 1, (n, nin))
+    tgt = rng.normal(0, 1, (n, G))
+    out, caches = S.forward_species(nets, x)
+    grads = S.backward_species(nets, caches, out, tgt)
+
+    def loss():
+        return S.mse_loss(S.forward_species(nets, x)[0], tgt)
+
+    eps = 1e-6
+    for g in (0, 2):
+        for li in range(4):
+            for which in (0, 1):
+                P = nets[g][li][which]
+                idx = tuple(rng.integers(0, d) for d in P.shape)
+                keep = P[idx]
+                P[idx] = keep + eps
+                lp = loss()
+                P[idx] = keep - eps
+                lm = loss()
+                P[idx] = keep
+                fd = (lp - lm) / (2 * eps)
+                an = grads[g][li][which][idx]
+                assert abs(fd - an) <= 1e-7 + 1e-5 * abs(fd), (g, li, which, fd, an)
