@@ -298,6 +298,21 @@ int chem_surrogate_default_checks(chem_surr_checks *checks);
 /* New surrogate for mech (Section 2's network, hidden widths h1, h2, h3)
  * with zero parameters and unset normalisation. */
 int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out);
+/* The paper's per-species variant (Section 2: one network per species, each
+ * with its own hidden layers h1, h2, h3 (the paper's are 1600, 800, 400) and
+ * a single output, all fed the same encoded input): K networks, species k's
+ * output in column k of the output rows, so encode, apply, infer, grad, adam
+ * and train work unchanged.  Stored as one network whose first layer stacks
+ * the K first layers and whose later layers are block diagonal; only the
+ * diagonal blocks are stored and multiplied (grouped BF16 MFMA products, one
+ * group per species).  Parameters in logical order network by network (each
+ * W1, b1, W2, b2, W3, b3, W4 (1 x h3), b4 (1)).  Inference runs the layered
+ * products (no fused kernel).  The weights file holds one network:
+ * chem_surrogate_save and _save_checkpoint return CHEM_EUNSUP for it.
+ * K * h_l <= 65536. */
+int chem_surrogate_create_species(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out);
+/* *groups = 1 for one network, K for the per-species networks. */
+int chem_surrogate_groups(chem_surr surr, int32_t *groups);
 void chem_free_surrogate(chem_surr surr);
 /* dims[0..5] = K+2, h1, h2, h3, K, number of logical parameters. */
 int chem_surrogate_info(chem_surr surr, int64_t *dims);

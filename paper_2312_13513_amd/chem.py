@@ -92,6 +92,8 @@ def _load():
     ckp = C.POINTER(chem_surr_checks)
     L.chem_surrogate_default_checks.argtypes = [ckp]
     L.chem_surrogate_create.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(vp)]
+    L.chem_surrogate_create_species.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(vp)]
+    L.chem_surrogate_groups.argtypes = [vp, C.POINTER(C.c_int32)]
     L.chem_free_surrogate.argtypes = [vp]
     L.chem_free_surrogate.restype = None
     L.chem_surrogate_info.argtypes = [vp, i64p]
@@ -139,6 +141,7 @@ EXPORTED = ("chem_default_opts", "chem_load_mechanism", "chem_free_mechanism",
             "chem_surrogate_train", "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_reserve",
             "chem_surrogate_set_pass_rows", "chem_surrogate_forward_trace", "chem_integrate_noalloc",
             "chem_surrogate_train_part", "chem_surrogate_save_checkpoint", "chem_surrogate_checkpoint_user",
+            "chem_surrogate_create_species", "chem_surrogate_groups",
             "chem_autotune_results", "chem_ldu_create", "chem_free_ldu", "chem_ldu_info", "chem_ldu_laplacian",
             "chem_ldu_to_csr", "chem_ldu_csr_pattern", "chem_ldu_laplacian_csr", "chem_mixture_h_cp",
             "chem_T_from_h", "chem_set_transport", "chem_transport_field")
@@ -358,16 +361,23 @@ def _host_f64(a):
 class Surrogate:
     """Owning wrapper of a chem_surr handle (the mechanism must stay open)."""
 
-    def __init__(self, mech: Mechanism, h1: int = 512, h2: int = 256, h3: int = 128, handle: int = 0):
+    def __init__(self, mech: Mechanism, h1: int = 512, h2: int = 256, h3: int = 128, handle: int = 0,
+                 per_species: bool = False):
+        """per_species: one network nin -> h1 -> h2 -> h3 -> 1 per species (the
+        paper's variant) instead of one network with K outputs."""
         self.mech = mech
         if not handle:
             h = C.c_void_p()
-            _check(_lib.chem_surrogate_create(C.c_void_p(mech.handle), int(h1), int(h2), int(h3), C.byref(h)))
+            create = _lib.chem_surrogate_create_species if per_species else _lib.chem_surrogate_create
+            _check(create(C.c_void_p(mech.handle), int(h1), int(h2), int(h3), C.byref(h)))
             handle = h.value
         self.handle = handle
         dims = (C.c_int64 * 6)()
         _check(_lib.chem_surrogate_info(C.c_void_p(self.handle), dims))
         self.nin, self.h1, self.h2, self.h3, self.K, self.nparams = (int(v) for v in dims)
+        g = C.c_int32()
+        _check(_lib.chem_surrogate_groups(C.c_void_p(self.handle), C.byref(g)))
+        self.groups = g.value
         self.nout_pad = (self.K + 15) // 16 * 16
         self.norm_len = 2 * self.nin + 2 * self.K + 1
 

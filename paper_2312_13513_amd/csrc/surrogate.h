@@ -38,6 +38,10 @@ struct GemmArgs {
     int64_t ldh;
     const float *u;
     int64_t ldu;
+    // grouped product (one independent GEMM per group, blockIdx.z): group z
+    // offsets every pointer by z times its stride (0 or 1 group: one GEMM)
+    int groups;
+    int64_t za, zb, zbias, zf, zh, zu;
 };
 
 hipError_t launch_gemm_bf16(const GemmArgs &g, hipStream_t s);

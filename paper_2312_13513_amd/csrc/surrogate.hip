@@ -67,7 +67,10 @@ __device__ __forceinline__ float gelu_grad(float u)
 constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
 typedef bf16_t TileRow[kBK + kPad];
 
-// lds[r][k] = X(r0 + r, k0 + k), zero outside [0,R) x [0,Kd).
+// lds[r][k] = X(r0 + r, k0 + k), zero outside [0,R) x [0,Kd).  Each thread
+// moves 8 consecutive values as one 16-byte load when they are aligned and
+// inside the matrix, else one by one (the single-column blocks of the
+// per-species networks' output layer start at any column).
 __device__ __forceinline__ void stage_tile(const bf16_t *X, int64_t sr, int64_t sk, int R, int Kd,
                                            int r0, int k0, TileRow *lds)
 {
@@ -77,14 +80,30 @@ __device__ __forceinline__ void stage_tile(const bf16_t *X, int64_t sr, int64_t 
         const int r = t >> 2, kc = (t & 3) * 8;
         const int gr = r0 + r, gk = k0 + kc;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (gr < R && gk < Kd) v = *(const uint4 *)(X + (int64_t)gr * sr + gk);
+        if (gr < R && gk < Kd) {
+            const bf16_t *src = X + (int64_t)gr * sr + gk;
+            if (gk + 8 <= Kd && ((uintptr_t)src & 15) == 0) {
+                v = *(const uint4 *)src;
+            } else {
+                bf16_t *e = (bf16_t *)&v;
+                for (int i = 0; i < 8 && gk + i < Kd; i++) e[i] = src[i];
+            }
+        }
         *(uint4 *)&lds[r][kc] = v;
     } else {
         // contiguous along r: 8 r-values of one k, transposed into LDS
         const int k = t >> 3, rc = (t & 7) * 8;
         const int gr = r0 + rc, gk = k0 + k;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (gr < R && gk < Kd) v = *(const uint4 *)(X + (int64_t)gk * sk + gr);
+        if (gr < R && gk < Kd) {
+            const bf16_t *src = X + (int64_t)gk * sk + gr;
+            if (gr + 8 <= R && ((uintptr_t)src & 15) == 0) {
+                v = *(const uint4 *)src;
+            } else {
+                bf16_t *e = (bf16_t *)&v;
+                for (int i = 0; i < 8 && gr + i < R; i++) e[i] = src[i];
+            }
+        }
         const bf16_t *e = (const bf16_t *)&v;
 #pragma unroll
         for (int i = 0; i < 8; i++) lds[rc + i][k] = e[i];
@@ -93,6 +112,16 @@ __device__ __forceinline__ void stage_tile(const bf16_t *X, int64_t sr, int64_t 
 
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
 {
+    if (blockIdx.z) {
+        // group z of a grouped product (the per-species networks' layers)
+        const int64_t z = blockIdx.z;
+        g.A += z * g.za;
+        g.B += z * g.zb;
+        if (g.bias) g.bias += z * g.zbias;
+        if (g.outf) g.outf += z * g.zf;
+        if (g.outh) g.outh += z * g.zh;
+        if (g.u) g.u += z * g.zu;
+    }
     __shared__ __attribute__((aligned(16))) TileRow As[kBM];
     __shared__ __attribute__((aligned(16))) TileRow Bs[kBN];
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
@@ -764,7 +793,8 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 hipError_t launch_gemm_bf16(const GemmArgs &g, hipStream_t s)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM));
+    dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM),
+              (unsigned)(g.groups > 1 ? g.groups : 1));
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }

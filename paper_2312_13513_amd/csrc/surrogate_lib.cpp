@@ -52,7 +52,13 @@ struct chem_surr_s {
     chem_mech mech = nullptr;
     int device = 0;
     int K = 0, E = 0, nin = 0, h[3] = {0, 0, 0}, nout_pad = 0;
-    int in_l[4], out_l[4];            // padded GEMM shapes of the four layers
+    // G > 1: one network per species (G = K), each nin -> hg[0] -> hg[1] ->
+    // hg[2] -> 1, stored as one network of widths h = G hg whose layers 2-4
+    // are block diagonal (only the diagonal blocks are stored and computed,
+    // as grouped products); G = 1: one network nin -> h -> K
+    int G = 1, hg[3] = {0, 0, 0};
+    int in_l[4], out_l[4];            // padded GEMM shapes of the four layers (in_l: a weight row's length)
+    int ain[4];                       // width of each layer's input activations (G in_l for grouped layers)
     int64_t off_W[4], off_b[4], n_pad = 0, n_logical = 0;
     float *master = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
     bf16_t *wbf = nullptr;
@@ -148,7 +154,29 @@ hipError_t gemm(const bf16_t *A, int64_t sam, int64_t sak, const bf16_t *B, int6
     return chem::launch_gemm_bf16(g, st);
 }
 
-bool fused_ok(const chem_surr_s *s) { return s->in_l[0] == kInPad && chem::mlp_fused_supported(s->out_l); }
+// G independent products, group z's operands offset by z times the strides.
+struct GroupStrides {
+    int groups;
+    int64_t za, zb, zbias, zf, zh, zu;
+};
+
+hipError_t gemm_grouped(const GroupStrides &z, const bf16_t *A, int64_t sam, int64_t sak, const bf16_t *B,
+                        int64_t sbn, int64_t sbk, int M, int N, int K, int epi, const float *bias, float *outf,
+                        int64_t ldf, bf16_t *outh, int64_t ldh, const float *u, int64_t ldu, hipStream_t st)
+{
+    chem::GemmArgs g{A, sam, sak, B, sbn, sbk, M, N, K, epi, bias, outf, ldf, outh, ldh, u, ldu,
+                     z.groups, z.za, z.zb, z.zbias, z.zf, z.zh, z.zu};
+    return chem::launch_gemm_bf16(g, st);
+}
+
+bool fused_ok(const chem_surr_s *s)
+{
+    return s->G == 1 && s->in_l[0] == kInPad && chem::mlp_fused_supported(s->out_l);
+}
+
+// Columns per group of layer l's output: the whole layer unless it is grouped.
+int group_n(const chem_surr_s *s, int l) { return s->G == 1 || l == 0 ? s->out_l[l] : (l == 3 ? 1 : s->hg[l]); }
+bool grouped(const chem_surr_s *s, int l) { return s->G > 1 && l > 0; }
 
 // Inference forward pass of all four layers in one kernel (activations in
 // LDS); the fragment-order copy of the weights is made when they changed.
@@ -185,18 +213,30 @@ hipError_t forward(chem_surr_s *s, const bf16_t *X, int rows, bf16_t *const H[3]
 {
     if (!U[0] && !layered && fused_ok(s)) return forward_fused(s, X, rows, OUT, ldo, st);
     const bf16_t *in = X;
-    int64_t ld_in = kInPad;
     hipError_t e = hipSuccess;
-    for (int l = 0; l < 3 && e == hipSuccess; l++) {
-        const int N = s->out_l[l], Kd = s->in_l[l];
-        e = gemm(in, ld_in, 1, s->wbf + s->off_W[l], Kd, 1, rows, N, Kd, chem::kEpiBiasGeluBf16,
-                 s->master + s->off_b[l], U[l], N, H[l], N, nullptr, 0, st);
-        in = H[l];
-        ld_in = N;
+    for (int l = 0; l < 4 && e == hipSuccess; l++) {
+        const int N = s->out_l[l], Kd = s->in_l[l], ld_in = s->ain[l];
+        const bool last = l == 3;
+        const int epi = last ? chem::kEpiBiasF32 : chem::kEpiBiasGeluBf16;
+        float *outf = last ? OUT : U[l];
+        const int64_t ldf = last ? ldo : N;
+        bf16_t *outh = last ? nullptr : H[l];
+        if (!grouped(s, l)) {
+            e = gemm(in, ld_in, 1, s->wbf + s->off_W[l], Kd, 1, rows, N, Kd, epi, s->master + s->off_b[l], outf,
+                     ldf, outh, N, nullptr, 0, st);
+        } else {
+            // group z: its block of the input columns times its block of weight rows
+            const int gn = group_n(s, l);
+            const GroupStrides z{s->G, Kd, (int64_t)gn * Kd, gn, gn, gn, 0};
+            e = gemm_grouped(z, in, ld_in, 1, s->wbf + s->off_W[l], Kd, 1, rows, gn, Kd, epi,
+                             s->master + s->off_b[l], outf, ldf, outh, N, nullptr, 0, st);
+            if (last && e == hipSuccess && s->G < N)
+                // the padding columns G .. nout_pad-1: zero weight rows and biases, so zeros
+                e = gemm(in, ld_in, 1, s->wbf + s->off_W[l] + (int64_t)s->G * Kd, Kd, 1, rows, N - s->G, Kd, epi,
+                         s->master + s->off_b[l] + s->G, outf + s->G, ldf, nullptr, 0, nullptr, 0, st);
+        }
+        if (!last) in = H[l];
     }
-    if (e == hipSuccess)
-        e = gemm(in, ld_in, 1, s->wbf + s->off_W[3], s->in_l[3], 1, rows, s->out_l[3], s->in_l[3],
-                 chem::kEpiBiasF32, s->master + s->off_b[3], OUT, ldo, nullptr, 0, nullptr, 0, st);
     return e;
 }
 
@@ -207,19 +247,33 @@ hipError_t backward(const chem_surr_s *s, const Acts &a, const bf16_t *X, int ro
     const bf16_t *d = a.dOut;
     int64_t ldd = s->nout_pad;
     for (int l = 3; l >= 0 && e == hipSuccess; l--) {
-        const int Nout = s->out_l[l], Kin = s->in_l[l];
+        const int Nout = s->out_l[l], Kin = s->in_l[l], gn = group_n(s, l);
         const bf16_t *hin = l == 0 ? X : a.H[l - 1];
-        // dW[n][k] = sum_r d[r][n] h[r][k]
-        e = gemm(d, 1, ldd, hin, 1, Kin, Nout, Kin, rows, chem::kEpiF32, nullptr,
-                 s->grad + s->off_W[l], Kin, nullptr, 0, nullptr, 0, st);
+        const int64_t ld_h = s->ain[l];
+        const bf16_t *W = s->wbf + s->off_W[l];
+        if (!grouped(s, l)) {
+            // dW[n][k] = sum_r d[r][n] h[r][k]
+            e = gemm(d, 1, ldd, hin, 1, ld_h, Nout, Kin, rows, chem::kEpiF32, nullptr, s->grad + s->off_W[l], Kin,
+                     nullptr, 0, nullptr, 0, st);
+        } else {
+            const GroupStrides z{s->G, gn, Kin, 0, (int64_t)gn * Kin, 0, 0};
+            e = gemm_grouped(z, d, 1, ldd, hin, 1, ld_h, gn, Kin, rows, chem::kEpiF32, nullptr,
+                             s->grad + s->off_W[l], Kin, nullptr, 0, nullptr, 0, st);
+        }
         if (e == hipSuccess)
             e = chem::launch_bias_grad(d, rows, Nout, (int)ldd, a.bpart, s->grad + s->off_b[l], st);
         if (l > 0 && e == hipSuccess) {
             // d_prev[r][k] = (sum_n d[r][n] W[n][k]) * gelu'(u_prev[r][k])
-            e = gemm(d, ldd, 1, s->wbf + s->off_W[l], 1, Kin, rows, Kin, Nout, chem::kEpiGeluGradBf16,
-                     nullptr, nullptr, 0, a.D[l - 1], Kin, a.U[l - 1], Kin, st);
+            if (!grouped(s, l)) {
+                e = gemm(d, ldd, 1, W, 1, Kin, rows, Kin, Nout, chem::kEpiGeluGradBf16, nullptr, nullptr, 0,
+                         a.D[l - 1], ld_h, a.U[l - 1], ld_h, st);
+            } else {
+                const GroupStrides z{s->G, gn, (int64_t)gn * Kin, 0, 0, Kin, Kin};
+                e = gemm_grouped(z, d, ldd, 1, W, 1, Kin, rows, Kin, gn, chem::kEpiGeluGradBf16, nullptr, nullptr,
+                                 0, a.D[l - 1], ld_h, a.U[l - 1], ld_h, st);
+            }
             d = a.D[l - 1];
-            ldd = Kin;
+            ldd = ld_h;
         }
     }
     return e;
@@ -228,14 +282,28 @@ hipError_t backward(const chem_surr_s *s, const Acts &a, const bf16_t *X, int ro
 // logical <-> padded parameter vectors
 void logical_map(const chem_surr_s *s, std::vector<std::pair<int64_t, int64_t>> &runs)
 {
-    // (padded offset, length) runs in logical order
+    // (padded offset, length) runs in logical order: layer by layer (W rows,
+    // then b) for one network; network by network for the per-species ones
     runs.clear();
-    const int in_real[4] = {s->nin, s->h[0], s->h[1], s->h[2]};
-    const int out_real[4] = {s->h[0], s->h[1], s->h[2], s->K};
-    for (int l = 0; l < 4; l++) {
-        for (int r = 0; r < out_real[l]; r++) runs.push_back({s->off_W[l] + (int64_t)r * s->in_l[l], in_real[l]});
-        runs.push_back({s->off_b[l], out_real[l]});
+    if (s->G == 1) {
+        const int in_real[4] = {s->nin, s->h[0], s->h[1], s->h[2]};
+        const int out_real[4] = {s->h[0], s->h[1], s->h[2], s->K};
+        for (int l = 0; l < 4; l++) {
+            for (int r = 0; r < out_real[l]; r++)
+                runs.push_back({s->off_W[l] + (int64_t)r * s->in_l[l], in_real[l]});
+            runs.push_back({s->off_b[l], out_real[l]});
+        }
+        return;
     }
+    const int in_real[4] = {s->nin, s->hg[0], s->hg[1], s->hg[2]};
+    const int out_g[4] = {s->hg[0], s->hg[1], s->hg[2], 1};
+    for (int g = 0; g < s->G; g++)
+        for (int l = 0; l < 4; l++) {
+            const int64_t row0 = (int64_t)g * out_g[l];
+            for (int r = 0; r < out_g[l]; r++)
+                runs.push_back({s->off_W[l] + (row0 + r) * s->in_l[l], in_real[l]});
+            runs.push_back({s->off_b[l] + row0, out_g[l]});
+        }
 }
 
 int upload_logical(chem_surr_s *s, float *dev, const float *host, int64_t count)
@@ -354,7 +422,11 @@ int chem_surrogate_default_checks(chem_surr_checks *c)
     return CHEM_OK;
 }
 
-int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out)
+namespace {
+
+// One network nin -> h1 -> h2 -> h3 -> K (G = 1) or K per-species networks
+// nin -> h1 -> h2 -> h3 -> 1 (G = K).
+int create_surrogate(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, bool per_species, chem_surr *out)
 {
     if (!mech || !out) return fail(CHEM_EINVAL, "mech and out must not be NULL");
     *out = nullptr;
@@ -364,6 +436,9 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
     for (int v : {h1, h2, h3})
         if (v < 64 || v % 64 != 0 || v > 4096)
             return fail(CHEM_EINVAL, "hidden widths must be multiples of 64 in [64, 4096]");
+    const int G = per_species ? K : 1;
+    if ((int64_t)G * h1 > 65536 || (int64_t)G * h2 > 65536 || (int64_t)G * h3 > 65536)
+        return fail(CHEM_EINVAL, "the per-species networks' layers exceed 65,536 units in all");
     int prev = 0;
     hipGetDevice(&prev);
     if (hipSetDevice(mech->device) != hipSuccess) return fail(CHEM_EHIP, "hipSetDevice failed");
@@ -373,23 +448,32 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
     s->K = K;
     s->E = E;
     s->nin = K + 2;
-    s->h[0] = h1;
-    s->h[1] = h2;
-    s->h[2] = h3;
+    s->G = G;
+    s->hg[0] = h1;
+    s->hg[1] = h2;
+    s->hg[2] = h3;
+    s->h[0] = G * h1;
+    s->h[1] = G * h2;
+    s->h[2] = G * h3;
     s->nout_pad = round_up(K, 16);
-    const int in_l[4] = {kInPad, h1, h2, h3}, out_l[4] = {h1, h2, h3, s->nout_pad};
+    const int in_l[4] = {kInPad, h1, h2, h3};
+    const int out_l[4] = {G * h1, G * h2, G * h3, s->nout_pad};
+    const int ain[4] = {kInPad, G * h1, G * h2, G * h3};
     int64_t off = 0;
     s->n_logical = 0;
-    const int in_real[4] = {s->nin, h1, h2, h3}, out_real[4] = {h1, h2, h3, K};
     for (int l = 0; l < 4; l++) {
         s->in_l[l] = in_l[l];
         s->out_l[l] = out_l[l];
+        s->ain[l] = ain[l];
         s->off_W[l] = off;
         off += (int64_t)in_l[l] * out_l[l];
         s->off_b[l] = off;
         off += round_up(out_l[l], 64);
-        s->n_logical += (int64_t)in_real[l] * out_real[l] + out_real[l];
     }
+    if (G == 1)
+        s->n_logical = (int64_t)s->nin * h1 + h1 + (int64_t)h1 * h2 + h2 + (int64_t)h2 * h3 + h3 + (int64_t)h3 * K + K;
+    else
+        s->n_logical = (int64_t)G * ((int64_t)s->nin * h1 + h1 + (int64_t)h1 * h2 + h2 + (int64_t)h2 * h3 + h3 + h3 + 1);
     s->n_pad = off;
     const int64_t nn = 2 * (int64_t)s->nin + 2 * K;
     const size_t bytes = 4 * carve_size<float>(s->n_pad) + 2 * carve_size<bf16_t>(s->n_pad) +
@@ -429,6 +513,25 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
         return rc;
     }
     *out = s;
+    return CHEM_OK;
+}
+
+}  // namespace
+
+int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out)
+{
+    return create_surrogate(mech, h1, h2, h3, false, out);
+}
+
+int chem_surrogate_create_species(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out)
+{
+    return create_surrogate(mech, h1, h2, h3, true, out);
+}
+
+int chem_surrogate_groups(chem_surr s, int32_t *groups)
+{
+    if (!s || !groups) return fail(CHEM_EINVAL, "surrogate and groups must not be NULL");
+    *groups = s->G;
     return CHEM_OK;
 }
 
@@ -552,7 +655,8 @@ int chem_surrogate_forward_path(chem_surr s, const uint16_t *X, int64_t n, float
     int rc = check_surr(s);
     if (rc != CHEM_OK) return rc;
     if (path < 0 || path > 2) return fail(CHEM_EINVAL, "path must be 0, 1 or 2");
-    if (path == 2 && !fused_ok(s)) return fail(CHEM_EUNSUP, "the fused forward kernel takes widths up to 512");
+    if (path == 2 && !fused_ok(s))
+        return fail(CHEM_EUNSUP, "the fused forward kernel takes one network with widths up to 512");
     if (n == 0) return CHEM_OK;
     if (n < 0 || ldo < s->nout_pad) return fail(CHEM_EINVAL, "need ncells >= 0 and ldo >= K rounded up to 16");
     if (!is_device_ptr(X) || !is_device_ptr(out)) return fail(CHEM_EINVAL, "X and out must be device pointers");
@@ -877,6 +981,9 @@ namespace {
 // The handle's network, normalisation and, with opt, optimiser state as a file image.
 int surr_to_file(chem_surr s, bool opt, chem_file::SurrFile &f)
 {
+    if (s->G != 1)
+        return fail(CHEM_EUNSUP, "the weights file holds one network; the per-species networks are not saved "
+                                 "(get their parameters with chem_surrogate_get_params)");
     f.K = s->K;
     f.nin = s->nin;
     for (int l = 0; l < 3; l++) f.h[l] = s->h[l];
