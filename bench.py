@@ -28,6 +28,12 @@ Other workloads (``--workload``):
              FP64 residuals and state, wave-per-cell schedule;
   laplacian128  implicit Laplacian assembly (Algorithm 1) + ldu -> CSR
              conversion on a graded 128^3 box (HBM roofline);
+  species_nets  the paper's per-species networks (one 1600-800-400 network
+             per species, grouped BF16 MFMA products) against the single
+             512-256-128 network, both trained on the same integrator-
+             labelled states of the 9-species mechanism (dt = 1e-6) and
+             served on flame64: forward TFLOP/s, served step, fallback and
+             max |dT| against the plain GPU integrator and the oracle;
   props_tgv  the Thermo field kernels on one GPU's share of the 256^3 TGV
              mesh (256x128x128 = 4,194,304 cells, 9 species): T from h by
              Newton from the previous step's T, then mixture-averaged
@@ -698,6 +704,141 @@ def run_laplacian(args):
     return result
 
 
+def run_species(args):
+    """Per-species networks vs one network (survey row f2), each trained on
+    the same states for the same epochs, served on flame64 through the same
+    checks and fallback.  One step = chem_surrogate_infer over the field from
+    the pristine state (restored by a device copy inside the step)."""
+    import torch
+
+    from chemgen import fields as F
+    from chemgen.surrogate_data import (epoch_orders, flame_like_states, init_params, init_species_params,
+                                        network_dims, trajectory_starts)
+    from paper_2312_13513_amd import chem
+
+    dev = torch.device("cuda:0")
+    mpy, path = mech_file("M9")
+    mech = chem.Mechanism(path, 0)
+    dt, K = 1e-6, mpy.K
+    t = lambda a, dtype=torch.float64: torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=dev)
+    n_samples = min(args.train_samples, 524288)
+    n_half = n_samples // 2
+    T1, p1, Y1 = flame_like_states(mpy, n_half, seed=7)
+    n_traj = max(2, n_half // args.traj_steps)
+    T2, p2, Y2 = trajectory_starts(mpy, n_traj // 2, seed=8)
+    T3, p3, Y3 = flame_like_states(mpy, n_traj - n_traj // 2, seed=9)
+    T2, p2, Y2 = np.concatenate([T2, T3]), np.concatenate([p2, p3]), np.concatenate([Y2, Y3], axis=1)
+    Tt, pt, Yt = t(T2), t(p2), t(Y2)
+    Ts, Ys = [], []
+    for _ in range(args.traj_steps):
+        mech.integrate(Tt, pt, Yt, dt)
+        Ts.append(Tt.clone())
+        Ys.append(Yt.clone())
+    Td = torch.cat([t(T1)] + Ts)
+    pd = torch.cat([t(p1), t(np.full(n_traj * args.traj_steps, p2[0]))])
+    Yd = torch.cat([t(Y1)] + Ys, dim=1).contiguous()
+    del Ts, Ys
+    Yn, Tn = Yd.clone(), Td.clone()
+    mech.integrate(Tn, pd, Yn, dt)
+    torch.cuda.synchronize()
+    n_train = Td.shape[0]
+    progress(f"species_nets: labelled {n_train} states")
+    field = F.flame64(mpy)
+    n = field.n
+    T0, p0, Y0 = t(field.T), t(field.p), t(field.Y)
+    # the reference: the plain FP64 integrator on the whole field
+    Tp, Yp = T0.clone(), Y0.clone()
+    mech.integrate(Tp, p0, Yp, dt)
+    Tp_ = Tp.cpu().numpy()
+    stream = torch.cuda.current_stream()
+    nets = {"single": ((512, 256, 128), False), "species": ((1600, 800, 400), True)}
+    out = {}
+    for name, (h, per_species) in nets.items():
+        s = chem.Surrogate(mech, *h, per_species=per_species)
+        s.set_params(init_species_params(K, h, 11) if per_species else init_params(network_dims(K, *h), 11))
+        s.fit_norm(Td, pd, Yd, Yn, dt)
+        order = t(epoch_orders(n_train, args.epochs, 12), torch.int32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = s.train(Td, pd, Yd, Yn, epochs=args.epochs, batch=4096, lr0=1e-3, lr1=1e-5, order=order)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        del order
+        progress(f"species_nets: {name} trained in {train_s:.1f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}")
+        # forward alone on the field's encoded rows
+        X = torch.zeros((n, 64), dtype=torch.int16, device=dev)
+        s.encode(T0, p0, Y0, X)
+        o = torch.zeros((n, s.nout_pad), dtype=torch.float32, device=dev)
+        for _ in range(2):
+            s.forward(X, o)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            s.forward(X, o)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        fwd_s = ev[0].elapsed_time(ev[1]) * 1e-3 / args.steps
+        hh = (K + 2, *h)
+        per_net = 2 * (hh[0] * hh[1] + hh[1] * hh[2] + hh[2] * hh[3])
+        flops = n * (K * (per_net + 2 * hh[3]) if per_species else per_net + 2 * hh[3] * K)
+        del X, o
+        # served steps
+        T, Y = T0.clone(), Y0.clone()
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def step(e=None):
+            T.copy_(T0)
+            Y.copy_(Y0)
+            if e is not None:
+                e[0].record(stream)
+            s.infer(T, p0, Y, dt, fallback_count=cnt, stream=stream)
+            if e is not None:
+                e[1].record(stream)
+
+        for _ in range(args.warmup):
+            step()
+        evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(2)) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        step_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        Ts_ = T.cpu().numpy()
+        out[name] = {
+            "hidden": list(h), "networks": K if per_species else 1, "params": s.nparams,
+            "served_cell_steps_per_s": n * args.steps / wall, "ms_per_step": wall / args.steps * 1e3,
+            "infer_ms": step_ms, "fallback_cells": int(cnt.item()),
+            "forward": {"ms": fwd_s * 1e3, "flops_per_cell": flops / n, "achieved_TFLOPs": flops / fwd_s / 1e12,
+                        "frac_of_bf16_peak": flops / fwd_s / 2.5e15},
+            "max_dT_vs_plain_gpu": float(np.abs(Ts_ - Tp_).max()),
+            "mean_dT_vs_plain_gpu": float(np.abs(Ts_ - Tp_).mean()),
+            "train": {"samples": n_train, "epochs": args.epochs, "s": train_s, "loss_first": float(losses[0]),
+                      "loss_last": float(losses[-1])},
+        }
+        progress(f"species_nets: {name}: {out[name]['infer_ms']:.2f} ms/step, forward {fwd_s * 1e3:.3f} ms "
+                 f"({flops / fwd_s / 1e12:.0f} TFLOP/s), fallback {out[name]['fallback_cells']}, "
+                 f"max|dT| {out[name]['max_dT_vs_plain_gpu']:.3f} K")
+        s.close()
+    sp = out["species"]
+    result = {
+        "metric": "per-species vs single-network surrogate on flame64 (9 species, dt = 1e-6 s), served cell-steps/s",
+        "value": sp["served_cell_steps_per_s"], "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sp["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "species_nets: flame64 (262,144 cells, 9 species), both networks trained on the same "
+                               f"{n_train} integrator-labelled states for {args.epochs} epochs",
+                   "ncells": n},
+        "roofline": {"bound": "mfma", "achieved": sp["forward"]["achieved_TFLOPs"], "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": sp["forward"]["frac_of_bf16_peak"], "traffic": None,
+                     "kernel": "gemm_bf16_kernel (grouped, one group per species)"},
+        "species": sp, "single": out["single"],
+    }
+    mech.close()
+    return result
+
+
 def props_flops(K: int) -> dict:
     """Algorithmic FP64 flops per cell of the property kernels (add, mul,
     div = 1, fused multiply-add = 2, log and sqrt = 20), from the
@@ -837,7 +978,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="flame64",
-                    choices=("flame64", "cells4096", "zones128", "surrogate", "laplacian128", "props_tgv"))
+                    choices=("flame64", "cells4096", "zones128", "surrogate", "laplacian128", "props_tgv",
+                             "species_nets"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", type=int, default=None, choices=(-2, -1, 0, 1, 2),
                     help="integrator workloads: -2 autotuned (flame64 default), -1 library choice, 0 thread, "
@@ -894,6 +1036,8 @@ def main():
         result = run_laplacian(args)
     elif args.workload == "props_tgv":
         result = run_props(args)
+    elif args.workload == "species_nets":
+        result = run_species(args)
     else:
         result = run_integrator(args, args.workload)
         if args.workload == "flame64" and not args.no_surrogate:

@@ -309,7 +309,9 @@ int chem_surrogate_create(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, ch
  * W1, b1, W2, b2, W3, b3, W4 (1 x h3), b4 (1)).  Inference runs the layered
  * products (no fused kernel).  The weights file holds one network:
  * chem_surrogate_save and _save_checkpoint return CHEM_EUNSUP for it.
- * K * h_l <= 65536. */
+ * Widths 16 .. 4096, each padded to a multiple of 64 with units whose
+ * weights and biases stay zero; K * (padded h_l) <= 65536.
+ * chem_surrogate_info reports the padded totals K * padded h_l. */
 int chem_surrogate_create_species(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, chem_surr *out);
 /* *groups = 1 for one network, K for the per-species networks. */
 int chem_surrogate_groups(chem_surr surr, int32_t *groups);

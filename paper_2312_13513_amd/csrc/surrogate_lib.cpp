@@ -57,6 +57,7 @@ struct chem_surr_s {
     // are block diagonal (only the diagonal blocks are stored and computed,
     // as grouped products); G = 1: one network nin -> h -> K
     int G = 1, hg[3] = {0, 0, 0};
+    int hr[3] = {0, 0, 0};            // the per-species networks' real widths (hg: padded to 64)
     int in_l[4], out_l[4];            // padded GEMM shapes of the four layers (in_l: a weight row's length)
     int ain[4];                       // width of each layer's input activations (G in_l for grouped layers)
     int64_t off_W[4], off_b[4], n_pad = 0, n_logical = 0;
@@ -102,6 +103,14 @@ struct Acts {
     float *OUT, *U[3], *Yb, *bpart;
 };
 
+// Partial bias gradients: 64 row chunks times the widest layer.
+int64_t bias_part_len(const chem_surr_s *s)
+{
+    int w = 0;
+    for (int l = 0; l < 4; l++) w = s->out_l[l] > w ? s->out_l[l] : w;
+    return 64 * (int64_t)w;
+}
+
 size_t acts_bytes(const chem_surr_s *s, int64_t rows, bool train)
 {
     size_t b = carve_size<bf16_t>(rows * kInPad) + carve_size<float>(rows * s->nout_pad);
@@ -109,7 +118,7 @@ size_t acts_bytes(const chem_surr_s *s, int64_t rows, bool train)
     if (train) {
         for (int l = 0; l < 3; l++) b += carve_size<float>(rows * s->h[l]) + carve_size<bf16_t>(rows * s->h[l]);
         b += carve_size<float>(rows * s->nout_pad) + carve_size<bf16_t>(rows * s->nout_pad);
-        b += carve_size<float>(64 * 4096);
+        b += carve_size<float>(bias_part_len(s));
     }
     return b;
 }
@@ -141,7 +150,7 @@ Acts carve_acts(const chem_surr_s *s)
         }
         a.Yb = c.take<float>(rows * s->nout_pad);
         a.dOut = c.take<bf16_t>(rows * s->nout_pad);
-        a.bpart = c.take<float>(64 * 4096);
+        a.bpart = c.take<float>(bias_part_len(s));
     }
     return a;
 }
@@ -295,14 +304,15 @@ void logical_map(const chem_surr_s *s, std::vector<std::pair<int64_t, int64_t>> 
         }
         return;
     }
-    const int in_real[4] = {s->nin, s->hg[0], s->hg[1], s->hg[2]};
-    const int out_g[4] = {s->hg[0], s->hg[1], s->hg[2], 1};
+    const int in_real[4] = {s->nin, s->hr[0], s->hr[1], s->hr[2]};
+    const int out_real[4] = {s->hr[0], s->hr[1], s->hr[2], 1};
+    const int out_pad[4] = {s->hg[0], s->hg[1], s->hg[2], 1};
     for (int g = 0; g < s->G; g++)
         for (int l = 0; l < 4; l++) {
-            const int64_t row0 = (int64_t)g * out_g[l];
-            for (int r = 0; r < out_g[l]; r++)
+            const int64_t row0 = (int64_t)g * out_pad[l];
+            for (int r = 0; r < out_real[l]; r++)
                 runs.push_back({s->off_W[l] + (row0 + r) * s->in_l[l], in_real[l]});
-            runs.push_back({s->off_b[l] + row0, out_g[l]});
+            runs.push_back({s->off_b[l] + row0, out_real[l]});
         }
 }
 
@@ -433,10 +443,21 @@ int create_surrogate(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, bool pe
     const int K = mech->host.K, E = mech->host.E;
     if (K + 2 > kInPad) return fail(CHEM_EUNSUP, "the surrogate takes at most 62 species");
     if (E > 8) return fail(CHEM_EUNSUP, "the surrogate takes at most 8 elements");
-    for (int v : {h1, h2, h3})
-        if (v < 64 || v % 64 != 0 || v > 4096)
-            return fail(CHEM_EINVAL, "hidden widths must be multiples of 64 in [64, 4096]");
+    if (per_species) {
+        // any width: each network's layers are padded to multiples of 64 with
+        // units whose weights and biases stay zero (their gradients are zero)
+        for (int v : {h1, h2, h3})
+            if (v < 16 || v > 4096) return fail(CHEM_EINVAL, "hidden widths must be in [16, 4096]");
+    } else {
+        for (int v : {h1, h2, h3})
+            if (v < 64 || v % 64 != 0 || v > 4096)
+                return fail(CHEM_EINVAL, "hidden widths must be multiples of 64 in [64, 4096]");
+    }
     const int G = per_species ? K : 1;
+    const int hr[3] = {h1, h2, h3};
+    h1 = round_up(h1, 64);
+    h2 = round_up(h2, 64);
+    h3 = round_up(h3, 64);
     if ((int64_t)G * h1 > 65536 || (int64_t)G * h2 > 65536 || (int64_t)G * h3 > 65536)
         return fail(CHEM_EINVAL, "the per-species networks' layers exceed 65,536 units in all");
     int prev = 0;
@@ -449,6 +470,7 @@ int create_surrogate(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, bool pe
     s->E = E;
     s->nin = K + 2;
     s->G = G;
+    for (int l = 0; l < 3; l++) s->hr[l] = hr[l];
     s->hg[0] = h1;
     s->hg[1] = h2;
     s->hg[2] = h3;
@@ -473,7 +495,8 @@ int create_surrogate(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, bool pe
     if (G == 1)
         s->n_logical = (int64_t)s->nin * h1 + h1 + (int64_t)h1 * h2 + h2 + (int64_t)h2 * h3 + h3 + (int64_t)h3 * K + K;
     else
-        s->n_logical = (int64_t)G * ((int64_t)s->nin * h1 + h1 + (int64_t)h1 * h2 + h2 + (int64_t)h2 * h3 + h3 + h3 + 1);
+        s->n_logical = (int64_t)G * ((int64_t)s->nin * hr[0] + hr[0] + (int64_t)hr[0] * hr[1] + hr[1] +
+                                     (int64_t)hr[1] * hr[2] + hr[2] + hr[2] + 1);
     s->n_pad = off;
     const int64_t nn = 2 * (int64_t)s->nin + 2 * K;
     const size_t bytes = 4 * carve_size<float>(s->n_pad) + 2 * carve_size<bf16_t>(s->n_pad) +

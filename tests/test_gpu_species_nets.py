@@ -37,14 +37,17 @@ def _species_surr(chem, mech, K, h, seed):
     return s, flat
 
 
-@pytest.mark.parametrize("rows", [1, 63, 2050])
-def test_species_forward_parity(torch, mechs, rows):
-    """K = 9 networks of widths 128 / 64 / 64: the per-layer BF16 activations
-    of every species' block against the oracle, and each species' output."""
+@pytest.mark.parametrize("rows,h", [(1, (128, 64, 64)), (63, (128, 64, 64)), (2050, (128, 64, 64)),
+                                    (257, (100, 72, 40))])
+def test_species_forward_parity(torch, mechs, rows, h):
+    """K = 9 networks: the per-layer BF16 activations of every species' block
+    against the oracle, and each species' output; widths that are not
+    multiples of 64 are padded with units that stay exactly zero."""
     from chemgen.surrogate_data import split_species_params
     from oracle import surrogate as S
     from paper_2312_13513_amd import chem
-    K, h = 9, (128, 64, 64)
+    K = 9
+    hp = [(w + 63) // 64 * 64 for w in h]
     s, flat = _species_surr(chem, mechs["M9"], K, h, 41)
     rng = np.random.default_rng(rows + 5)
     x = S.to_bf16(rng.normal(0, 1, (rows, K + 2)).astype(np.float32))
@@ -72,7 +75,8 @@ def test_species_forward_parity(torch, mechs, rows):
             tol_u = (W.shape[1] + 1) * 2.0 ** -24 * (np.abs(hin) @ np.abs(W).T + np.abs(b))
             gl = S.gelu(u)
             tol = 2.0 * (GELU_LIP * tol_u + GELU_REL * np.abs(gl)) + 1e-37
-            got = Hh[li][:, g * h[li]:(g + 1) * h[li]]
+            got = Hh[li][:, g * hp[li]:g * hp[li] + h[li]]
+            assert np.all(Hh[li][:, g * hp[li] + h[li]:(g + 1) * hp[li]] == 0.0)
             exact = S.to_bf16(gl)
             lo, hi = S.to_bf16(gl - tol), S.to_bf16(gl + tol)
             flip = got != exact
@@ -93,11 +97,15 @@ def test_species_forward_parity(torch, mechs, rows):
     s.close()
 
 
-def test_species_gradient_parity(torch, mechs):
+@pytest.mark.parametrize("h,rows", [((128, 64, 64), 640), ((512, 72, 64), 256)])
+def test_species_gradient_parity(torch, mechs, h, rows):
+    """Gradients of all K networks by norms; the second case has a first
+    layer of 9 x 512 = 4,608 units in all, wider than any single network,
+    whose partial bias gradients the training buffers must hold."""
     from chemgen.surrogate_data import split_species_params
     from oracle import surrogate as S
     from paper_2312_13513_amd import chem
-    K, h, rows = 9, (128, 64, 64), 640
+    K = 9
     s, flat = _species_surr(chem, mechs["M9"], K, h, 51)
     rng = np.random.default_rng(52)
     x = S.to_bf16(rng.normal(0, 1, (rows, K + 2)).astype(np.float32))
