@@ -673,7 +673,8 @@ def run_laplacian(args):
                                "zero-gradient patches", "ncells": nc, "faces": nf, "boundary_faces": nb,
                    "csr_entries": nnz},
         "roofline": {"bound": "hbm", "achieved": bytes_dir / dir_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                     "frac": bytes_dir / dir_s / 1e9 / 8000.0, "traffic": None,
+                     "frac": bytes_dir / dir_s / 1e9 / 8000.0,
+                     "traffic": traffic_for("laplacian128", "csr_assemble_faces_kernel+csr_assemble_cells_kernel"),
                      "kernel": "csr_assemble_faces_kernel + csr_assemble_cells_kernel (direct CSR assembly)",
                      "kernel_ms": dir_s * 1e3, "bytes_per_launch": bytes_dir},
         "ldu_path": {"cells_per_s": nc * args.steps / wall2, "ms_per_step": wall2 / args.steps * 1e3,
@@ -933,7 +934,7 @@ def run_props(args):
                 "hbm_frac": nbytes / secs / 8e12}
 
     km = 12 if K <= 12 else 16
-    r_tr = roof(flops_tr, bytes_tr, trans_s, f"transport_kernel<{km}, true, 3>")
+    r_tr = roof(flops_tr, bytes_tr, trans_s, f"transport_kernel<{km},true,3>")
     r_nw = roof(flops_nw, bytes_nw, newton_s, f"t_from_h_kernel<{km}>")
     dominant = r_tr if trans_s >= newton_s else r_nw
     result = {
