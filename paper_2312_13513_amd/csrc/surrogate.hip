@@ -71,8 +71,9 @@ typedef bf16_t TileRow[kBK + kPad];
 // moves 8 consecutive values as one 16-byte load when they are aligned and
 // inside the matrix, else one by one (the single-column blocks of the
 // per-species networks' output layer start at any column).
+template <int W = kBK + kPad>
 __device__ __forceinline__ void stage_tile(const bf16_t *X, int64_t sr, int64_t sk, int R, int Kd,
-                                           int r0, int k0, TileRow *lds)
+                                           int r0, int k0, bf16_t (*lds)[W], int c0 = 0)
 {
     const int t = threadIdx.x;
     if (sk == 1) {
@@ -86,10 +87,12 @@ __device__ __forceinline__ void stage_tile(const bf16_t *X, int64_t sr, int64_t 
                 v = *(const uint4 *)src;
             } else {
                 bf16_t *e = (bf16_t *)&v;
-                for (int i = 0; i < 8 && gk + i < Kd; i++) e[i] = src[i];
+#pragma unroll
+                for (int i = 0; i < 8; i++)
+                    if (gk + i < Kd) e[i] = src[i];
             }
         }
-        *(uint4 *)&lds[r][kc] = v;
+        *(uint4 *)&lds[r][c0 + kc] = v;
     } else {
         // contiguous along r: 8 r-values of one k, transposed into LDS
         const int k = t >> 3, rc = (t & 7) * 8;
@@ -101,16 +104,19 @@ __device__ __forceinline__ void stage_tile(const bf16_t *X, int64_t sr, int64_t 
                 v = *(const uint4 *)src;
             } else {
                 bf16_t *e = (bf16_t *)&v;
-                for (int i = 0; i < 8 && gr + i < R; i++) e[i] = src[i];
+#pragma unroll
+                for (int i = 0; i < 8; i++)
+                    if (gr + i < R) e[i] = src[i];
             }
         }
         const bf16_t *e = (const bf16_t *)&v;
 #pragma unroll
-        for (int i = 0; i < 8; i++) lds[rc + i][k] = e[i];
+        for (int i = 0; i < 8; i++) lds[rc + i][c0 + k] = e[i];
     }
 }
 
-__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
+// Offsets of group blockIdx.z of a grouped product.
+__device__ __forceinline__ void gemm_group(GemmArgs &g)
 {
     if (blockIdx.z) {
         // group z of a grouped product (the per-species networks' layers)
@@ -122,62 +128,89 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
         if (g.outh) g.outh += z * g.zh;
         if (g.u) g.u += z * g.zu;
     }
-    __shared__ __attribute__((aligned(16))) TileRow As[kBM];
-    __shared__ __attribute__((aligned(16))) TileRow Bs[kBN];
-    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+}
+
+__device__ __forceinline__ void gemm_store(const GemmArgs &g, int m, int n, float v)
+{
+    if (m >= g.M || n >= g.N) return;
+    switch (g.epi) {
+    case kEpiBiasF32:
+        g.outf[(int64_t)m * g.ldf + n] = v + (g.bias ? g.bias[n] : 0.0f);
+        break;
+    case kEpiBiasGeluBf16: {
+        const float u = v + (g.bias ? g.bias[n] : 0.0f);
+        if (g.outf) g.outf[(int64_t)m * g.ldf + n] = u;
+        g.outh[(int64_t)m * g.ldh + n] = act_bf16(gelu(u));
+        break;
+    }
+    case kEpiGeluGradBf16:
+        g.outh[(int64_t)m * g.ldh + n] = act_bf16(v * gelu_grad(g.u[(int64_t)m * g.ldu + n]));
+        break;
+    default:
+        g.outf[(int64_t)m * g.ldf + n] = v;
+        break;
+    }
+}
+
+// TM x TM output tile per 256-thread block (TM = 64 or 128), four waves in
+// 2 x 2, each wave (TM/2) x (TM/2) = (TM/32)^2 MFMA 16x16x32 tiles; K in
+// steps of 32 through LDS, in increasing order: every output element sees
+// the same sequence of MFMAs whatever TM, so both tile sizes (and the fused
+// forward kernel) give the same bits.  The 128 tile does four times the
+// MFMA work per barrier pair and per staged byte.
+template <int TM>
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
+{
+    constexpr int WT = TM / 32;              // MFMA tiles per wave and dimension
+    constexpr int KB = TM == 128 ? 64 : 32;  // K per staged step (two MFMA K steps at the 128 tile)
+    constexpr int RW = KB + kPad;            // LDS row, padded
+    gemm_group(g);
+    __shared__ __attribute__((aligned(16))) bf16_t As[TM][RW];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[TM][RW];
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int wm = (w & 1) * (TM / 2), wn = (w >> 1) * (TM / 2);
     const int kk = (lane >> 4) * 8;
-    floatx4 acc[2][2];
+    floatx4 acc[WT][WT];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < WT; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
-        stage_tile(g.A, g.sam, g.sak, g.M, g.K, m0, k0, As);
-        stage_tile(g.B, g.sbn, g.sbk, g.N, g.K, n0, k0, Bs);
+        for (int j = 0; j < WT; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += KB) {
+#pragma unroll
+        for (int h = 0; h < TM / 64; h++)
+#pragma unroll
+            for (int c = 0; c < KB / kBK; c++) {
+                stage_tile<RW>(g.A, g.sam, g.sak, g.M, g.K, m0 + 64 * h, k0 + kBK * c, As + 64 * h, kBK * c);
+                stage_tile<RW>(g.B, g.sbn, g.sbk, g.N, g.K, n0 + 64 * h, k0 + kBK * c, Bs + 64 * h, kBK * c);
+            }
         __syncthreads();
-        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; i++) __builtin_memcpy(&a[i], &As[wm + i * 16 + (lane & 15)][kk], 16);
+        for (int c = 0; c < KB / kBK; c++) {
+            bf16x8 a[WT], b[WT];
 #pragma unroll
-        for (int j = 0; j < 2; j++) __builtin_memcpy(&b[j], &Bs[wn + j * 16 + (lane & 15)][kk], 16);
+            for (int i = 0; i < WT; i++)
+                __builtin_memcpy(&a[i], &As[wm + i * 16 + (lane & 15)][kBK * c + kk], 16);
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+            for (int j = 0; j < WT; j++)
+                __builtin_memcpy(&b[j], &Bs[wn + j * 16 + (lane & 15)][kBK * c + kk], 16);
 #pragma unroll
-            for (int j = 0; j < 2; j++)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < WT; i++)
+#pragma unroll
+                for (int j = 0; j < WT; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
     // D layout of a 16x16 MFMA tile: lane l holds rows 4*(l/16) + r, column l%16
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < WT; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < WT; j++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
-                const int n = n0 + wn + j * 16 + (lane & 15);
-                if (m >= g.M || n >= g.N) continue;
-                const float v = acc[i][j][r];
-                switch (g.epi) {
-                case kEpiBiasF32:
-                    g.outf[(int64_t)m * g.ldf + n] = v + (g.bias ? g.bias[n] : 0.0f);
-                    break;
-                case kEpiBiasGeluBf16: {
-                    const float u = v + (g.bias ? g.bias[n] : 0.0f);
-                    if (g.outf) g.outf[(int64_t)m * g.ldf + n] = u;
-                    g.outh[(int64_t)m * g.ldh + n] = act_bf16(gelu(u));
-                    break;
-                }
-                case kEpiGeluGradBf16:
-                    g.outh[(int64_t)m * g.ldh + n] = act_bf16(v * gelu_grad(g.u[(int64_t)m * g.ldu + n]));
-                    break;
-                default:
-                    g.outf[(int64_t)m * g.ldf + n] = v;
-                    break;
-                }
-            }
+            for (int r = 0; r < 4; r++)
+                gemm_store(g, m0 + wm + i * 16 + (lane >> 4) * 4 + r, n0 + wn + j * 16 + (lane & 15),
+                           acc[i][j][r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -793,9 +826,16 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 hipError_t launch_gemm_bf16(const GemmArgs &g, hipStream_t s)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM),
-              (unsigned)(g.groups > 1 ? g.groups : 1));
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+    const unsigned gz = (unsigned)(g.groups > 1 ? g.groups : 1);
+    // the 128 tile where it still gives every CU several blocks
+    const int64_t tiles128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * gz;
+    if (g.M >= 128 && g.N >= 128 && tiles128 >= 1024) {
+        dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), gz);
+        hipLaunchKernelGGL(gemm_bf16_kernel<128>, grid, dim3(256), 0, s, g);
+    } else {
+        dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM), gz);
+        hipLaunchKernelGGL(gemm_bf16_kernel<64>, grid, dim3(256), 0, s, g);
+    }
     return hipGetLastError();
 }
 
