@@ -102,6 +102,16 @@ hipError_t launch_apply(const ApplyArgs &a, double *T, const double *p, double *
                         int32_t *status, int32_t *list, int64_t *count, hipStream_t s);
 
 hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s);
+// out = v[0] + ... + v[n-1], one small kernel
+hipError_t launch_sum_i64(const int64_t *v, int n, int64_t *out, hipStream_t s);
+// gather / scatter with the compacted arrays' leading dimension ldc apart
+// from the capacity cap (a pass's slice of a larger compaction buffer)
+hipError_t launch_gather_cells_ld(const int32_t *list, const int64_t *count, int64_t cap, int64_t ldc,
+                                  const double *T, const double *p, const double *Y, int64_t ldY,
+                                  int K, double *cT, double *cp, double *cY, hipStream_t s);
+hipError_t launch_scatter_cells_ld(const int32_t *list, const int64_t *count, int64_t cap, int64_t ldc,
+                                   const double *cT, const double *cY, const int32_t *cstatus, int K,
+                                   double *T, double *Y, int64_t ldY, int32_t *status, hipStream_t s);
 
 // Compaction of the listed cells into contiguous arrays and back.
 hipError_t launch_gather_cells(const int32_t *list, const int64_t *count, int64_t cap,

@@ -673,6 +673,15 @@ __global__ void __launch_bounds__(256, 3) apply_kernel(ApplyArgs a, double *__re
     }
 }
 
+// out = v[0] + ... + v[n-1] (one wave; n is a handful of pass counts)
+__global__ void sum_i64_kernel(const int64_t *__restrict__ v, int n, int64_t *__restrict__ out)
+{
+    int64_t s = 0;
+    for (int i = threadIdx.x; i < n; i += 64) s += v[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+    if (threadIdx.x == 0) *out = s;
+}
+
 __global__ void zero_i64_kernel(int64_t *p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -681,7 +690,7 @@ __global__ void zero_i64_kernel(int64_t *p, int n)
 
 __global__ void __launch_bounds__(256) gather_cells_kernel(const int32_t *__restrict__ list,
                                                            const int64_t *__restrict__ count,
-                                                           int64_t cap, const double *__restrict__ T,
+                                                           int64_t cap, int64_t ldc, const double *__restrict__ T,
                                                            const double *__restrict__ p,
                                                            const double *__restrict__ Y, int64_t ldY,
                                                            int K, double *__restrict__ cT,
@@ -694,12 +703,12 @@ __global__ void __launch_bounds__(256) gather_cells_kernel(const int32_t *__rest
     const int64_t i = list[j];
     cT[j] = T[i];
     cp[j] = p[i];
-    for (int k = 0; k < K; k++) cY[(int64_t)k * cap + j] = Y[(int64_t)k * ldY + i];
+    for (int k = 0; k < K; k++) cY[(int64_t)k * ldc + j] = Y[(int64_t)k * ldY + i];
 }
 
 __global__ void __launch_bounds__(256) scatter_cells_kernel(const int32_t *__restrict__ list,
                                                             const int64_t *__restrict__ count,
-                                                            int64_t cap, const double *__restrict__ cT,
+                                                            int64_t cap, int64_t ldc, const double *__restrict__ cT,
                                                             const double *__restrict__ cY,
                                                             const int32_t *__restrict__ cstatus, int K,
                                                             double *__restrict__ T,
@@ -711,7 +720,7 @@ __global__ void __launch_bounds__(256) scatter_cells_kernel(const int32_t *__res
     if (j >= cnt) return;
     const int64_t i = list[j];
     T[i] = cT[j];
-    for (int k = 0; k < K; k++) Y[(int64_t)k * ldY + i] = cY[(int64_t)k * cap + j];
+    for (int k = 0; k < K; k++) Y[(int64_t)k * ldY + i] = cY[(int64_t)k * ldc + j];
     if (status) status[i] = cstatus ? cstatus[j] : 0;
 }
 
@@ -957,13 +966,30 @@ hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_gather_cells_ld(const int32_t *list, const int64_t *count, int64_t cap, int64_t ldc,
+                                  const double *T, const double *p, const double *Y, int64_t ldY,
+                                  int K, double *cT, double *cp, double *cY, hipStream_t s)
+{
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_cells_kernel, dim3(blocks_for(cap, 256)), dim3(256), 0, s, list, count,
+                       cap, ldc, T, p, Y, ldY, K, cT, cp, cY);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_cells(const int32_t *list, const int64_t *count, int64_t cap,
                                const double *T, const double *p, const double *Y, int64_t ldY,
                                int K, double *cT, double *cp, double *cY, hipStream_t s)
 {
+    return launch_gather_cells_ld(list, count, cap, cap, T, p, Y, ldY, K, cT, cp, cY, s);
+}
+
+hipError_t launch_scatter_cells_ld(const int32_t *list, const int64_t *count, int64_t cap, int64_t ldc,
+                                   const double *cT, const double *cY, const int32_t *cstatus, int K,
+                                   double *T, double *Y, int64_t ldY, int32_t *status, hipStream_t s)
+{
     if (cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_cells_kernel, dim3(blocks_for(cap, 256)), dim3(256), 0, s, list, count,
-                       cap, T, p, Y, ldY, K, cT, cp, cY);
+    hipLaunchKernelGGL(scatter_cells_kernel, dim3(blocks_for(cap, 256)), dim3(256), 0, s, list, count,
+                       cap, ldc, cT, cY, cstatus, K, T, Y, ldY, status);
     return hipGetLastError();
 }
 
@@ -971,9 +997,12 @@ hipError_t launch_scatter_cells(const int32_t *list, const int64_t *count, int64
                                 const double *cT, const double *cY, const int32_t *cstatus, int K,
                                 double *T, double *Y, int64_t ldY, int32_t *status, hipStream_t s)
 {
-    if (cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scatter_cells_kernel, dim3(blocks_for(cap, 256)), dim3(256), 0, s, list, count,
-                       cap, cT, cY, cstatus, K, T, Y, ldY, status);
+    return launch_scatter_cells_ld(list, count, cap, cap, cT, cY, cstatus, K, T, Y, ldY, status, s);
+}
+
+hipError_t launch_sum_i64(const int64_t *v, int n, int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sum_i64_kernel, dim3(1), dim3(64), 0, s, v, n, out);
     return hipGetLastError();
 }
 

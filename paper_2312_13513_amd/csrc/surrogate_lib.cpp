@@ -81,6 +81,13 @@ struct chem_surr_s {
     DevBuf io;                        // encoded rows and outputs of the fused inference pass
     int64_t io_rows = 0;
     int64_t pass_rows = 0;            // rows per inference pass (0: the library's choice)
+    // inference: each pass's rejected cells are integrated on a second
+    // stream (default priority) while the later passes run; fork events
+    // (reused in turn: a wait binds to the record before it) and the join
+    hipStream_t side = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    DevBuf pcount;                    // per-pass fallback counts
+    int64_t pcount_len = 0;
 };
 
 namespace {
@@ -529,8 +536,15 @@ int create_surrogate(chem_mech mech, int32_t h1, int32_t h2, int32_t h3, bool pe
         rc = check_hip(hipMemcpy(s->coef_dev, cnt.data(), cnt.size() * sizeof(double), hipMemcpyHostToDevice),
                        "decode constants upload");
     s->norm.assign((size_t)norm_len(s), 0.0);
+    if (rc == CHEM_OK)
+        rc = check_hip(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking), "fallback stream");
+    for (int i = 0; i < 4 && rc == CHEM_OK; i++)
+        rc = check_hip(hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming), "fallback events");
     hipSetDevice(prev);
     if (rc != CHEM_OK) {
+        for (hipEvent_t e : s->ev)
+            if (e) hipEventDestroy(e);
+        if (s->side) hipStreamDestroy(s->side);
         hipFree(s->block);
         delete s;
         return rc;
@@ -567,6 +581,13 @@ void chem_free_surrogate(chem_surr s)
     s->act.release();
     s->fb.release();
     s->io.release();
+    s->pcount.release();
+    if (s->side) {
+        hipStreamSynchronize(s->side);
+        hipStreamDestroy(s->side);
+    }
+    for (hipEvent_t e : s->ev)
+        if (e) hipEventDestroy(e);
     if (s->block) hipFree(s->block);
     hipSetDevice(prev);
     delete s;
@@ -836,10 +857,22 @@ int chem_surrogate_infer(chem_surr s, double *T, const double *p, double *Y, int
     Fallback &fb = w.fb;
     float *noU[3] = {nullptr, nullptr, nullptr};
     int64_t *count = fallback_count ? fallback_count : s->scalars;
-    rc = check_hip(chem::launch_zero_i64(count, 1, st), "zero");
+    // per-pass counts: pass q's rejected cells go to fb.list[r0 ..] (at most
+    // its rr rows), gathered into fb.T/p/Y/status[r0 ..] and integrated on
+    // the side stream as soon as the pass is applied
+    const int64_t npass = (n + chunk - 1) / chunk;
+    if (npass > s->pcount_len) {
+        rc = s->pcount.grow(carve_size<int64_t>(npass), st);
+        if (rc != CHEM_OK) return rc;
+        s->pcount_len = npass;
+    }
+    int64_t *pc = (int64_t *)s->pcount.p;
+    rc = check_hip(chem::launch_zero_i64(pc, (int)npass, st), "zero");
     if (rc != CHEM_OK) return rc;
     const chem::ApplyArgs aa = apply_args(s, c);
-    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+    hipStream_t sd = s->side;
+    int64_t q = 0;
+    for (int64_t r0 = 0; r0 < n; r0 += chunk, q++) {
         const int rr = (int)(n - r0 < chunk ? n - r0 : chunk);
         hipError_t e = chem::launch_encode(T + r0, p + r0, Y + r0, ldY, rr, K, kInPad, s->norm_dev, Xc, st);
         if (e == hipSuccess)
@@ -847,19 +880,29 @@ int chem_surrogate_infer(chem_surr s, double *T, const double *p, double *Y, int
                       : forward(s, Xc, rr, a.H, noU, OUTc, s->nout_pad, st, true);
         if (e == hipSuccess)
             e = chem::launch_apply(aa, T + r0, p + r0, Y + r0, ldY, rr, r0, OUTc, s->nout_pad,
-                                   mask ? mask + r0 : nullptr, status ? status + r0 : nullptr, fb.list,
-                                   count, st);
+                                   mask ? mask + r0 : nullptr, status ? status + r0 : nullptr, fb.list + r0,
+                                   pc + q, st);
         if (e != hipSuccess) return check_hip(e, "surrogate pass");
+        hipEvent_t fork = s->ev[q % 3];
+        rc = check_hip(hipEventRecord(fork, st), "fork event");
+        if (rc == CHEM_OK) rc = check_hip(hipStreamWaitEvent(sd, fork, 0), "fork wait");
+        if (rc == CHEM_OK)
+            rc = check_hip(chem::launch_gather_cells_ld(fb.list + r0, pc + q, rr, fb.cap, T, p, Y, ldY, K,
+                                                        fb.T + r0, fb.p + r0, fb.Y + r0, sd),
+                           "gather");
+        if (rc == CHEM_OK)
+            rc = chem_host::integrate_cells(s->mech, fb.T + r0, fb.p + r0, fb.Y + r0, fb.cap, rr, dt, opts,
+                                            fb.status + r0, nullptr, sd, pc + q);
+        if (rc == CHEM_OK)
+            rc = check_hip(chem::launch_scatter_cells_ld(fb.list + r0, pc + q, rr, fb.cap, fb.T + r0, fb.Y + r0,
+                                                         fb.status + r0, K, T, Y, ldY, status, sd),
+                           "scatter");
+        if (rc != CHEM_OK) return rc;
     }
-    rc = check_hip(chem::launch_gather_cells(fb.list, count, fb.cap, T, p, Y, ldY, K, fb.T, fb.p, fb.Y, st),
-                   "gather");
-    if (rc != CHEM_OK) return rc;
-    rc = chem_host::integrate_cells(s->mech, fb.T, fb.p, fb.Y, fb.cap, fb.cap, dt, opts, fb.status, nullptr, st,
-                                    count);
-    if (rc != CHEM_OK) return rc;
-    return check_hip(chem::launch_scatter_cells(fb.list, count, fb.cap, fb.T, fb.Y, fb.status, K, T, Y, ldY,
-                                                status, st),
-                     "scatter");
+    rc = check_hip(hipEventRecord(s->ev[3], sd), "join event");
+    if (rc == CHEM_OK) rc = check_hip(hipStreamWaitEvent(st, s->ev[3], 0), "join wait");
+    if (rc == CHEM_OK) rc = check_hip(chem::launch_sum_i64(pc, (int)npass, count, st), "fallback count");
+    return rc;
 }
 
 int chem_surrogate_grad(chem_surr s, const uint16_t *X, const float *Yt, int64_t ldt, int64_t n,
