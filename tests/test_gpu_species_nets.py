@@ -173,3 +173,64 @@ def test_species_training_and_serving(torch, mechs, mech_dir, tmp_path):
     with pytest.raises(chem.ChemError, match="one network"):
         s.forward(X, out, path=2)
     s.close()
+
+
+def test_species_full_size_sampled(torch, mechs):
+    """The benchmark's configuration: 9 networks of 1600 / 800 / 400 units
+    (padded to 1600 / 832 / 448) on 262,144 rows (the flame64 field's size,
+    128 x 128 tiles).  Rows are independent and every output element sees the
+    same MFMA sequence whatever the tile, so 96 seeded rows of the full-size
+    output must equal, bit for bit, a 96-row forward of those rows (64 x 64
+    tiles); that small forward is checked layer by layer against the
+    oracle as in test_species_forward_parity."""
+    from chemgen.fields import seeded_sample
+    from chemgen.surrogate_data import split_species_params
+    from oracle import surrogate as S
+    from paper_2312_13513_amd import chem
+    K, h, rows = 9, (1600, 800, 400), 262144
+    hp = [(w + 63) // 64 * 64 for w in h]
+    s, flat = _species_surr(chem, mechs["M9"], K, h, 61)
+    rng = np.random.default_rng(62)
+    x = S.to_bf16(rng.normal(0, 1, (rows, K + 2)).astype(np.float32))
+    Xb = np.zeros((rows, 64), dtype=np.uint16)
+    Xb[:, :K + 2] = S.bf16_bits(x)
+    X = torch.tensor(Xb.view(np.int16), device="cuda:0")
+    out = torch.zeros((rows, s.nout_pad), dtype=torch.float32, device="cuda:0")
+    s.forward(X, out)
+    idx = seeded_sample(rows, 96, 63)
+    Xs = X[torch.tensor(idx, device="cuda:0")].contiguous()
+    H = [torch.zeros((idx.size, K * w), dtype=torch.int16, device="cuda:0") for w in hp]
+    out_s = torch.zeros((idx.size, s.nout_pad), dtype=torch.float32, device="cuda:0")
+    s.forward_trace(Xs, *H, out_s)
+    torch.cuda.synchronize()
+    full = out.cpu().numpy()[idx]
+    small = out_s.cpu().numpy()
+    assert np.array_equal(full, small), "full-size rows differ from the same rows run alone"
+    Hh = [_bf16_vals(t) for t in H]
+    nets = split_species_params(flat, K, h)
+    xs = x[idx]
+    n_act = n_flip = 0
+    for g in range(K):
+        params_bf = [(S.to_bf16(W.astype(np.float32)), b) for W, b in nets[g]]
+        hin = xs
+        for li in range(3):
+            W, b = params_bf[li]
+            u = hin @ W.T + b
+            tol_u = (W.shape[1] + 1) * 2.0 ** -24 * (np.abs(hin) @ np.abs(W).T + np.abs(b))
+            gl = S.gelu(u)
+            tol = 2.0 * (GELU_LIP * tol_u + GELU_REL * np.abs(gl)) + 1e-37
+            got = Hh[li][:, g * hp[li]:g * hp[li] + h[li]]
+            exact = S.to_bf16(gl)
+            lo, hi = S.to_bf16(gl - tol), S.to_bf16(gl + tol)
+            flip = got != exact
+            n_act += got.size
+            n_flip += int(flip.sum())
+            assert np.all(~flip | ((got >= lo) & (got <= hi) & (lo != hi))), (g, li)
+            hin = got
+        W, b = params_bf[3]
+        ref = (hin @ W.T + b)[:, 0]
+        tol = 2.0 * (W.shape[1] + 1) * 2.0 ** -24 * ((np.abs(hin) @ np.abs(W).T)[:, 0] + np.abs(b[0])) + 1e-30
+        assert np.all(np.abs(small[:, g] - ref) <= tol), g
+    _say(f"[species full size] {rows} rows, {idx.size} sampled: {n_act} activations, {n_flip} rounding flips")
+    assert n_flip <= max(2, 0.02 * n_act)
+    s.close()
