@@ -277,7 +277,8 @@ const char *chem_last_error(void);
  * A call that would have to grow the workspace while its stream is being
  * captured fails with CHEM_EINVAL instead; buffers replaced by growth stay
  * allocated until the handle is freed, so graphs captured earlier stay
- * valid.
+ * valid.  The workspace belongs to the handle: calls on one surrogate
+ * handle must not overlap (issue them on one stream, or order them).
  * ------------------------------------------------------------------------ */
 typedef struct chem_surr_s *chem_surr;
 
@@ -381,7 +382,11 @@ int chem_surrogate_apply(chem_surr surr, double *T, const double *p, double *Y, 
  * chem_integrate (opts) over dt.  mask (nullable): 1 for fallback cells.
  * status (nullable): integrator status of fallback cells, 0 elsewhere.
  * fallback_count (nullable, device int64): number of fallback cells.
- * dt must equal the dt of the normalisation. */
+ * dt must equal the dt of the normalisation.  The cells run in passes; the
+ * rejected cells of each pass are integrated on the handle's own second
+ * stream (default priority) while the later passes run, joined back into
+ * hip_stream by events before the call's last kernel, so the call stays
+ * asynchronous and capturable. */
 int chem_surrogate_infer(chem_surr surr, double *T, const double *p, double *Y, int64_t ldY,
                          int64_t n, double dt, const chem_opts *opts,
                          const chem_surr_checks *checks, int32_t *mask, int32_t *status,
