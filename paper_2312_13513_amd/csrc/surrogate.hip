@@ -159,7 +159,7 @@ __device__ __forceinline__ void gemm_store(const GemmArgs &g, int m, int n, floa
 // forward kernel) give the same bits.  The 128 tile does four times the
 // MFMA work per barrier pair and per staged byte.
 template <int TM>
-__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 128 ? 4 : 1))) gemm_bf16_kernel(GemmArgs g)
 {
     constexpr int WT = TM / 32;              // MFMA tiles per wave and dimension
     constexpr int KB = TM == 128 ? 64 : 32;  // K per staged step (two MFMA K steps at the 128 tile)
