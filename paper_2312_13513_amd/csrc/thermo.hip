@@ -147,7 +147,7 @@ __device__ __forceinline__ void load_yr(const double *__restrict__ Y, int64_t ld
 // registers; otherwise the outer loops run at run time and take X_k, y_k and
 // s_k again from the inputs (a run-time index cannot address registers).
 // UO is chosen per phase (see launch_transport).
-template <int KM, bool UO, int MODE>
+template <int KM, bool UO, int MODE, bool EX = false>
 __global__ void __launch_bounds__(kThermoBlock) transport_kernel(TrView v, const double *__restrict__ T,
                                                                  const double *__restrict__ p,
                                                                  const double *__restrict__ Y, int64_t ldY,
@@ -419,7 +419,7 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kThermoBlock - 1) / kThe
 // kernel's registers would cut occupancy to one or two waves per SIMD), the
 // diffusion phase unrolled at 24 (its triangular pair loop needs
 // compile-time indices) and both phases with run-time outer loops beyond.
-#define CHEM_TR_BOUNDS(X) X(12) X(16) X(24) X(36) X(48) X(64)
+#define CHEM_TR_BOUNDS(X) X(9) X(12) X(16) X(24) X(36) X(48) X(64)
 
 // The kernel bound KM for K species (the tables' padded row count).
 int tr_bound(int K)
@@ -440,12 +440,23 @@ hipError_t launch_transport_km(const TrView &v, const double *T, const double *p
 {
     const dim3 g(blocks_for(n)), b(kThermoBlock);
     if constexpr (KM <= 16) {
+        const bool ex = v.K == KM;
+#define CHEM_TR_UO(MODE)                                                                                      \
+    do {                                                                                                     \
+        if (ex)                                                                                              \
+            hipLaunchKernelGGL((transport_kernel<KM, true, MODE, true>), g, b, 0, st, v, T, p, Y, ldY, n, mu,  \
+                               lam, D, ldD);                                                                 \
+        else                                                                                                 \
+            hipLaunchKernelGGL((transport_kernel<KM, true, MODE, false>), g, b, 0, st, v, T, p, Y, ldY, n, mu, \
+                               lam, D, ldD);                                                                 \
+    } while (0)
         if (mu && D)
-            hipLaunchKernelGGL((transport_kernel<KM, true, 3>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam, D, ldD);
+            CHEM_TR_UO(3);
         else if (mu)
-            hipLaunchKernelGGL((transport_kernel<KM, true, 1>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam, D, ldD);
+            CHEM_TR_UO(1);
         else
-            hipLaunchKernelGGL((transport_kernel<KM, true, 2>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam, D, ldD);
+            CHEM_TR_UO(2);
+#undef CHEM_TR_UO
     } else {
         if (mu)
             hipLaunchKernelGGL((transport_kernel<KM, false, 1>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam, D, ldD);
