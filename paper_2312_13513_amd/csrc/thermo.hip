@@ -374,9 +374,9 @@ __global__ void __launch_bounds__(kThermoBlock) h_cp_kernel(const double *__rest
 // below tol; after max_iter steps without that, T = NaN and iters =
 // max_iter + 1.  The mixture coefficients are rebuilt only when T crosses a
 // range boundary.  cp is the mixture cp at the result.
-template <int KM>
+template <int KM, bool EX>
 __global__ void __launch_bounds__(kThermoBlock) t_from_h_kernel(const double *__restrict__ species,
-                                                                const double *__restrict__ invW, int K, MidSet ms,
+                                                                const double *__restrict__ invW, int Kr, MidSet ms,
                                                                 const double *__restrict__ h,
                                                                 const double *__restrict__ Y, int64_t ldY,
                                                                 int64_t n, double *__restrict__ T,
@@ -386,6 +386,7 @@ __global__ void __launch_bounds__(kThermoBlock) t_from_h_kernel(const double *__
 {
     const int64_t i = (int64_t)blockIdx.x * kThermoBlock + threadIdx.x;
     if (i >= n) return;
+    const int K = EX ? KM : Kr;   // EX: exactly KM species, guards known at compile time
     double yr[KM], M[10];
     load_yr<KM>(Y, ldY, i, K, invW, yr);
     const double h0 = h[i] * (1.0 / kRu);
@@ -497,8 +498,12 @@ hipError_t launch_t_from_h(const DevMechView &m, const MidSet &ms, const double 
 {
 #define CHEM_TN_CASE(KM)                                                                                 \
     if (m.K <= KM) {                                                                                          \
-        hipLaunchKernelGGL((t_from_h_kernel<KM>), dim3(blocks_for(n)), dim3(kThermoBlock), 0, st, m.species, \
-                           m.invW, m.K, ms, h, Y, ldY, n, T, cp, iters, max_iter, tol);                       \
+        if (m.K == KM)                                                                                        \
+            hipLaunchKernelGGL((t_from_h_kernel<KM, true>), dim3(blocks_for(n)), dim3(kThermoBlock), 0, st,  \
+                               m.species, m.invW, m.K, ms, h, Y, ldY, n, T, cp, iters, max_iter, tol);        \
+        else                                                                                                  \
+            hipLaunchKernelGGL((t_from_h_kernel<KM, false>), dim3(blocks_for(n)), dim3(kThermoBlock), 0, st, \
+                               m.species, m.invW, m.K, ms, h, Y, ldY, n, T, cp, iters, max_iter, tol);        \
         return hipGetLastError();                                                                             \
     }
     CHEM_TR_BOUNDS(CHEM_TN_CASE)
