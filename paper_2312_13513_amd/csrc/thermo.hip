@@ -415,12 +415,13 @@ __global__ void __launch_bounds__(kThermoBlock) t_from_h_kernel(const double *__
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kThermoBlock - 1) / kThermoBlock); }
 
 // Dispatch on the smallest compile-time bound that holds K.  The bounds up to
-// 16 unroll every loop and run both phases in one kernel; from 24 on the two
+// 16 unroll every loop and run both phases in one kernel; 20 unrolls them in
+// two kernels (the size of the paper's CH4 mechanism); from 24 on the two
 // phases are separate kernels (the segments of Section 3.2: the fused
 // kernel's registers would cut occupancy to one or two waves per SIMD), the
 // diffusion phase unrolled at 24 (its triangular pair loop needs
 // compile-time indices) and both phases with run-time outer loops beyond.
-#define CHEM_TR_BOUNDS(X) X(9) X(12) X(16) X(24) X(36) X(48) X(64)
+#define CHEM_TR_BOUNDS(X) X(9) X(12) X(16) X(20) X(24) X(36) X(48) X(64)
 
 // The kernel bound KM for K species (the tables' padded row count).
 int tr_bound(int K)
@@ -458,6 +459,26 @@ hipError_t launch_transport_km(const TrView &v, const double *T, const double *p
         else
             CHEM_TR_UO(2);
 #undef CHEM_TR_UO
+    } else if constexpr (KM <= 20) {
+        // unrolled, in two kernels (the fused one would hold five species
+        // vectors: two waves per SIMD)
+        const bool ex = v.K == KM;
+        if (mu) {
+            if (ex)
+                hipLaunchKernelGGL((transport_kernel<KM, true, 1, true>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam,
+                                   D, ldD);
+            else
+                hipLaunchKernelGGL((transport_kernel<KM, true, 1, false>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam,
+                                   D, ldD);
+        }
+        if (D) {
+            if (ex)
+                hipLaunchKernelGGL((transport_kernel<KM, true, 2, true>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam,
+                                   D, ldD);
+            else
+                hipLaunchKernelGGL((transport_kernel<KM, true, 2, false>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam,
+                                   D, ldD);
+        }
     } else {
         if (mu)
             hipLaunchKernelGGL((transport_kernel<KM, false, 1>), g, b, 0, st, v, T, p, Y, ldY, n, mu, lam, D, ldD);

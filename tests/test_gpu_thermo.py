@@ -36,10 +36,9 @@ def _mech(name):
     from chemgen.mechanism import make_mechanism, standard_mechanism
     if name == "K64":
         return make_mechanism(seed=78, K=64, R=150, E=4)
-    if name == "K12":
-        return make_mechanism(seed=76, K=12, R=30, E=3)
-    if name == "K14":
-        return make_mechanism(seed=77, K=14, R=30, E=3)
+    if name.startswith("K") and name[1:].isdigit():
+        k = int(name[1:])
+        return make_mechanism(seed=70 + k, K=k, R=max(12, 2 * k), E=3 if k < 30 else 4)
     return standard_mechanism(name)
 
 
@@ -94,12 +93,13 @@ def _transport_check(tag, mech, fits, T, p, Y, mu, lam, D):
     assert np.all(np.isfinite(mu)) and np.all(np.isfinite(D))
 
 
-@pytest.mark.parametrize("name", ["M9", "H2R", "K12", "K14", "CH4R", "M35", "K64"])
+@pytest.mark.parametrize("name", ["K6", "M9", "H2R", "K11", "K12", "K14", "K16", "K18", "CH4R", "M35", "K64"])
 def test_transport_parity(torch, tmp_path, name):
     """Wilke viscosity, Mathur conductivity and mixture-averaged diffusion
     over 3,001 cells (several blocks and a ragged tail) with padded leading
-    dimensions, for K = 9, 12, 14, 20, 35, 64 (every kernel bound from 9 to
-    64, the bounds 9 and 12 with K equal to the bound, 16 with padding)."""
+    dimensions, for K = 6 .. 64: every kernel bound from 9 to 64, the
+    unrolled bounds (9, 12, 16, 20) both with K equal to the bound and with
+    padding."""
     from chemgen.transport import transport_fits
     mech, m, _ = _open(tmp_path, name)
     fits = transport_fits(mech, 21)
@@ -124,7 +124,7 @@ def test_transport_parity(torch, tmp_path, name):
     m.close()
 
 
-@pytest.mark.parametrize("name", ["M9", "H2R", "K14", "CH4R", "M35", "K64"])
+@pytest.mark.parametrize("name", ["K6", "M9", "H2R", "K14", "K18", "CH4R", "M35", "K64"])
 def test_h_cp_and_T_from_h_parity(torch, tmp_path, name, oracle_lib):
     """Mixture h and cp at T, then T back from h by Newton from guesses
     150 K away (across the NASA range boundary for some cells), with cp and
