@@ -933,9 +933,11 @@ def run_props(args):
                 "kernel_ms": secs * 1e3, "bytes_per_launch": nbytes, "flops_per_launch": flops,
                 "hbm_frac": nbytes / secs / 8e12}
 
-    km = 12 if K <= 12 else 16
-    r_tr = roof(flops_tr, bytes_tr, trans_s, f"transport_kernel<{km},true,3>")
-    r_nw = roof(flops_nw, bytes_nw, newton_s, f"t_from_h_kernel<{km}>")
+    # the library's kernel bound for K species (exact when K equals it)
+    km = next(b for b in (9, 12, 16, 20, 24, 36, 48, 64) if K <= b)
+    ex = "true" if km == K else "false"
+    r_tr = roof(flops_tr, bytes_tr, trans_s, f"transport_kernel<{km},true,3,{ex}>")
+    r_nw = roof(flops_nw, bytes_nw, newton_s, f"t_from_h_kernel<{km},{ex}>")
     dominant = r_tr if trans_s >= newton_s else r_nw
     result = {
         "metric": "thermo/transport field properties (T from h, mu, lambda, D), cells/s",
