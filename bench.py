@@ -659,11 +659,13 @@ def run_laplacian(args):
     nf, nc, nb = m.nfaces, m.ncells, m.nbfaces
     bytes_asm = nf * 48 + nc * 16 + nb * 48
     bytes_csr = nf * 40 + nc * 32 + nb * 20
-    # direct: face arrays, positions, gamma once per cell, both CSR writes;
-    # per cell the row's entries (read back), row_ptr, diag_pos, the diagonal
-    # and rhs writes; boundary faces' data once
+    # direct: the face pass reads each face's two cells and geometry and
+    # writes its coefficient; the entry pass reads every entry's face slot
+    # and writes its value, reads the coefficients; per cell gamma, row_ptr,
+    # bnd_ptr and the rhs write; boundary faces' index, type and data.  Every
+    # array counted once.
     nnz = g.nnz
-    bytes_dir = nf * (4 + 4 + 24 + 8 + 16) + nc * (8 + 4 + 4 + 4 + 8 + 8) + (nnz - nc) * 8 + nb * (4 + 4 + 32)
+    bytes_dir = nf * (8 + 24 + 8 + 8) + nnz * (4 + 8) + nc * (8 + 4 + 4 + 8) + nb * (4 + 4 + 32)
     result = {
         "metric": "implicit Laplacian assembly into CSR, cells/s",
         "value": nc * args.steps / wall, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
@@ -674,8 +676,8 @@ def run_laplacian(args):
                    "csr_entries": nnz},
         "roofline": {"bound": "hbm", "achieved": bytes_dir / dir_s / 1e9, "peak": 8000.0, "unit": "GB/s",
                      "frac": bytes_dir / dir_s / 1e9 / 8000.0,
-                     "traffic": traffic_for("laplacian128", "csr_assemble_faces_kernel+csr_assemble_cells_kernel"),
-                     "kernel": "csr_assemble_faces_kernel + csr_assemble_cells_kernel (direct CSR assembly)",
+                     "traffic": traffic_for("laplacian128", "face_coeff_kernel+csr_assemble_entries_kernel"),
+                     "kernel": "face_coeff_kernel + csr_assemble_entries_kernel (direct CSR assembly)",
                      "kernel_ms": dir_s * 1e3, "bytes_per_launch": bytes_dir},
         "ldu_path": {"cells_per_s": nc * args.steps / wall2, "ms_per_step": wall2 / args.steps * 1e3,
                      "assembly": {"kernel": "ldu_internal_kernel (atomic diagonal) + patch kernels",

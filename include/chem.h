@@ -495,12 +495,14 @@ int chem_ldu_to_csr(chem_ldu mesh, const double *lower, const double *upper, con
                     const double *internal, const double *boundary, double *csr_val, double *rhs,
                     void *hip_stream);
 /* The same matrix and right-hand side assembled straight into CSR, with no
- * ldu arrays and no atomics: each internal face writes gamma_f delta_f
- * |S_f| to its two off-diagonal places, then each cell's diagonal is minus
- * the sum of its row's off-diagonal entries (in column order) plus its
- * boundary faces' internal coefficients, and rhs its boundary coefficients
+ * ldu arrays and no atomics: every off-diagonal entry is gamma_f delta_f
+ * |S_f| of the face it comes from (the same bits as chem_ldu_laplacian's
+ * upper and lower), each diagonal entry minus the sum of its row's
+ * off-diagonal entries (in column order) plus its boundary faces' internal
+ * coefficients, and rhs its boundary coefficients
  * (deterministic: the same bits every call).  Device arrays; enqueued on the
- * stream; allocates nothing. */
+ * stream; allocates nothing.  The face coefficients pass through a work
+ * array of the mesh handle: calls on one mesh must not overlap. */
 int chem_ldu_laplacian_csr(chem_ldu mesh, const double *gamma_c, const double *gamma_b, const double *psi_b,
                            double *csr_val, double *rhs, void *hip_stream);
 /* Copies the CSR pattern: row_ptr (ncells + 1) and col (CSR entries), device. */

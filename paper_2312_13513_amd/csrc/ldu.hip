@@ -2,11 +2,11 @@
 // with atomic accumulation of the diagonal (paper Section 3.1, Algorithm 1)
 // and its conversion to CSR (the ldu/CSR figure), for meshes in
 // owner/neighbour addressing; and the same matrix assembled straight into
-// CSR without atomics (each face writes its two entries, each cell sums its
-// row), which on a GPU of several dies with their own L2 avoids the atomic
-// traffic between them.  Both are HBM-bound: one thread per face or
-// per cell, face arrays read once in face order (coalesced), the diagonal
-// accumulated with FP64 atomics that stay in L2.  The CSR pattern and the
+// CSR without atomics (one thread per CSR entry), which on a GPU of several
+// dies with their own L2 avoids the atomic traffic between them and writes
+// the value array in order.  All are HBM-bound: one thread
+// per face or per cell, face arrays read in face order (coalesced), the
+// diagonal of the ldu path accumulated with FP64 atomics that stay in L2.  The CSR pattern and the
 // position of every ldu coefficient in it are built once per mesh on the
 // host, so a conversion is a scatter of the face values plus one pass over
 // the cells.
@@ -34,6 +34,8 @@ struct chem_ldu_s {
     const int32_t *upper_pos = nullptr, *lower_pos = nullptr, *diag_pos = nullptr;
     const int32_t *bnd_ptr = nullptr, *bnd_face = nullptr, *row_ptr = nullptr, *col = nullptr;
     const int32_t *btype = nullptr;   // patch type of every boundary face
+    const int32_t *ent_face = nullptr;   // face of every CSR entry; -(row + 1) on the diagonal
+    double *coef = nullptr;              // face coefficients of the direct CSR assembly (work space)
 };
 
 namespace chem {
@@ -50,7 +52,8 @@ __global__ void __launch_bounds__(kLduBlock) ldu_zero_kernel(double *__restrict_
 }
 
 // The coefficient of an internal face: gamma_f by linear interpolation,
-// times delta_f |S_f|.
+// times delta_f |S_f| (every kernel forms it here: the same bits on every
+// path).
 __device__ __forceinline__ double face_coeff(int64_t f, const int32_t *__restrict__ owner,
                                              const int32_t *__restrict__ neighbour, const double *__restrict__ weight,
                                              const double *__restrict__ delta, const double *__restrict__ mag_sf,
@@ -79,48 +82,105 @@ __global__ void __launch_bounds__(kLduBlock) ldu_internal_kernel(
     atomicAdd(&diag[neighbour[f]], -c);
 }
 
-// Assembly straight into CSR, without atomics: each face writes its
-// coefficient to both places it has in the rows ...
-__global__ void __launch_bounds__(kLduBlock) csr_assemble_faces_kernel(
+// Assembly straight into CSR, without atomics, in two passes.  First every
+// internal face's coefficient, in face order (all reads and writes
+// coalesced) ...
+__global__ void __launch_bounds__(kLduBlock) face_coeff_kernel(
     int64_t nfaces, const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
     const double *__restrict__ weight, const double *__restrict__ delta, const double *__restrict__ mag_sf,
-    const double *__restrict__ gamma_c, const int32_t *__restrict__ upper_pos, const int32_t *__restrict__ lower_pos,
-    double *__restrict__ val)
+    const double *__restrict__ gamma_c, double *__restrict__ coef)
 {
     const int64_t f = (int64_t)blockIdx.x * kLduBlock + threadIdx.x;
     if (f >= nfaces) return;
-    const double c = face_coeff(f, owner, neighbour, weight, delta, mag_sf, gamma_c);
-    val[upper_pos[f]] = c;
-    val[lower_pos[f]] = c;
+    coef[f] = face_coeff(f, owner, neighbour, weight, delta, mag_sf, gamma_c);
 }
 
-// ... then each cell sums its row's off-diagonal entries (contiguous, in
-// column order: the same sum every call) into the diagonal and adds its
-// boundary faces (fixed value: -gamma_b |S_b| delta_b to the diagonal,
-// gamma_b |S_b| delta_b psi_b to the right-hand side; zero gradient nothing).
-__global__ void __launch_bounds__(kLduBlock) csr_assemble_cells_kernel(
-    int64_t ncells, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ diag_pos,
-    const int32_t *__restrict__ bnd_ptr, const int32_t *__restrict__ bnd_face, const int32_t *__restrict__ btype,
-    const double *__restrict__ bdelta, const double *__restrict__ bmag_sf, const double *__restrict__ gamma_b,
-    const double *__restrict__ psi_b, double *__restrict__ val, double *__restrict__ rhs)
+constexpr int kHalo = 16;                       // entries beyond each end of a block kept in LDS
+constexpr int kEntPer = 4;                      // entries per thread
+constexpr int kEntBlock = kLduBlock * kEntPer;  // entries per block
+
+// ... then the CSR entries in blocks of kEntBlock, kEntPer per thread (all
+// their loads issued before the first wait), so the entry arrays are read
+// and the values written in order (each once): an off-diagonal entry takes the
+// coefficient of the face it comes from (the face's index stored beside the
+// entry).  The diagonal entry (its slot holds -(row + 1)) is minus the sum
+// of its row's off-diagonal entries in column order, from the block's LDS
+// copy (which reaches kHalo entries into the neighbouring blocks; an entry
+// of a longer row beyond that is read from the coefficient array: the same
+// bits), plus the row's fixed-value boundary faces (-gamma_b |S_b| delta_b;
+// gamma_b |S_b| delta_b psi_b to the right-hand side; a zero-gradient face
+// adds nothing).
+__global__ void __launch_bounds__(kLduBlock) csr_assemble_entries_kernel(
+    int64_t nnz, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ ent_face,
+    const double *__restrict__ coef, const int32_t *__restrict__ bnd_ptr, const int32_t *__restrict__ bnd_face,
+    const int32_t *__restrict__ btype, const double *__restrict__ bdelta, const double *__restrict__ bmag_sf,
+    const double *__restrict__ gamma_b, const double *__restrict__ psi_b, double *__restrict__ val,
+    double *__restrict__ rhs)
 {
-    const int64_t i = (int64_t)blockIdx.x * kLduBlock + threadIdx.x;
-    if (i >= ncells) return;
-    const int dp = diag_pos[i];
-    double s = 0.0;
-    for (int j = row_ptr[i]; j < row_ptr[i + 1]; j++)
-        if (j != dp) s += val[j];
-    double d = -s, r = 0.0;
-    for (int j = bnd_ptr[i]; j < bnd_ptr[i + 1]; j++) {
-        const int b = bnd_face[j];
-        if (btype[b] == 0) {
-            const double c = gamma_b[b] * bmag_sf[b] * bdelta[b];
-            d += -c;
-            r += c * psi_b[b];
+    __shared__ double sv[kEntBlock + 2 * kHalo];
+    const int t = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * kEntBlock;
+    const int64_t lo = j0 - kHalo, hi = j0 + kEntBlock + kHalo;
+    int f[kEntPer], b[kEntPer], e[kEntPer], bb[kEntPer], be[kEntPer];
+#pragma unroll
+    for (int q = 0; q < kEntPer; q++) {
+        const int64_t j = j0 + q * kLduBlock + t;
+        f[q] = j < nnz ? ent_face[j] : 0;
+    }
+    // halo entries: the threads at the block's two ends take one each
+    const int hs = t < kHalo ? t : (t >= kLduBlock - kHalo ? t + kEntBlock + 2 * kHalo - kLduBlock : -1);
+    const int64_t h = lo + hs;
+    const int fh = (hs >= 0 && h >= 0 && h < nnz) ? ent_face[h] : -1;
+    // the diagonals' row and boundary extents, loaded beside the coefficients
+#pragma unroll
+    for (int q = 0; q < kEntPer; q++) {
+        const int64_t j = j0 + q * kLduBlock + t;
+        b[q] = e[q] = bb[q] = be[q] = 0;
+        if (j < nnz && f[q] < 0) {
+            const int i = -(f[q] + 1);
+            b[q] = row_ptr[i];
+            e[q] = row_ptr[i + 1];
+            bb[q] = bnd_ptr[i];
+            be[q] = bnd_ptr[i + 1];
         }
     }
-    val[dp] = d;
-    rhs[i] = r;
+    double v[kEntPer];
+#pragma unroll
+    for (int q = 0; q < kEntPer; q++) {
+        const int64_t j = j0 + q * kLduBlock + t;
+        v[q] = (j < nnz && f[q] >= 0) ? coef[f[q]] : 0.0;
+        sv[kHalo + q * kLduBlock + t] = v[q];
+    }
+    if (hs >= 0) sv[hs] = fh >= 0 ? coef[fh] : 0.0;
+    __syncthreads();
+    // every value is written once, after the diagonals are known: each store
+    // covers whole lines of the value array
+#pragma unroll
+    for (int q = 0; q < kEntPer; q++) {
+        const int64_t j = j0 + q * kLduBlock + t;
+        if (j >= nnz) continue;
+        if (f[q] >= 0) {
+            val[j] = v[q];
+            continue;
+        }
+        const int i = -(f[q] + 1);
+        double s = 0.0;
+        for (int k = b[q]; k < e[q]; k++) {
+            if (k == j) continue;
+            s += (k >= lo && k < hi) ? sv[k - lo] : coef[ent_face[k]];
+        }
+        double d = -s, r = 0.0;
+        for (int k = bb[q]; k < be[q]; k++) {
+            const int bf = bnd_face[k];
+            if (btype[bf] == 0) {
+                const double c = gamma_b[bf] * bmag_sf[bf] * bdelta[bf];
+                d += -c;
+                r += c * psi_b[bf];
+            }
+        }
+        val[j] = d;
+        rhs[i] = r;
+    }
 }
 
 // One boundary patch (Algorithm 1, boundary loop: a launch per patch, the
@@ -264,6 +324,12 @@ int chem_ldu_create(int64_t ncells, int64_t nfaces, const int32_t *owner, const 
         upos[f] = row_ptr[o] + nlo[o] + 1 + ufill[o]++;
         col[upos[f]] = neighbour[f];
     }
+    std::vector<int32_t> entf(nnz);
+    for (int64_t i = 0; i < ncells; i++) entf[dpos[i]] = -(int32_t)i - 1;
+    for (int64_t f = 0; f < nfaces; f++) {
+        entf[lpos[f]] = (int32_t)f;
+        entf[upos[f]] = (int32_t)f;
+    }
     std::vector<int32_t> btype(nb);
     for (int32_t p = 0; p < npatches; p++)
         for (int64_t b = patch_start[p]; b < patch_start[p + 1]; b++) btype[b] = patch_type[p];
@@ -296,7 +362,8 @@ int chem_ldu_create(int64_t ncells, int64_t nfaces, const int32_t *owner, const 
         {lpos.data(), (size_t)nfaces * 4, 0}, {dpos.data(), (size_t)ncells * 4, 0},
         {bptr.data(), (size_t)(ncells + 1) * 4, 0}, {bface.data(), (size_t)nb * 4, 0},
         {row_ptr.data(), (size_t)(ncells + 1) * 4, 0}, {col.data(), (size_t)nnz * 4, 0},
-        {btype.data(), (size_t)nb * 4, 0}};
+        {btype.data(), (size_t)nb * 4, 0},      {entf.data(), (size_t)nnz * 4, 0},
+        {nullptr, (size_t)nfaces * 8, 0}};
     size_t total = 0;
     for (auto &p : parts) {
         p.off = total;
@@ -310,7 +377,7 @@ int chem_ldu_create(int64_t ncells, int64_t nfaces, const int32_t *owner, const 
         rc = fail(CHEM_ENOMEM, "mesh allocation failed");
     }
     for (auto &p : parts)
-        if (rc == CHEM_OK && p.bytes)
+        if (rc == CHEM_OK && p.bytes && p.src)
             rc = check_hip(hipMemcpy((char *)m->block + p.off, p.src, p.bytes, hipMemcpyHostToDevice), "mesh upload");
     (void)hipSetDevice(prev);
     if (rc != CHEM_OK) {
@@ -336,6 +403,8 @@ int chem_ldu_create(int64_t ncells, int64_t nfaces, const int32_t *owner, const 
     m->row_ptr = (const int32_t *)(base + parts[k++].off);
     m->col = (const int32_t *)(base + parts[k++].off);
     m->btype = (const int32_t *)(base + parts[k++].off);
+    m->ent_face = (const int32_t *)(base + parts[k++].off);
+    m->coef = (double *)(base + parts[k++].off);
     *out = m;
     return CHEM_OK;
 }
@@ -417,11 +486,11 @@ int chem_ldu_laplacian_csr(chem_ldu m, const double *gamma_c, const double *gamm
         return fail(CHEM_EINVAL, "arrays must be device pointers");
     hipStream_t st = (hipStream_t)stream;
     if (m->nfaces)
-        hipLaunchKernelGGL(chem::csr_assemble_faces_kernel, dim3(chem::ldu_blocks(m->nfaces)), dim3(chem::kLduBlock),
-                           0, st, m->nfaces, m->owner, m->neighbour, m->weight, m->delta, m->mag_sf, gamma_c,
-                           m->upper_pos, m->lower_pos, csr_val);
-    hipLaunchKernelGGL(chem::csr_assemble_cells_kernel, dim3(chem::ldu_blocks(m->ncells)), dim3(chem::kLduBlock), 0,
-                       st, m->ncells, m->row_ptr, m->diag_pos, m->bnd_ptr, m->bnd_face, m->btype, m->bdelta,
+        hipLaunchKernelGGL(chem::face_coeff_kernel, dim3(chem::ldu_blocks(m->nfaces)), dim3(chem::kLduBlock), 0, st,
+                           m->nfaces, m->owner, m->neighbour, m->weight, m->delta, m->mag_sf, gamma_c, m->coef);
+    hipLaunchKernelGGL(chem::csr_assemble_entries_kernel, dim3((unsigned)((m->nnz + chem::kEntBlock - 1) / chem::kEntBlock)),
+                       dim3(chem::kLduBlock), 0,
+                       st, m->nnz, m->row_ptr, m->ent_face, m->coef, m->bnd_ptr, m->bnd_face, m->btype, m->bdelta,
                        m->bmag_sf, gamma_b, psi_b, csr_val, rhs);
     return check_hip(hipGetLastError(), "csr assembly launch");
 }

@@ -56,7 +56,9 @@ def _run(torch, m, seed):
     return (gc, gb, pb), out
 
 
-def _compare(tag, m, fields, out):
+def _compare(tag, m, fields, out, dbar=2.5e-15):
+    """dbar: the diagonal's bar relative to the sum of its terms' magnitudes
+    (two summation orders of n terms differ by at most 2 (n - 1) u of it)."""
     from oracle import laplacian as L
     lo, up, dg, ic, bc = L.assemble(m, *fields)
     rp, col, val, rhs = L.to_csr(m, lo, up, dg, ic, bc)
@@ -71,7 +73,7 @@ def _compare(tag, m, fields, out):
     dcsr = np.abs(out["val"] - val)
     _say(f"[{tag}] cells {m.ncells} faces {m.nfaces} nnz {rp[-1]}: upper {e_up:.1e} lower {e_lo:.1e} "
          f"diag {e_dg:.1e} boundary {e_b:.1e} csr max|d| {dcsr.max():.1e}")
-    assert e_up <= 1.5e-15 and e_lo <= 1.5e-15 and e_b <= 1e-15 and e_dg <= 2.5e-15
+    assert e_up <= 1.5e-15 and e_lo <= 1.5e-15 and e_b <= 1e-15 and e_dg <= dbar
     assert np.array_equal(out["lower"], out["upper"])
     # the CSR values are the GPU's own ldu values moved (off-diagonals
     # bitwise), diagonal entries and rhs within the diagonal's bar
@@ -82,7 +84,7 @@ def _compare(tag, m, fields, out):
     assert np.max(np.abs(out["val"][~diag_entry] - val[~diag_entry]) /
                   np.maximum(np.abs(val[~diag_entry]), 1e-300), initial=0.0) <= 1.5e-15
     dscale = gross + np.abs(val[diag_entry])
-    assert np.max(np.abs(out["val"][diag_entry] - val[diag_entry]) / np.maximum(dscale, 1e-300)) <= 2.5e-15
+    assert np.max(np.abs(out["val"][diag_entry] - val[diag_entry]) / np.maximum(dscale, 1e-300)) <= dbar
     # rhs: a sum of up to three boundary terms of either sign, measured
     # against the sum of their magnitudes
     rgross = np.zeros(m.ncells)
@@ -92,7 +94,7 @@ def _compare(tag, m, fields, out):
     # the ldu path (bitwise), diagonal and rhs within the same bars
     vd = out["val_direct"]
     assert np.array_equal(vd[~diag_entry], out["val"][~diag_entry])
-    assert np.max(np.abs(vd[diag_entry] - val[diag_entry]) / np.maximum(dscale, 1e-300)) <= 2.5e-15
+    assert np.max(np.abs(vd[diag_entry] - val[diag_entry]) / np.maximum(dscale, 1e-300)) <= dbar
     assert np.max(np.abs(out["rhs_direct"] - rhs) / np.maximum(rgross, 1e-300)) <= 2.5e-15
 
 
@@ -104,6 +106,55 @@ def test_parity_small_meshes(torch, shape, grading):
                  patch_types=(FIXED_VALUE, ZERO_GRADIENT, FIXED_VALUE, FIXED_VALUE, ZERO_GRADIENT, FIXED_VALUE))
     fields, out = _run(torch, m, 5)
     _compare(f"ldu-{shape}", m, fields, out)
+
+
+def _hub_mesh():
+    """A graded box plus extra faces that join ten hub cells to up to 60
+    others each (owner < neighbour, upper-triangular order kept): rows of up
+    to 68 entries, two of which reach past the edge of the 1024-entry block
+    holding their diagonal (one 21 entries past its end, one 46 before its
+    start), beyond the direct assembly's 16-entry LDS halo."""
+    import dataclasses
+
+    from chemgen.mesh import box_mesh
+    m = box_mesh(16, 12, 6, grading=(1.5, 1.0, 0.8))
+    rng = np.random.default_rng(11)
+    pairs = set(zip(m.owner.tolist(), m.neighbour.tolist()))
+    own, nei = m.owner.tolist(), m.neighbour.tolist()
+    w, d, s = m.weight.tolist(), m.delta.tolist(), m.mag_sf.tolist()
+    for hub in (184, 418, 427, 446, 592, 932, 934, 1007, 1076, 1097):
+        for o in rng.choice(m.ncells, size=60, replace=False).tolist():
+            a, b = min(hub, o), max(hub, o)
+            if a == b or (a, b) in pairs:
+                continue
+            pairs.add((a, b))
+            own.append(a)
+            nei.append(b)
+            w.append(rng.uniform(0.2, 0.8))
+            d.append(rng.uniform(1.0, 20.0))
+            s.append(rng.uniform(0.01, 0.1))
+    order = np.lexsort((np.array(nei), np.array(own)))
+    arr = lambda x, t: np.asarray(x, dtype=t)[order]
+    return dataclasses.replace(m, owner=arr(own, np.int32), neighbour=arr(nei, np.int32), weight=arr(w, np.float64),
+                               delta=arr(d, np.float64), mag_sf=arr(s, np.float64))
+
+
+def test_parity_long_rows(torch):
+    """Rows longer than a block's halo, crossing block edges both ways: the
+    direct assembly's diagonal takes the far entries from the coefficient
+    array.  Diagonal bar from the longest row's term count."""
+    m = _hub_mesh()
+    fields, out = _run(torch, m, 8)
+    rp, col = out["row_ptr"].astype(np.int64), out["col"].astype(np.int64)
+    before = after = 0
+    for i in range(m.ncells):
+        b, e = rp[i], rp[i + 1]
+        dp = b + int(np.searchsorted(col[b:e], i))
+        j0 = dp // 1024 * 1024
+        before, after = max(before, j0 - b), max(after, e - (j0 + 1024))
+    assert before > 16 and after > 16   # the cases the test is for
+    nterms = int(np.diff(rp).max()) + 3
+    _compare("ldu-hub", m, fields, out, dbar=2 * (nterms - 1) * 2.0 ** -53)
 
 
 def test_csr_product_matches_operator(torch):
