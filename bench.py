@@ -708,7 +708,7 @@ def run_laplacian(args):
 
 
 def run_species(args):
-    """Per-species networks vs one network (survey row f2), each trained on
+    """Per-species networks (Section 2) vs one network, each trained on
     the same states for the same epochs, served on flame64 through the same
     checks and fallback.  One step = chem_surrogate_infer over the field from
     the pristine state (restored by a device copy inside the step)."""
