@@ -1032,7 +1032,7 @@ def main():
         print(json.dumps({"copy_bytes_per_dispatch": src.numel() * 8, "dispatches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the per-cell "
+        print(f"bench.py: this benchmark runs on one GPU only (asked for {args.gpus}); the per-cell "
               "chemistry shards trivially across GPUs but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
     if args.workload == "surrogate":
