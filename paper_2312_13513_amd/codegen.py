@@ -172,6 +172,10 @@ def _eff_row(kin, K: int) -> List[float]:
     return eff
 
 
+def _start_waves(K: int, kins) -> int:
+    return 2 if K <= 9 and all(k["kind"] == "elem" for k in kins) else 1
+
+
 def generate(path: str, tag: str) -> Tuple[str, int, int]:
     """Return (source, K, hash) of the specialised functor and kernels for a file."""
     data = open(path, "rb").read()
@@ -180,7 +184,10 @@ def generate(path: str, tag: str) -> Tuple[str, int, int]:
     N = K + 1
     out = [f"// Generated from {os.path.basename(path)} (FNV-1a {hsh:016x}); do not edit.",
            '#include "bdf_driver.h"', "", "namespace chem {", "namespace {", "",
-           f"struct GenMech_{tag} {{", f"    static constexpr int K = {K};", ""]
+           f"struct GenMech_{tag} {{", f"    static constexpr int K = {K};",
+           # waves per SIMD of the start pass: two where its registers fit
+           # 256 (up to 9 species, elementary reactions), else one
+           f"    static constexpr int kStartWaves = {_start_waves(K, kins)};", ""]
     ln_c0_const = math.log(PSTD / RU)
 
     # ---------------- right-hand side

@@ -745,8 +745,11 @@ __device__ __forceinline__ int cost_bucket(double h, double t_end, int st)
 
 // Start pass: one thread per work item; bucket counts per block in LDS, then
 // one atomic per non-empty bucket.
+// Mech::kStartWaves waves per SIMD: the pass runs a few rounds of waves
+// through long exp chains, so a second resident wave hides their latency
+// where the mechanism's code fits 256 registers without spills.
 template <class Mech>
-__global__ void __launch_bounds__(256) bdf_start_kernel(Mech mech, double *__restrict__ T,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Mech::kStartWaves))) bdf_start_kernel(Mech mech, double *__restrict__ T,
                                                         const double *__restrict__ p,
                                                         double *__restrict__ Y, int64_t ldY, int64_t n,
                                                         double dt, BdfParams prm, StartPass sp)
